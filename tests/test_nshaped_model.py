@@ -1,0 +1,77 @@
+"""The reading of Table 1 / Appendix I (CPU model) against the oracle, no GPU.
+
+Pins the readings of the printed stages: r_i in RD, joint-line neighbours in RS, the
+(RD+JD)+(RU+JU) order, blocks without interior rows, two-slot joins and nesting (Eq. (6)).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import nshaped_model as nm
+
+
+def rel(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 7, 10])
+def test_every_joint_line_subset(oracle_mod, n):
+    a, b, c, d = workloads.random_system(n, 100 + n, "dd")
+    ref = oracle_mod.thomas(a, b, c, d)
+    inner = list(range(1, n - 1))
+    for k in range(len(inner) + 1):
+        for sub in itertools.combinations(inner, k):
+            J = [0, *sub, n - 1]
+            assert rel(nm.solve(a, b, c, d, J), ref) <= 1e-13, J
+
+
+def test_stage_orders_agree_bitwise():
+    a, b, c, d = workloads.random_system(200, 3, "herm")
+    J = nm.uniform_joints(200, 13)
+    x1 = nm.solve(a, b, c, d, J, order="RD+JD,RU+JU")
+    x2 = nm.solve(a, b, c, d, J, order="RD+RU,JU+JD")
+    np.testing.assert_array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 8, 64, 5000])
+def test_uniform_partitions(oracle_mod, p):
+    a, b, c, d = workloads.random_system(4097, 7, "herm")
+    x = nm.solve(a, b, c, d, nm.uniform_joints(4097, p))
+    assert rel(x, oracle_mod.thomas(a, b, c, d)) <= 1e-13
+
+
+def test_random_uneven_joints(oracle_mod):
+    g = np.random.default_rng(4)
+    n = 20000
+    a, b, c, d = workloads.random_system(n, 8, "dd")
+    inner = np.sort(g.choice(np.arange(1, n - 1), 700, replace=False))
+    J = [0, *inner.tolist(), n - 1]
+    assert rel(nm.solve(a, b, c, d, J), oracle_mod.thomas(a, b, c, d)) <= 1e-13
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 4])
+def test_nested_levels(oracle_mod, depth):
+    n = 6000
+    a, b, c, d = workloads.random_system(n, 9, "herm")
+    J = nm.uniform_joints(n, 7)
+    nested = []
+    m = len(J)
+    for _ in range(depth - 1):
+        Jn = nm.uniform_joints(m, 5)
+        nested.append(Jn)
+        m = len(Jn)
+    x = nm.solve(a, b, c, d, J, nested)
+    assert rel(x, oracle_mod.thomas(a, b, c, d)) <= 1e-13
+
+
+def test_cn_pivots_have_real_part_at_least_one(oracle_mod):
+    """T = I + iK with K real symmetric: every Schur-complement pivot has Re >= 1."""
+    w = workloads.plain_1d(n=3000)
+    a, b, c = oracle_mod.cn_coeffs(w["V"], w["dx"], w["dt"])
+    d = oracle_mod.cn_rhs(w["psi0"], w["V"], w["dx"], w["dt"])
+    J = nm.uniform_joints(3000, 37)
+    x, piv = nm.solve(a, b, c, d, J, [nm.uniform_joints(len(J), 4)], return_pivots=True)
+    assert min(np.real(piv)) >= 1.0 - 1e-12
+    assert rel(x, oracle_mod.thomas(a, b, c, d)) <= 1e-13
