@@ -1,0 +1,160 @@
+/*
+ * cntri.h -- C ABI of the MI355X (gfx950) N-shaped partition Crank-Nicolson solver.
+ *
+ * Method: Lutsyshyn, Navarrete, Bauer, "The N-shaped partition method: A novel parallel
+ * implementation of the Crank Nicolson algorithm", arXiv 2205.00856.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are DEVICE pointers owned by the caller (for example the storage of
+ *   torch tensors on the GPU); the library never frees or keeps them past the call.
+ *   Exception: cn_layout.offsets is a HOST pointer (see below).
+ * - Complex values are interleaved FP64 pairs (re, im), 16 bytes, 16-byte aligned (the
+ *   layout of torch.complex128 / C99 double complex).  Real values are FP64.
+ * - Tridiagonal naming follows Sec. 4, Eq. (5) of the paper: row i reads
+ *       b_i x_{i-1} + a_i x_i + c_i x_{i+1} = d_i,
+ *   a = main diagonal, b = sub-diagonal (b[0] is ignored), c = super-diagonal (c[n-1] is
+ *   ignored).  Rows are 0-based.
+ * - The matrix must be factorizable without pivoting: every matrix whose Hermitian part is
+ *   positive definite (all Crank-Nicolson matrices with a real potential) and every strictly
+ *   diagonally dominant matrix qualifies.  There is no pivoting, as in the paper.
+ * - Work is enqueued asynchronously on the caller's stream (a hipStream_t passed as void*;
+ *   NULL is the default stream).  Argument errors are reported synchronously with a negative
+ *   status and nothing is enqueued.  A zero or non-finite pivot makes the solution
+ *   non-finite; the kernels then raise a sticky device flag that cn_get_status reports as
+ *   CN_NUMERICAL_BREAKDOWN.  The library never aborts the process.
+ * - Workspace: the handle owns a device workspace that grows on demand.  Inside HIP graph
+ *   capture nothing may be allocated: call cn_reserve with the same layout first, else the
+ *   call returns CN_ERR_NOT_RESERVED.
+ * - Threading: a handle is used by one host thread at a time.  Calls that overlap on
+ *   different streams of one handle share its workspace and must not run concurrently.
+ * - All arithmetic is FP64.  Results are deterministic: no floating-point atomics.
+ */
+#ifndef CNTRI_H
+#define CNTRI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cn_handle_s* cn_handle_t;
+typedef void* cn_stream_t; /* hipStream_t */
+
+typedef enum {
+  CN_OK = 0,
+  CN_NUMERICAL_BREAKDOWN = 1, /* a zero or non-finite pivot was met (sticky, per handle)  */
+  CN_ERR_INVALID_ARG = -1,    /* null pointer, bad size, stride or offsets                 */
+  CN_ERR_UNSUPPORTED = -2,    /* valid request the library does not implement               */
+  CN_ERR_NO_MEMORY = -3,      /* device allocation failed                                   */
+  CN_ERR_HIP = -4,            /* a HIP runtime call failed                                  */
+  CN_ERR_NOT_RESERVED = -5    /* workspace would have to grow during graph capture          */
+} cn_status;
+
+/* Shape of the batch of independent systems handled by one call.
+ * Uniform batch (offsets == NULL): system s, row i lives at element
+ *     s * batch_stride + i * elem_stride
+ * of every array (a, b, c, d, x, psi, V, xgrid).  elem_stride = 1, batch_stride = n is the
+ * contiguous layout (ADI x-lines); elem_stride = batch, batch_stride = 1 is the interleaved
+ * layout (ADI y-lines).  The rows of different systems must not overlap.
+ * Uneven batch (offsets != NULL): system s owns rows offsets[s] .. offsets[s+1]-1 of every
+ * array, packed contiguously; n, elem_stride and batch_stride are ignored.  offsets is a HOST
+ * array of batch+1 non-decreasing values starting at 0 (empty systems are allowed). */
+typedef struct {
+  int64_t n;
+  int64_t batch;
+  int64_t elem_stride;
+  int64_t batch_stride;
+  const int64_t* offsets;
+  int32_t partition;       /* rows per first-level partition (one workgroup tile); a power
+                              of two in [64, 16384]; 0 = automatic                         */
+  int32_t rows_per_thread; /* rows per innermost block (4 or 8); 0 = automatic             */
+} cn_layout;
+
+/* Crank-Nicolson operator of Sec. 2, Eqs. (2)-(4) on a uniform grid with Dirichlet walls:
+ *   H = -1/2 d^2/dx^2 + v,  v_j = v_scale * V_j + (xgrid ? xgrid_j * E : 0),
+ *   three-point Laplacian, tau = dt/2, kappa = tau / (2 dx^2):
+ *   T = 1 + i tau H: diagonal 1 + i tau (1/dx^2 + v_j), off-diagonals -i kappa.
+ * V and xgrid are DEVICE arrays with the layout of psi.  dx_per_system (DEVICE, batch values)
+ * overrides dx when non-NULL. */
+typedef struct {
+  const double* V;
+  double v_scale;
+  double dx;
+  const double* dx_per_system;
+  double dt;
+  const double* xgrid;
+} cn_operator;
+
+cn_status cn_create(cn_handle_t* handle, int device);
+cn_status cn_destroy(cn_handle_t handle);
+const char* cn_status_string(cn_status status);
+
+/* Builds the plan for this layout and grows the workspace so that later calls with the same
+ * layout allocate nothing (required before HIP graph capture). */
+cn_status cn_reserve(cn_handle_t handle, const cn_layout* layout);
+
+/* x = T^{-1} d for every system of the batch: the N-shaped partition method (Sec. 4,
+ * Table 1) -- partition-local RD+JD and RU+JU sweeps, the reduced system on the joint
+ * lines solved by nesting the same method (Sec. 4.1.6, Eq. (6)) and, at the top, the RS
+ * stage; then SS back-substitution on every level.  x may alias d; a, b, c are read only. */
+cn_status cn_tridiag_solve(cn_handle_t handle, const cn_layout* layout, const void* a,
+                           const void* b, const void* c, const void* d, void* x,
+                           cn_stream_t stream);
+
+/* Reverse mode of cn_tridiag_solve.  Given x = T^{-1} d and gx, the gradient of a real loss
+ * with respect to x in the (d/dRe + i d/dIm) convention, writes
+ *   gd = lambda = T^{-H} gx   (solved with the same partitioned method on T^H),
+ *   ga_i = -lambda_i conj(x_i),  gb_i = -lambda_i conj(x_{i-1}),  gc_i = -lambda_i conj(x_{i+1}).
+ * ga, gb, gc may each be NULL.  gb[0] and gc[n-1] are written as 0. */
+cn_status cn_tridiag_solve_adjoint(cn_handle_t handle, const cn_layout* layout, const void* a,
+                                   const void* b, const void* c, const void* x, const void* gx,
+                                   void* gd, void* ga, void* gb, void* gc, cn_stream_t stream);
+
+/* Materialised coefficient assembly of T (a, b, c; b[0] = c[n-1] = 0) for the layout. */
+cn_status cn_assemble(cn_handle_t handle, const cn_layout* layout, const cn_operator* op,
+                      double E, void* a, void* b, void* c, cn_stream_t stream);
+
+/* Materialised explicit half-step d = (1 - i tau H) psi (Sec. 2, Eq. (3)). */
+cn_status cn_rhs(cn_handle_t handle, const cn_layout* layout, const cn_operator* op, double E,
+                 const void* psi, void* d, cn_stream_t stream);
+
+/* One Crank-Nicolson step psi_out = T^{-1} (1 - i tau H) psi_in for every system, with the
+ * explicit half-step fused into the reduction sweep (Sec. 5.3).  E is the field of this
+ * step, used on both sides.  psi_out may alias psi_in. */
+cn_status cn_step(cn_handle_t handle, const cn_layout* layout, const cn_operator* op, double E,
+                  const void* psi_in, void* psi_out, cn_stream_t stream);
+
+/* nsteps chained cn_step calls in place on psi.  E: DEVICE-free HOST array of nsteps field
+ * values, or NULL for no field.  If ckpt is non-NULL, the state before step k is copied to
+ * ckpt + (k / K) * (rows of the layout) for every k divisible by K (K >= 1). */
+cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_operator* op,
+                       int64_t nsteps, const double* E, void* psi, void* ckpt, int64_t K,
+                       cn_stream_t stream);
+
+/* One step of the adjoint recursion of cn_propagate (uniform batch of one system).
+ * With psi_np1 = T_n^{-1} (1 - i tau H_n) psi_n and g_np1 the gradient at psi_np1:
+ *   lambda = T_n^{-H} g_np1   (T_n^H = 1 - i tau H_n for real v),
+ *   g_n = T_n lambda,
+ *   dV_accum_j += v_scale * tau * Im(conj(lambda_j) (psi_n,j + psi_np1,j)),
+ *   dE_partial[0] = sum_j xgrid_j * tau * Im(conj(lambda_j) (psi_n,j + psi_np1,j))
+ * (dE_partial may be NULL; it needs xgrid).  The sum is deterministic. */
+cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_operator* op,
+                          double E, const void* psi_n, const void* psi_np1, const void* g_np1,
+                          void* g_n, double* dV_accum, double* dE_partial, cn_stream_t stream);
+
+/* Synchronises the stream, returns CN_NUMERICAL_BREAKDOWN if any kernel of this handle met a
+ * non-finite result since the last call (and clears the flag), else CN_OK. */
+cn_status cn_get_status(cn_handle_t handle, cn_stream_t stream);
+
+/* Version string and the plan chosen for a layout (for logs and benchmarks). */
+const char* cn_version(void);
+cn_status cn_describe_plan(cn_handle_t handle, const cn_layout* layout, int cn_mode, char* buf,
+                           int64_t buflen);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CNTRI_H */

@@ -1,0 +1,310 @@
+"""Python front end of the C ABI (include/cntri.h) over torch device tensors.
+
+Argument marshalling only: pointers, sizes and the current HIP stream go to libcntri.so,
+whose kernels do every step of the solve.  PyTorch provides device memory and streams.
+
+Names follow the paper (arXiv 2205.00856, Sec. 4, Eq. (5)): a = diagonal, b = sub-diagonal,
+c = super-diagonal, d = right-hand side; psi is the wave function of the CN step (Sec. 2).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CnLayout, CnOperator, check
+
+__all__ = ["Layout", "Handle", "handle", "solve", "solve_adjoint", "assemble", "rhs", "step",
+           "propagate", "step_adjoint", "get_status", "describe_plan", "reserve"]
+
+
+@dataclass
+class Layout:
+    """Shape of the batch (see cn_layout in include/cntri.h).
+
+    Uniform batch: system s, row i at element s*batch_stride + i*elem_stride.
+    Uneven batch: offsets (host, batch+1 values) of systems packed back to back.
+    """
+
+    n: int = 0
+    batch: int = 1
+    elem_stride: int = 1
+    batch_stride: int = 0
+    offsets: Optional[Sequence[int]] = None
+    partition: int = 0
+    rows_per_thread: int = 0
+    _offs_np: Optional[np.ndarray] = field(default=None, repr=False)
+
+    @staticmethod
+    def contiguous(n: int, batch: int = 1, **kw) -> "Layout":
+        return Layout(n=n, batch=batch, elem_stride=1, batch_stride=n, **kw)
+
+    @staticmethod
+    def interleaved(n: int, batch: int, **kw) -> "Layout":
+        return Layout(n=n, batch=batch, elem_stride=batch, batch_stride=1, **kw)
+
+    @staticmethod
+    def uneven(offsets, **kw) -> "Layout":
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        return Layout(n=0, batch=int(offs.shape[0] - 1), offsets=offs, _offs_np=offs, **kw)
+
+    def rows(self) -> int:
+        if self.offsets is not None:
+            return int(self._np_offsets()[-1])
+        return self.n * self.batch
+
+    def span(self) -> int:
+        if self.offsets is not None:
+            return int(self._np_offsets()[-1])
+        return (self.batch - 1) * self.batch_stride + (self.n - 1) * self.elem_stride + 1
+
+    def _np_offsets(self) -> np.ndarray:
+        if self._offs_np is None:
+            self._offs_np = np.ascontiguousarray(np.asarray(self.offsets, dtype=np.int64))
+        return self._offs_np
+
+    def c(self) -> CnLayout:
+        L = CnLayout()
+        L.n = int(self.n)
+        L.batch = int(self.batch)
+        L.elem_stride = int(self.elem_stride)
+        L.batch_stride = int(self.batch_stride if self.batch_stride else self.n)
+        if self.offsets is not None:
+            o = self._np_offsets()
+            L.offsets = o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        else:
+            L.offsets = None
+        L.partition = int(self.partition)
+        L.rows_per_thread = int(self.rows_per_thread)
+        return L
+
+
+class Handle:
+    """Owns a cn_handle_t (workspace, plans, status flag) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self._h = ctypes.c_void_p()
+        check(_lib.lib().cn_create(ctypes.byref(self._h), device), "cn_create")
+
+    def close(self):
+        if self._h:
+            _lib.lib().cn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    @property
+    def ptr(self):
+        return self._h
+
+
+_handles: dict = {}
+
+
+def handle(device: Optional[int] = None) -> Handle:
+    if device is None:
+        device = torch.cuda.current_device()
+    h = _handles.get(device)
+    if h is None:
+        h = _handles[device] = Handle(device)
+    return h
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, name: str, min_elems: int):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (strides are given by the layout)")
+    if t.numel() < min_elems:
+        raise ValueError(f"{name} has {t.numel()} elements, the layout needs {min_elems}")
+
+
+def _layout_for(t: torch.Tensor, layout: Optional[Layout]) -> Layout:
+    if layout is not None:
+        return layout
+    if t.dim() == 1:
+        return Layout.contiguous(t.shape[0], 1)
+    if t.dim() == 2:
+        return Layout.contiguous(t.shape[1], t.shape[0])
+    raise ValueError("give a Layout for tensors of more than two dimensions")
+
+
+def _operator(V, dx, dt, xgrid=None, v_scale=1.0, dx_per_system=None) -> CnOperator:
+    op = CnOperator()
+    op.V = V.data_ptr()
+    op.v_scale = float(v_scale)
+    op.dx = float(dx)
+    op.dx_per_system = None if dx_per_system is None else dx_per_system.data_ptr()
+    op.dt = float(dt)
+    op.xgrid = None if xgrid is None else xgrid.data_ptr()
+    return op
+
+
+def _check_op(L: Layout, V, xgrid, dx_per_system):
+    span = L.span()
+    _need(V, torch.float64, "V", span)
+    if xgrid is not None:
+        _need(xgrid, torch.float64, "xgrid", span)
+    if dx_per_system is not None:
+        _need(dx_per_system, torch.float64, "dx_per_system", L.batch)
+
+
+def reserve(layout: Layout, device=None):
+    h = handle(device)
+    Lc = layout.c()
+    check(_lib.lib().cn_reserve(h.ptr, ctypes.byref(Lc)), "cn_reserve")
+
+
+def describe_plan(layout: Layout, cn_mode: bool = False, device=None) -> str:
+    h = handle(device)
+    Lc = layout.c()
+    buf = ctypes.create_string_buffer(4096)
+    check(_lib.lib().cn_describe_plan(h.ptr, ctypes.byref(Lc), int(cn_mode), buf, 4096),
+          "cn_describe_plan")
+    return buf.value.decode()
+
+
+def solve(a, b, c, d, out=None, layout: Optional[Layout] = None):
+    """x = T^{-1} d (cn_tridiag_solve).  out may be d (in place)."""
+    L = _layout_for(d, layout)
+    span = L.span()
+    for t, nm in ((a, "a"), (b, "b"), (c, "c"), (d, "d")):
+        _need(t, torch.complex128, nm, span)
+    if out is None:
+        out = torch.empty_like(d)
+    _need(out, torch.complex128, "out", span)
+    h = handle(d.device.index)
+    Lc = L.c()
+    check(_lib.lib().cn_tridiag_solve(h.ptr, ctypes.byref(Lc), _ptr(a), _ptr(b), _ptr(c), _ptr(d),
+                                      _ptr(out), _stream(d)), "cn_tridiag_solve")
+    return out
+
+
+def solve_adjoint(a, b, c, x, gx, need_abc=True, layout: Optional[Layout] = None):
+    """Reverse mode of solve: returns (gd, ga, gb, gc) (ga/gb/gc None unless need_abc)."""
+    L = _layout_for(x, layout)
+    span = L.span()
+    for t, nm in ((a, "a"), (b, "b"), (c, "c"), (x, "x"), (gx, "gx")):
+        _need(t, torch.complex128, nm, span)
+    gd = torch.empty_like(x)
+    ga = gb = gc = None
+    if need_abc:
+        ga, gb, gc = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+    h = handle(x.device.index)
+    Lc = L.c()
+    check(_lib.lib().cn_tridiag_solve_adjoint(h.ptr, ctypes.byref(Lc), _ptr(a), _ptr(b), _ptr(c),
+                                              _ptr(x), _ptr(gx), _ptr(gd), _ptr(ga), _ptr(gb),
+                                              _ptr(gc), _stream(x)), "cn_tridiag_solve_adjoint")
+    return gd, ga, gb, gc
+
+
+def assemble(V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
+             layout: Optional[Layout] = None):
+    """Materialised coefficients (a, b, c) of T = 1 + i dt/2 H (cn_assemble)."""
+    L = _layout_for(V, layout)
+    _check_op(L, V, xgrid, dx_per_system)
+    shape = V.shape
+    a = torch.empty(shape, dtype=torch.complex128, device=V.device)
+    b = torch.empty_like(a)
+    c = torch.empty_like(a)
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    h = handle(V.device.index)
+    Lc = L.c()
+    check(_lib.lib().cn_assemble(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E), _ptr(a),
+                                 _ptr(b), _ptr(c), _stream(V)), "cn_assemble")
+    return a, b, c
+
+
+def rhs(psi, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
+        layout: Optional[Layout] = None):
+    """Materialised explicit half-step d = (1 - i dt/2 H) psi (cn_rhs)."""
+    L = _layout_for(psi, layout)
+    _need(psi, torch.complex128, "psi", L.span())
+    _check_op(L, V, xgrid, dx_per_system)
+    d = torch.empty_like(psi)
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    h = handle(psi.device.index)
+    Lc = L.c()
+    check(_lib.lib().cn_rhs(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E), _ptr(psi),
+                            _ptr(d), _stream(psi)), "cn_rhs")
+    return d
+
+
+def step(psi, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None, out=None,
+         layout: Optional[Layout] = None):
+    """One Crank-Nicolson step (cn_step).  out may be psi (in place)."""
+    L = _layout_for(psi, layout)
+    _need(psi, torch.complex128, "psi", L.span())
+    _check_op(L, V, xgrid, dx_per_system)
+    if out is None:
+        out = torch.empty_like(psi)
+    _need(out, torch.complex128, "out", L.span())
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    h = handle(psi.device.index)
+    Lc = L.c()
+    check(_lib.lib().cn_step(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E), _ptr(psi),
+                             _ptr(out), _stream(psi)), "cn_step")
+    return out
+
+
+def propagate(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0, dx_per_system=None,
+              ckpt=None, K=1, layout: Optional[Layout] = None):
+    """nsteps CN steps in place on psi (cn_propagate); E: host sequence of nsteps values."""
+    L = _layout_for(psi, layout)
+    _need(psi, torch.complex128, "psi", L.span())
+    _check_op(L, V, xgrid, dx_per_system)
+    Earr = None
+    if E is not None:
+        Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
+        if Earr.shape[0] < nsteps:
+            raise ValueError("E needs one value per step")
+    if ckpt is not None:
+        _need(ckpt, torch.complex128, "ckpt", ((nsteps + K - 1) // K) * L.span())
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    h = handle(psi.device.index)
+    Lc = L.c()
+    Ep = None if Earr is None else Earr.ctypes.data_as(ctypes.c_void_p)
+    check(_lib.lib().cn_propagate(h.ptr, ctypes.byref(Lc), ctypes.byref(op), int(nsteps), Ep,
+                                  _ptr(psi), _ptr(ckpt), int(K), _stream(psi)), "cn_propagate")
+    return psi
+
+
+def step_adjoint(psi_n, psi_np1, g_np1, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dV=None,
+                 dE_out=None, g_out=None, layout: Optional[Layout] = None):
+    """One step of the adjoint recursion (cn_step_adjoint).  Returns g_n; accumulates into dV
+    (float64, in place) and writes dE_out[0] when given (needs xgrid)."""
+    L = _layout_for(psi_n, layout)
+    span = L.span()
+    for t, nm in ((psi_n, "psi_n"), (psi_np1, "psi_np1"), (g_np1, "g_np1")):
+        _need(t, torch.complex128, nm, span)
+    _check_op(L, V, xgrid, None)
+    if g_out is None:
+        g_out = torch.empty_like(psi_n)
+    op = _operator(V, dx, dt, xgrid, v_scale, None)
+    h = handle(psi_n.device.index)
+    Lc = L.c()
+    check(_lib.lib().cn_step_adjoint(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E),
+                                     _ptr(psi_n), _ptr(psi_np1), _ptr(g_np1), _ptr(g_out),
+                                     _ptr(dV), _ptr(dE_out), _stream(psi_n)), "cn_step_adjoint")
+    return g_out
+
+
+def get_status(device=None) -> int:
+    """Synchronises the current stream; 1 if a non-finite result was met since the last call."""
+    h = handle(device)
+    dev = torch.device("cuda", h.device)
+    return check(_lib.lib().cn_get_status(h.ptr, ctypes.c_void_p(
+        torch.cuda.current_stream(dev).cuda_stream)), "cn_get_status")

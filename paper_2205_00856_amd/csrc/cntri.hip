@@ -1,0 +1,846 @@
+// Host runtime and C ABI of the N-shaped partition Crank-Nicolson solver (gfx950).
+// The ABI is declared and documented in include/cntri.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cntri.h"
+#include "nshaped_kernels.hpp"
+
+using nsd::cd;
+using nsd::KArgs;
+
+namespace {
+
+// ----------------------------------------------------------------------- kernel table
+struct Cfg {
+  int M, W;
+  int64_t T() const { return 64LL * W * M; }
+};
+// (rows per lane, wavefronts per workgroup); tile T = 64 W M rows
+constexpr Cfg kCfgs[] = {{2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16},
+                         {8, 1}, {8, 2}, {8, 4}, {8, 8}, {2, 2}, {2, 4}};
+constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+typedef void (*KFn)(KArgs);
+const void* g_kern[kNumCfg][4][3];
+
+template <int M, int W, int SRC>
+void reg_src(int ci) {
+  g_kern[ci][SRC][nsd::PH_SINGLE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_SINGLE>;
+  g_kern[ci][SRC][nsd::PH_REDUCE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_REDUCE>;
+  g_kern[ci][SRC][nsd::PH_SUBST] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_SUBST>;
+}
+template <int M, int W>
+void reg_cfg(int ci) {
+  reg_src<M, W, nsd::SRC_EXPL>(ci);
+  reg_src<M, W, nsd::SRC_EXPL_CT>(ci);
+  reg_src<M, W, nsd::SRC_CN>(ci);
+  reg_src<M, W, nsd::SRC_SLOTS>(ci);
+}
+struct KernTableInit {
+  KernTableInit() {
+    reg_cfg<2, 1>(0);
+    reg_cfg<4, 1>(1);
+    reg_cfg<4, 2>(2);
+    reg_cfg<4, 4>(3);
+    reg_cfg<4, 8>(4);
+    reg_cfg<4, 16>(5);
+    reg_cfg<8, 1>(6);
+    reg_cfg<8, 2>(7);
+    reg_cfg<8, 4>(8);
+    reg_cfg<8, 8>(9);
+    reg_cfg<2, 2>(10);
+    reg_cfg<2, 4>(11);
+  }
+} g_kern_init;
+
+int find_cfg(int64_t T, int M) {
+  for (int i = 0; i < kNumCfg; ++i)
+    if (kCfgs[i].T() == T && kCfgs[i].M == M) return i;
+  return -1;
+}
+
+constexpr int64_t kSingleMax = 4096;  // largest tile that solves a whole system in one pass
+
+// Workgroup configuration for a system that fits one tile: the smallest tile that holds it.
+int single_cfg(int64_t n) {
+  if (n <= 128) return find_cfg(128, 2);
+  if (n <= 256) return find_cfg(256, 4);
+  if (n <= 512) return find_cfg(512, 4);
+  if (n <= 1024) return find_cfg(1024, 4);
+  if (n <= 2048) return find_cfg(2048, 4);
+  return find_cfg(4096, 4);
+}
+
+// ------------------------------------------------------------------------------- plans
+enum class Src { EXPL = nsd::SRC_EXPL, CT = nsd::SRC_EXPL_CT, CN = nsd::SRC_CN };
+
+struct Launch {
+  const void* fn;
+  dim3 grid;
+  int threads;
+  KArgs a;
+  int level;  // 1 = the caller's system
+  int src, ph, cfg;
+  // table offsets (bytes into plan tables) or -1
+  int64_t t_offs = -1, t_tbase = -1, t_wgs = -1, t_wgt = -1;
+  // workspace offsets (bytes) or -1
+  int64_t o_sU = -1, o_sD = -1, o_oU = -1, o_oD = -1, o_x = -1, o_psi_if = -1, o_hout = -1,
+          o_hin = -1;
+};
+
+struct Plan {
+  std::vector<Launch> L;
+  size_t ws_bytes = 0;
+  void* tables = nullptr;
+  size_t tables_bytes = 0;
+  std::string desc;
+  int64_t span = 0;  // element extent of the caller's arrays
+  int64_t rows = 0;  // total rows
+  int64_t o_aux = -1;   // workspace for an extra state vector (adjoint step)
+  int64_t o_part = -1;  // workspace for per-block partial sums
+  int64_t nparts = 0;
+  ~Plan() {
+    if (tables) (void)hipFree(tables);
+  }
+};
+
+struct Knobs {
+  int64_t partition = 0;
+  int rpt = 0;
+};
+
+struct Builder {
+  std::vector<char> tab;
+  size_t ws = 0;
+  std::string desc;
+  int64_t add_tab(const void* p, size_t bytes) {
+    size_t off = (tab.size() + 255) & ~size_t(255);
+    tab.resize(off + bytes);
+    if (bytes) memcpy(tab.data() + off, p, bytes);
+    return (int64_t)off;
+  }
+  int64_t add_ws(size_t bytes) {
+    size_t off = (ws + 255) & ~size_t(255);
+    ws = off + std::max<size_t>(bytes, 16);
+    return (int64_t)off;
+  }
+};
+
+struct BatchDesc {
+  bool uneven = false;
+  int64_t n = 0, batch = 0, es = 1, bs = 1;
+  std::vector<int64_t> offs;
+};
+
+int multi_cfg(int64_t n, int64_t batch, const Knobs& k, int level) {
+  if (level == 1 && k.partition > 0) {
+    int M = k.rpt > 0 ? k.rpt : (k.partition >= 512 ? 8 : 4);
+    int ci = find_cfg(k.partition, M);
+    if (ci < 0) ci = find_cfg(k.partition, 4);
+    if (ci < 0) ci = find_cfg(k.partition, 8);
+    if (ci < 0) ci = find_cfg(k.partition, 2);
+    return ci;
+  }
+  // enough tiles to fill the chip (>= 4 workgroups per CU when the system allows it)
+  const int64_t target = 1024;
+  int64_t T = 2048;
+  while (T > 256 && batch * ((n + T - 1) / T) < target) T /= 2;
+  int M = (level == 1 && k.rpt > 0) ? k.rpt : 4;
+  int ci = find_cfg(T, M);
+  if (ci < 0) ci = find_cfg(T, 4);
+  return ci;
+}
+
+void add_launch(std::vector<Launch>& L, int ci, int src, int ph, dim3 grid, int level,
+                const KArgs& a) {
+  Launch l;
+  l.fn = g_kern[ci][src][ph];
+  l.grid = grid;
+  l.threads = 64 * kCfgs[ci].W;
+  l.a = a;
+  l.level = level;
+  l.src = src;
+  l.ph = ph;
+  l.cfg = ci;
+  L.push_back(l);
+}
+
+std::string cfg_str(int ci) {
+  char s[64];
+  snprintf(s, sizeof(s), "T=%lld(M=%d,W=%d)", (long long)kCfgs[ci].T(), kCfgs[ci].M, kCfgs[ci].W);
+  return s;
+}
+
+// Appends the launches that solve one level; x goes to the caller (level 1) or to workspace
+// offset o_x.  At level >= 2 the source is the slot arrays at (o_sU, o_sD).
+void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src, int level,
+                int64_t o_sU, int64_t o_sD, int64_t o_x, const Knobs& kn) {
+  KArgs base{};
+  base.vscale = 1.0;
+  auto set_common = [&](Launch& l) {
+    l.o_sU = o_sU;
+    l.o_sD = o_sD;
+    l.o_x = o_x;
+  };
+  char line[256];
+  if (!bd.uneven) {
+    const int64_t n = bd.n, batch = bd.batch;
+    const bool fits = n <= kSingleMax && (batch >= 64 || n <= 1024 || level > 1);
+    if (fits) {
+      int ci = single_cfg(n);
+      KArgs a = base;
+      a.n = n;
+      a.ntiles = 1;
+      a.es = bd.es;
+      a.bs = bd.bs;
+      add_launch(L, ci, src, nsd::PH_SINGLE, dim3(1, (unsigned)batch), level, a);
+      set_common(L.back());
+      snprintf(line, sizeof(line), "L%d single %s n=%lld batch=%lld; ", level, cfg_str(ci).c_str(),
+               (long long)n, (long long)batch);
+      B.desc += line;
+      return;
+    }
+    int ci = multi_cfg(n, batch, kn, level);
+    const int64_t T = kCfgs[ci].T();
+    const int64_t K = (n + T - 1) / T, G = K * batch;
+    const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
+    const int64_t oP = B.add_ws(G * sizeof(cd));
+    const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+    KArgs a = base;
+    a.n = n;
+    a.ntiles = K;
+    a.es = bd.es;
+    a.bs = bd.bs;
+    snprintf(line, sizeof(line), "L%d multi %s n=%lld batch=%lld tiles=%lld; ", level,
+             cfg_str(ci).c_str(), (long long)n, (long long)batch, (long long)K);
+    B.desc += line;
+    add_launch(L, ci, src, nsd::PH_REDUCE, dim3((unsigned)K, (unsigned)batch), level, a);
+    set_common(L.back());
+    L.back().o_oU = oU;
+    L.back().o_oD = oD;
+    L.back().o_hout = oH;
+    BatchDesc ib;
+    ib.uneven = true;
+    ib.batch = batch;
+    ib.offs.resize(batch + 1);
+    for (int64_t s = 0; s <= batch; ++s) ib.offs[s] = s * K;
+    plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+    add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)K, (unsigned)batch), level, a);
+    set_common(L.back());
+    L.back().o_psi_if = oP;
+    L.back().o_hin = oH;
+    return;
+  }
+  // uneven batch: small systems by bucket (one pass), large ones in tiles
+  const int64_t batch = bd.batch;
+  const int64_t t_offs = B.add_tab(bd.offs.data(), (batch + 1) * sizeof(int64_t));
+  std::map<int, std::vector<int>> buckets;
+  std::vector<int> large;
+  for (int64_t s = 0; s < batch; ++s) {
+    const int64_t len = bd.offs[s + 1] - bd.offs[s];
+    if (len <= 0) continue;
+    if (len <= kSingleMax) {
+      buckets[single_cfg(len)].push_back((int)s);
+    } else {
+      large.push_back((int)s);
+    }
+  }
+  for (auto& kv : buckets) {
+    std::vector<int>& sys = kv.second;
+    // longest first inside the bucket
+    std::stable_sort(sys.begin(), sys.end(), [&](int p, int q) {
+      return bd.offs[p + 1] - bd.offs[p] > bd.offs[q + 1] - bd.offs[q];
+    });
+    std::vector<int> tiles(sys.size(), 0);
+    KArgs a = base;
+    add_launch(L, kv.first, src, nsd::PH_SINGLE, dim3((unsigned)sys.size()), level, a);
+    set_common(L.back());
+    L.back().t_offs = t_offs;
+    L.back().t_wgs = B.add_tab(sys.data(), sys.size() * sizeof(int));
+    L.back().t_wgt = B.add_tab(tiles.data(), tiles.size() * sizeof(int));
+    snprintf(line, sizeof(line), "L%d single %s systems=%zu; ", level, cfg_str(kv.first).c_str(),
+             sys.size());
+    B.desc += line;
+  }
+  if (large.empty()) return;
+  int64_t maxlen = 0, nl = 0;
+  for (int s : large) {
+    maxlen = std::max(maxlen, bd.offs[s + 1] - bd.offs[s]);
+    nl += bd.offs[s + 1] - bd.offs[s];
+  }
+  int ci = multi_cfg(nl / (int64_t)large.size(), (int64_t)large.size(), kn, level);
+  const int64_t T = kCfgs[ci].T();
+  std::vector<int64_t> tbase(batch + 1, 0);
+  std::vector<int> wgs, wgt;
+  for (int64_t s = 0; s < batch; ++s) {
+    const int64_t len = bd.offs[s + 1] - bd.offs[s];
+    const int64_t K = (len > kSingleMax) ? (len + T - 1) / T : 0;
+    tbase[s + 1] = tbase[s] + K;
+  }
+  // workgroups of the longest systems first
+  std::vector<int> order(large);
+  std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
+    return bd.offs[p + 1] - bd.offs[p] > bd.offs[q + 1] - bd.offs[q];
+  });
+  for (int s : order)
+    for (int64_t t = 0; t < tbase[s + 1] - tbase[s]; ++t) {
+      wgs.push_back(s);
+      wgt.push_back((int)t);
+    }
+  const int64_t G = tbase[batch];
+  const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
+  const int64_t oP = B.add_ws(G * sizeof(cd));
+  const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+  const int64_t t_tb = B.add_tab(tbase.data(), (batch + 1) * sizeof(int64_t));
+  const int64_t t_s = B.add_tab(wgs.data(), wgs.size() * sizeof(int));
+  const int64_t t_t = B.add_tab(wgt.data(), wgt.size() * sizeof(int));
+  snprintf(line, sizeof(line), "L%d multi %s systems=%zu tiles=%lld; ", level, cfg_str(ci).c_str(),
+           large.size(), (long long)G);
+  B.desc += line;
+  KArgs a = base;
+  add_launch(L, ci, src, nsd::PH_REDUCE, dim3((unsigned)wgs.size()), level, a);
+  set_common(L.back());
+  L.back().t_offs = t_offs;
+  L.back().t_tbase = t_tb;
+  L.back().t_wgs = t_s;
+  L.back().t_wgt = t_t;
+  L.back().o_oU = oU;
+  L.back().o_oD = oD;
+  L.back().o_hout = oH;
+  BatchDesc ib;
+  ib.uneven = true;
+  ib.batch = batch;
+  ib.offs = tbase;
+  plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+  add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)wgs.size()), level, a);
+  set_common(L.back());
+  L.back().t_offs = t_offs;
+  L.back().t_tbase = t_tb;
+  L.back().t_wgs = t_s;
+  L.back().t_wgt = t_t;
+  L.back().o_psi_if = oP;
+  L.back().o_hin = oH;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------- handle
+struct cn_handle_s {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  int* status = nullptr;
+  std::map<std::string, std::unique_ptr<Plan>> plans;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                        \
+  do {                                       \
+    if ((expr) != hipSuccess) return CN_ERR_HIP; \
+  } while (0)
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
+  if (!L) return CN_ERR_INVALID_ARG;
+  if (L->batch < 1) return CN_ERR_INVALID_ARG;
+  if (L->partition != 0) {
+    const int64_t p = L->partition;
+    if (p < 64 || p > 16384 || (p & (p - 1))) return CN_ERR_INVALID_ARG;
+  }
+  if (L->rows_per_thread != 0 && L->rows_per_thread != 2 && L->rows_per_thread != 4 &&
+      L->rows_per_thread != 8)
+    return CN_ERR_INVALID_ARG;
+  if (L->offsets) {
+    if (L->offsets[0] != 0) return CN_ERR_INVALID_ARG;
+    for (int64_t s = 0; s < L->batch; ++s)
+      if (L->offsets[s + 1] < L->offsets[s]) return CN_ERR_INVALID_ARG;
+    rows = span = L->offsets[L->batch];
+    if (rows < 1) return CN_ERR_INVALID_ARG;
+    return CN_OK;
+  }
+  if (L->n < 1 || L->elem_stride < 1 || L->batch_stride < 1) return CN_ERR_INVALID_ARG;
+  const int64_t n = L->n, B = L->batch, es = L->elem_stride, bs = L->batch_stride;
+  // systems must not share elements: either each system lies inside one batch_stride period,
+  // or the systems interleave inside one elem_stride period
+  const bool ok = (B == 1) || (bs >= (n - 1) * es + 1) || (es >= (B - 1) * bs + 1);
+  if (!ok) return CN_ERR_INVALID_ARG;
+  if (n > (int64_t)1 << 40 || B > (int64_t)1 << 31) return CN_ERR_UNSUPPORTED;
+  rows = n * B;
+  span = (B - 1) * bs + (n - 1) * es + 1;
+  return CN_OK;
+}
+
+std::string plan_key(const cn_layout* L, int src) {
+  std::string k;
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%d|%lld|%lld|%lld|%lld|%d|%d|", src, (long long)L->n,
+           (long long)L->batch, (long long)L->elem_stride, (long long)L->batch_stride,
+           L->partition, L->rows_per_thread);
+  k = buf;
+  if (L->offsets) {
+    k += "U";
+    k.append(reinterpret_cast<const char*>(L->offsets), (L->batch + 1) * sizeof(int64_t));
+  }
+  return k;
+}
+
+cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Plan** out) {
+  int64_t rows = 0, span = 0;
+  cn_status st = validate(L, rows, span);
+  if (st != CN_OK) return st;
+  const std::string key = plan_key(L, src);
+  auto it = h->plans.find(key);
+  const bool cap = s != nullptr ? capturing(s) : false;
+  if (it == h->plans.end()) {
+    if (cap) return CN_ERR_NOT_RESERVED;
+    std::unique_ptr<Plan> P(new Plan());
+    Builder B;
+    BatchDesc bd;
+    if (L->offsets) {
+      bd.uneven = true;
+      bd.batch = L->batch;
+      bd.offs.assign(L->offsets, L->offsets + L->batch + 1);
+    } else {
+      bd.n = L->n;
+      bd.batch = L->batch;
+      bd.es = L->elem_stride;
+      bd.bs = L->batch_stride;
+    }
+    Knobs kn;
+    kn.partition = L->partition;
+    kn.rpt = L->rows_per_thread;
+    if (kn.partition > 0) {
+      const int M = kn.rpt > 0 ? kn.rpt : (kn.partition >= 512 ? 8 : 4);
+      if (find_cfg(kn.partition, M) < 0 && find_cfg(kn.partition, 4) < 0 &&
+          find_cfg(kn.partition, 8) < 0 && find_cfg(kn.partition, 2) < 0)
+        return CN_ERR_UNSUPPORTED;
+    }
+    plan_level(B, P->L, bd, src, 1, -1, -1, -1, kn);
+    P->span = span;
+    P->rows = rows;
+    if (src == nsd::SRC_CN) {
+      P->o_aux = B.add_ws(rows * sizeof(cd) + 16);
+      P->nparts = (rows + 255) / 256;
+      P->o_part = B.add_ws(P->nparts * sizeof(double) + 16);
+    }
+    P->ws_bytes = B.ws;
+    P->desc = B.desc;
+    if (!B.tab.empty()) {
+      if (hipMalloc(&P->tables, B.tab.size()) != hipSuccess) return CN_ERR_NO_MEMORY;
+      if (hipMemcpy(P->tables, B.tab.data(), B.tab.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return CN_ERR_HIP;
+      P->tables_bytes = B.tab.size();
+    }
+    char* tb = (char*)P->tables;
+    for (Launch& l : P->L) {
+      if (l.t_offs >= 0) l.a.offs = (const int64_t*)(tb + l.t_offs);
+      if (l.t_tbase >= 0) l.a.tbase = (const int64_t*)(tb + l.t_tbase);
+      if (l.t_wgs >= 0) l.a.wg_sys = (const int*)(tb + l.t_wgs);
+      if (l.t_wgt >= 0) l.a.wg_tile = (const int*)(tb + l.t_wgt);
+    }
+    it = h->plans.emplace(key, std::move(P)).first;
+  }
+  Plan* P = it->second.get();
+  if (P->ws_bytes > h->ws_size) {
+    if (cap) return CN_ERR_NOT_RESERVED;
+    if (h->ws) {
+      if (hipDeviceSynchronize() != hipSuccess) return CN_ERR_HIP;
+      (void)hipFree(h->ws);
+      h->ws = nullptr;
+      h->ws_size = 0;
+    }
+    if (hipMalloc(&h->ws, P->ws_bytes) != hipSuccess) return CN_ERR_NO_MEMORY;
+    h->ws_size = P->ws_bytes;
+  }
+  *out = P;
+  return CN_OK;
+}
+
+struct UserArgs {
+  const cd *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
+  const cd* psi = nullptr;
+  const cd* rhs = nullptr;
+  const double* V = nullptr;
+  const double* xg = nullptr;
+  const double* dxs = nullptr;
+  double vscale = 1.0, E_mat = 0.0, E_rhs = 0.0, dx = 1.0, dt = 0.0;
+  cd* x = nullptr;
+};
+
+cn_status run_plan(cn_handle_t h, Plan* P, const UserArgs& u, hipStream_t s) {
+  char* ws = (char*)h->ws;
+  for (const Launch& l : P->L) {
+    KArgs a = l.a;
+    if (l.level == 1) {
+      a.a = u.a;
+      a.b = u.b;
+      a.c = u.c;
+      a.d = u.d;
+      a.psi = u.psi;
+      a.rhs = u.rhs;
+      a.V = u.V;
+      a.xg = u.xg;
+      a.dxs = u.dxs;
+      a.vscale = u.vscale;
+      a.E_mat = u.E_mat;
+      a.E_rhs = u.E_rhs;
+      a.dx = u.dx;
+      a.dt = u.dt;
+    }
+    a.x = (l.o_x >= 0) ? (cd*)(ws + l.o_x) : u.x;
+    if (l.o_sU >= 0) a.sU = (const cd*)(ws + l.o_sU);
+    if (l.o_sD >= 0) a.sD = (const cd*)(ws + l.o_sD);
+    if (l.o_oU >= 0) a.oU = (cd*)(ws + l.o_oU);
+    if (l.o_oD >= 0) a.oD = (cd*)(ws + l.o_oD);
+    if (l.o_psi_if >= 0) a.psi_if = (const cd*)(ws + l.o_psi_if);
+    if (l.o_hout >= 0) a.halo_out = (cd*)(ws + l.o_hout);
+    if (l.o_hin >= 0) a.halo_in = (const cd*)(ws + l.o_hin);
+    a.status = h->status;
+    void* params[] = {&a};
+    if (hipLaunchKernel(l.fn, l.grid, dim3(l.threads), params, 0, s) != hipSuccess)
+      return CN_ERR_HIP;
+  }
+  return CN_OK;
+}
+
+nsd::AuxArgs aux_from(const cn_layout* L, const Plan* P) {
+  nsd::AuxArgs x{};
+  x.n = L->n;
+  x.batch = L->batch;
+  x.es = L->elem_stride;
+  x.bs = L->batch_stride;
+  x.total = P->rows;
+  x.vscale = 1.0;
+  return x;
+}
+
+int64_t* dev_offsets(const Plan* P) {
+  // the first uneven launch at level 1 carries the caller's offsets table
+  for (const Launch& l : P->L)
+    if (l.level == 1 && l.a.offs) return const_cast<int64_t*>(l.a.offs);
+  return nullptr;
+}
+
+cn_status launch_aux(const void* fn, int64_t rows, nsd::AuxArgs& x, hipStream_t s) {
+  const unsigned blocks = (unsigned)((rows + 255) / 256);
+  void* params[] = {&x};
+  if (hipLaunchKernel(fn, dim3(blocks), dim3(256), params, 0, s) != hipSuccess) return CN_ERR_HIP;
+  return CN_OK;
+}
+
+cn_status check_op(const cn_operator* op) {
+  if (!op || !op->V) return CN_ERR_INVALID_ARG;
+  if (!op->dx_per_system && !(op->dx > 0.0)) return CN_ERR_INVALID_ARG;
+  if (!(op->dt == op->dt)) return CN_ERR_INVALID_ARG;
+  return CN_OK;
+}
+
+}  // namespace
+
+// =============================================================================== C ABI
+extern "C" {
+
+const char* cn_version(void) { return "cntri 0.1 (gfx950, FP64, N-shaped partition method)"; }
+
+const char* cn_status_string(cn_status st) {
+  switch (st) {
+    case CN_OK: return "CN_OK";
+    case CN_NUMERICAL_BREAKDOWN: return "CN_NUMERICAL_BREAKDOWN";
+    case CN_ERR_INVALID_ARG: return "CN_ERR_INVALID_ARG";
+    case CN_ERR_UNSUPPORTED: return "CN_ERR_UNSUPPORTED";
+    case CN_ERR_NO_MEMORY: return "CN_ERR_NO_MEMORY";
+    case CN_ERR_HIP: return "CN_ERR_HIP";
+    case CN_ERR_NOT_RESERVED: return "CN_ERR_NOT_RESERVED";
+  }
+  return "unknown cn_status";
+}
+
+cn_status cn_create(cn_handle_t* handle, int device) {
+  if (!handle) return CN_ERR_INVALID_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return CN_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return CN_ERR_HIP;
+  cn_handle_s* h = new cn_handle_s();
+  h->device = device;
+  if (hipMalloc(&h->status, sizeof(int)) != hipSuccess) {
+    delete h;
+    return CN_ERR_NO_MEMORY;
+  }
+  if (hipMemset(h->status, 0, sizeof(int)) != hipSuccess) {
+    (void)hipFree(h->status);
+    delete h;
+    return CN_ERR_HIP;
+  }
+  *handle = h;
+  return CN_OK;
+}
+
+cn_status cn_destroy(cn_handle_t h) {
+  if (!h) return CN_ERR_INVALID_ARG;
+  (void)hipDeviceSynchronize();
+  h->plans.clear();
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->status) (void)hipFree(h->status);
+  delete h;
+  return CN_OK;
+}
+
+cn_status cn_reserve(cn_handle_t h, const cn_layout* L) {
+  if (!h) return CN_ERR_INVALID_ARG;
+  Plan* P = nullptr;
+  for (int src : {nsd::SRC_EXPL, nsd::SRC_EXPL_CT, nsd::SRC_CN}) {
+    cn_status st = get_plan(h, L, src, nullptr, &P);
+    if (st != CN_OK) return st;
+  }
+  return CN_OK;
+}
+
+cn_status cn_describe_plan(cn_handle_t h, const cn_layout* L, int cn_mode, char* buf,
+                           int64_t buflen) {
+  if (!h || !buf || buflen < 1) return CN_ERR_INVALID_ARG;
+  Plan* P = nullptr;
+  cn_status st = get_plan(h, L, cn_mode ? nsd::SRC_CN : nsd::SRC_EXPL, nullptr, &P);
+  if (st != CN_OK) return st;
+  snprintf(buf, (size_t)buflen, "%s", P->desc.c_str());
+  return CN_OK;
+}
+
+cn_status cn_tridiag_solve(cn_handle_t h, const cn_layout* L, const void* a, const void* b,
+                           const void* c, const void* d, void* x, cn_stream_t stream) {
+  if (!h || !a || !b || !c || !d || !x) return CN_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  cn_status st = get_plan(h, L, nsd::SRC_EXPL, s, &P);
+  if (st != CN_OK) return st;
+  UserArgs u;
+  u.a = (const cd*)a;
+  u.b = (const cd*)b;
+  u.c = (const cd*)c;
+  u.d = (const cd*)d;
+  u.x = (cd*)x;
+  return run_plan(h, P, u, s);
+}
+
+cn_status cn_tridiag_solve_adjoint(cn_handle_t h, const cn_layout* L, const void* a,
+                                   const void* b, const void* c, const void* x, const void* gx,
+                                   void* gd, void* ga, void* gb, void* gc, cn_stream_t stream) {
+  if (!h || !a || !b || !c || !x || !gx || !gd) return CN_ERR_INVALID_ARG;
+  if (gd == x || gd == a || gd == b || gd == c) return CN_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  cn_status st = get_plan(h, L, nsd::SRC_EXPL_CT, s, &P);
+  if (st != CN_OK) return st;
+  UserArgs u;
+  u.a = (const cd*)a;
+  u.b = (const cd*)b;
+  u.c = (const cd*)c;
+  u.d = (const cd*)gx;
+  u.x = (cd*)gd;
+  st = run_plan(h, P, u, s);
+  if (st != CN_OK) return st;
+  if (ga || gb || gc) {
+    nsd::AuxArgs X = aux_from(L, P);
+    X.offs = dev_offsets(P);
+    X.lam = (const cd*)gd;
+    X.xsol = (const cd*)x;
+    X.ga = (cd*)ga;
+    X.gb = (cd*)gb;
+    X.gc = (cd*)gc;
+    st = launch_aux((const void*)&nsd::k_solve_grads, P->rows, X, s);
+  }
+  return st;
+}
+
+cn_status cn_assemble(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E, void* a,
+                      void* b, void* c, cn_stream_t stream) {
+  if (!h || !a || !b || !c) return CN_ERR_INVALID_ARG;
+  cn_status st = check_op(op);
+  if (st != CN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  if (st != CN_OK) return st;
+  nsd::AuxArgs X = aux_from(L, P);
+  X.offs = dev_offsets(P);
+  X.V = op->V;
+  X.xg = op->xgrid;
+  X.vscale = op->v_scale;
+  X.E = E;
+  X.dx = op->dx;
+  X.dxs = op->dx_per_system;
+  X.dt = op->dt;
+  X.a = (cd*)a;
+  X.b = (cd*)b;
+  X.c = (cd*)c;
+  return launch_aux((const void*)&nsd::k_assemble, P->rows, X, s);
+}
+
+cn_status cn_rhs(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E,
+                 const void* psi, void* d, cn_stream_t stream) {
+  if (!h || !psi || !d || psi == d) return CN_ERR_INVALID_ARG;
+  cn_status st = check_op(op);
+  if (st != CN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  if (st != CN_OK) return st;
+  nsd::AuxArgs X = aux_from(L, P);
+  X.offs = dev_offsets(P);
+  X.V = op->V;
+  X.xg = op->xgrid;
+  X.vscale = op->v_scale;
+  X.E = E;
+  X.dx = op->dx;
+  X.dxs = op->dx_per_system;
+  X.dt = op->dt;
+  X.psi = (const cd*)psi;
+  X.d = (cd*)d;
+  return launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
+}
+
+cn_status cn_step(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E,
+                  const void* psi_in, void* psi_out, cn_stream_t stream) {
+  if (!h || !psi_in || !psi_out) return CN_ERR_INVALID_ARG;
+  cn_status st = check_op(op);
+  if (st != CN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  if (st != CN_OK) return st;
+  UserArgs u;
+  u.psi = (const cd*)psi_in;
+  u.V = op->V;
+  u.xg = op->xgrid;
+  u.dxs = op->dx_per_system;
+  u.vscale = op->v_scale;
+  u.E_mat = E;
+  u.E_rhs = E;
+  u.dx = op->dx;
+  u.dt = op->dt;
+  u.x = (cd*)psi_out;
+  return run_plan(h, P, u, s);
+}
+
+cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op, int64_t nsteps,
+                       const double* E, void* psi, void* ckpt, int64_t K, cn_stream_t stream) {
+  if (!h || !psi || nsteps < 0) return CN_ERR_INVALID_ARG;
+  if (ckpt && K < 1) return CN_ERR_INVALID_ARG;
+  cn_status st = check_op(op);
+  if (st != CN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  if (st != CN_OK) return st;
+  UserArgs u;
+  u.psi = (const cd*)psi;
+  u.V = op->V;
+  u.xg = op->xgrid;
+  u.dxs = op->dx_per_system;
+  u.vscale = op->v_scale;
+  u.dx = op->dx;
+  u.dt = op->dt;
+  u.x = (cd*)psi;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (ckpt && k % K == 0) {
+      HIP_TRY(hipMemcpyAsync((cd*)ckpt + (k / K) * P->span, psi, P->span * sizeof(cd),
+                             hipMemcpyDeviceToDevice, s));
+    }
+    u.E_mat = u.E_rhs = E ? E[k] : 0.0;
+    st = run_plan(h, P, u, s);
+    if (st != CN_OK) return st;
+  }
+  return CN_OK;
+}
+
+cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E,
+                          const void* psi_n, const void* psi_np1, const void* g_np1, void* g_n,
+                          double* dV_accum, double* dE_partial, cn_stream_t stream) {
+  if (!h || !psi_n || !psi_np1 || !g_np1 || !g_n) return CN_ERR_INVALID_ARG;
+  if (dE_partial && !op->xgrid) return CN_ERR_INVALID_ARG;
+  cn_status st = check_op(op);
+  if (st != CN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  if (st != CN_OK) return st;
+  cd* lam = (cd*)((char*)h->ws + P->o_aux);
+  // lambda = T^{-H} g: T^H = 1 - i tau H is the CN matrix with dt -> -dt
+  UserArgs u;
+  u.rhs = (const cd*)g_np1;
+  u.psi = (const cd*)g_np1;
+  u.V = op->V;
+  u.xg = op->xgrid;
+  u.dxs = op->dx_per_system;
+  u.vscale = op->v_scale;
+  u.E_mat = u.E_rhs = E;
+  u.dx = op->dx;
+  u.dt = -op->dt;
+  u.x = lam;
+  st = run_plan(h, P, u, s);
+  if (st != CN_OK) return st;
+  // g_n = T lambda = (1 + i tau H) lambda: the explicit half-step with dt -> -dt
+  nsd::AuxArgs X = aux_from(L, P);
+  X.offs = dev_offsets(P);
+  X.V = op->V;
+  X.xg = op->xgrid;
+  X.vscale = op->v_scale;
+  X.E = E;
+  X.dx = op->dx;
+  X.dxs = op->dx_per_system;
+  X.dt = -op->dt;
+  X.psi = lam;
+  X.d = (cd*)g_n;
+  st = launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
+  if (st != CN_OK) return st;
+  // gradient terms
+  nsd::AuxArgs Y = aux_from(L, P);
+  Y.offs = X.offs;
+  Y.xg = op->xgrid;
+  Y.vscale = op->v_scale;
+  Y.dt = op->dt;
+  Y.lam = lam;
+  Y.psi_n = (const cd*)psi_n;
+  Y.psi_np1 = (const cd*)psi_np1;
+  Y.dV = dV_accum;
+  double* part = (double*)((char*)h->ws + P->o_part);
+  Y.dE_part = dE_partial ? part : nullptr;
+  st = launch_aux((const void*)&nsd::k_adj_accum, P->rows, Y, s);
+  if (st != CN_OK) return st;
+  if (dE_partial) {
+    hipLaunchKernelGGL(nsd::k_sum_partials, dim3(1), dim3(256), 0, s, (const double*)part,
+                       (int64_t)((P->rows + 255) / 256), dE_partial);
+    if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
+  }
+  return CN_OK;
+}
+
+cn_status cn_get_status(cn_handle_t h, cn_stream_t stream) {
+  if (!h) return CN_ERR_INVALID_ARG;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  int v = 0;
+  HIP_TRY(hipMemcpy(&v, h->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (v) {
+    HIP_TRY(hipMemset(h->status, 0, sizeof(int)));
+    return CN_NUMERICAL_BREAKDOWN;
+  }
+  return CN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// Device building blocks of the N-shaped partition solver for gfx950 (FP64 complex).
+//
+// Method: arXiv 2205.00856, Sec. 4 and Table 1.  One workgroup owns a "tile" of
+// T = 64 * W * M consecutive rows of one system and applies the method nested over three
+// granularities (Sec. 4.1.6, Eq. (6)):
+//   level 1  each lane owns a block of M rows: its top joint line J plus M-1 interior rows.
+//            RD+JD then RU+JU run on the block in registers (Table 1, in the order of
+//            Sec. 5.2.1).
+//   level 2+ the joint lines of neighbouring blocks form a reduced tridiagonal system; it is
+//            reduced again with blocks that contain exactly one interior joint line, for
+//            which RD/RU are empty and JU/JD are one elimination each.  Inside a wavefront
+//            the pairs exchange data with cross-lane moves (6 levels), across the W
+//            wavefronts of the workgroup through LDS (log2 W levels).
+//   top      either the RS stage on the tile's two joint lines (whole system in one tile),
+//            or the tile's two joint-line "slots" are written out so that the reduced system
+//            over all tiles is solved by the same method one level up.
+// SS runs the other way: from the tile's joint lines down the tree to every row.
+//
+// Every reduced row is scaled by its pivot as soon as the pivot is known (the 1/a_i
+// precompute of Sec. 5.2.2 applied in place), so a reduced interior row is stored as
+//     psi_i + beta_i psi_J + gamma_i psi_K = delta_i
+// and SS is psi_i = delta_i - beta_i psi_J - gamma_i psi_K.  Table 1's updates become
+//   RD (row i-1 scaled):  r = -b_i;       a_i += r gamma_{i-1}; b_i = r beta_{i-1}; d_i += r delta_{i-1}
+//   RU (row i+1 final):   r = -gamma_i;   beta_i += r beta_{i+1}; gamma_i = r gamma_{i+1}; delta_i += r delta_{i+1}
+// which are the printed operations applied to the row-scaled system.
+//
+// Block state ("two slots", Sec. 4.1.3): a reduced block [J, K] contributes
+//   to row J (U slot, own row folded in):  UA psi_J + UC psi_K = UD
+//   to row K (D slot):                     DB psi_J + DA psi_K = DD
+// and the reader adds the slots in a fixed order, so no floating-point atomics are used.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsd {
+
+typedef double2 cd;
+
+__device__ __forceinline__ cd mk(double r, double i) {
+  cd z;
+  z.x = r;
+  z.y = i;
+  return z;
+}
+__device__ __forceinline__ cd czero() { return mk(0.0, 0.0); }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return mk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return mk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd cneg(cd a) { return mk(-a.x, -a.y); }
+__device__ __forceinline__ cd cconj(cd a) { return mk(a.x, -a.y); }
+__device__ __forceinline__ cd cmul(cd a, cd b) {
+  return mk(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// acc + a * b
+__device__ __forceinline__ cd cfma(cd a, cd b, cd acc) {
+  return mk(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+// acc - a * b
+__device__ __forceinline__ cd cfms(cd a, cd b, cd acc) {
+  return mk(fma(-a.x, b.x, fma(a.y, b.y, acc.x)), fma(-a.x, b.y, fma(-a.y, b.x, acc.y)));
+}
+__device__ __forceinline__ cd csel(bool p, cd a, cd b) { return mk(p ? a.x : b.x, p ? a.y : b.y); }
+
+// 1/v from the hardware estimate refined by two Newton-Raphson steps
+// x <- x + x (1 - v x)  (Newton's iteration for the reciprocal; the error squares per step).
+__device__ __forceinline__ double rcp_nr(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  double e = fma(-v, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-v, r, 1.0);
+  r = fma(r, e, r);
+  return r;
+}
+// 1/a = conj(a) / |a|^2  (valid while |a|^2 is a normal double)
+__device__ __forceinline__ cd crecip(cd a) {
+  double s = rcp_nr(fma(a.x, a.x, a.y * a.y));
+  return mk(a.x * s, -a.y * s);
+}
+__device__ __forceinline__ bool cfinite(cd a) { return isfinite(a.x) && isfinite(a.y); }
+
+struct Blk {
+  cd UA, UC, UD;  // U slot: contribution to (and own data of) the top joint row
+  cd DB, DA, DD;  // D slot: contribution to the bottom joint row
+};
+// one eliminated joint line K between J and M, scaled:  psi_K = dl - B psi_J - C psi_M
+struct Node {
+  cd B, C, dl;
+};
+
+// ---------------------------------------------------------------- level 1: one lane's block
+// Input rows J .. J+M-1 (local 0 .. M-1) as (a, b, c, d) in (A, Bt, Ct, D); bK is the
+// sub-diagonal of the next joint line K = J+M.  On return rows 1..M-1 hold the scaled reduced
+// rows (beta in Bt, gamma in Ct, delta in D) for SS; A is consumed.
+template <int M>
+__device__ __forceinline__ void reduce_block(cd (&A)[M], cd (&Bt)[M], cd (&Ct)[M], cd (&D)[M],
+                                             cd bK, Blk& o) {
+  if constexpr (M == 1) {
+    // a block without interior rows: its two joint lines are coupled directly
+    o.UA = A[0];
+    o.UC = Ct[0];
+    o.UD = D[0];
+    o.DB = bK;
+    o.DA = czero();
+    o.DD = czero();
+  } else {
+    // row J+1 keeps its b (coefficient of psi_J); scale it by its pivot
+    {
+      cd ia = crecip(A[1]);
+      Bt[1] = cmul(Bt[1], ia);
+      Ct[1] = cmul(Ct[1], ia);
+      D[1] = cmul(D[1], ia);
+    }
+    // RD: i = J+2 .. K-1 with row i-1 scaled: r = -b_i
+#pragma unroll
+    for (int i = 2; i < M; ++i) {
+      cd a = cfms(Bt[i], Ct[i - 1], A[i]);       // a_i - b_i gamma_{i-1}
+      cd d = cfms(Bt[i], D[i - 1], D[i]);        // d_i - b_i delta_{i-1}
+      cd b = cneg(cmul(Bt[i], Bt[i - 1]));       // -b_i beta_{i-1}
+      cd ia = crecip(a);
+      Bt[i] = cmul(b, ia);
+      Ct[i] = cmul(Ct[i], ia);
+      D[i] = cmul(d, ia);
+    }
+    // JD at K: r = -b_K (row K-1 scaled)
+    o.DB = cneg(cmul(bK, Bt[M - 1]));
+    o.DA = cneg(cmul(bK, Ct[M - 1]));
+    o.DD = cneg(cmul(bK, D[M - 1]));
+    // RU: i = K-2 .. J+1 with row i+1 final: r = -gamma_i
+#pragma unroll
+    for (int i = M - 2; i >= 1; --i) {
+      cd g = Ct[i];
+      Bt[i] = cfms(g, Bt[i + 1], Bt[i]);
+      D[i] = cfms(g, D[i + 1], D[i]);
+      Ct[i] = cneg(cmul(g, Ct[i + 1]));
+    }
+    // JU at J: r = -c_J (row J+1 final)
+    o.UA = cfms(Ct[0], Bt[1], A[0]);
+    o.UD = cfms(Ct[0], D[1], D[0]);
+    o.UC = cneg(cmul(Ct[0], Ct[1]));
+  }
+}
+
+// SS on the lane's block: psi_i = delta_i - beta_i psi_J - gamma_i psi_K.
+template <int M>
+__device__ __forceinline__ void ss_block(const cd (&Bt)[M], const cd (&Ct)[M], const cd (&D)[M],
+                                         cd pJ, cd pK, cd (&x)[M]) {
+  x[0] = pJ;
+#pragma unroll
+  for (int i = 1; i < M; ++i) x[i] = cfms(Ct[i], pK, cfms(Bt[i], pJ, D[i]));
+}
+
+// ------------------------------------------------------------------ cross-lane xor moves
+// lane i receives the value of lane i ^ m (m a power of two below 64)
+template <int m>
+__device__ __forceinline__ int xmove(int v) {
+  if constexpr (m == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (m == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (m == 4) {
+    int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror: i ^ 7
+    return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false);    // quad_perm [3,2,1,0]: i ^ 3
+  } else if constexpr (m == 8) {
+    return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (m == 16) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // bitmask mode, xor 0x10 within 32 lanes
+  } else {
+    return __shfl_xor(v, m, 64);
+  }
+}
+template <int m>
+__device__ __forceinline__ double xmove(double v) {
+  int2 t = __builtin_bit_cast(int2, v);
+  t.x = xmove<m>(t.x);
+  t.y = xmove<m>(t.y);
+  return __builtin_bit_cast(double, t);
+}
+template <int m>
+__device__ __forceinline__ cd xmove(cd v) {
+  return mk(xmove<m>(v.x), xmove<m>(v.y));
+}
+
+// ------------------------------------------------------------- level 2+: pairs of blocks
+// L = [J, K], R = [K, M]: eliminate joint line K (the single interior row of [J, M]).
+//   row K: DB_L psi_J + (DA_L + UA_R) psi_K + UC_R psi_M = DD_L + UD_R, scaled by its pivot:
+//          psi_K + B psi_J + C psi_M = dl
+//   JU at J: r = -UC_L: UA += r B; UC = r C; UD += r dl
+//   JD at M: r = -DB_R: DB = r B;  DA += r C; DD += r dl
+// The pair is held by two lanes; both compute the scaled row K, then the lane of L keeps the
+// merged block and the lane of R keeps the node for SS.
+template <int m>
+__device__ __forceinline__ void tree_level_up(Blk& b, Node& nd, bool right, bool active) {
+  Blk o;
+  o.UA = xmove<m>(b.UA);
+  o.UC = xmove<m>(b.UC);
+  o.UD = xmove<m>(b.UD);
+  o.DB = xmove<m>(b.DB);
+  o.DA = xmove<m>(b.DA);
+  o.DD = xmove<m>(b.DD);
+  const cd LDA = csel(right, o.DA, b.DA), RUA = csel(right, b.UA, o.UA);
+  const cd LDD = csel(right, o.DD, b.DD), RUD = csel(right, b.UD, o.UD);
+  const cd LDB = csel(right, o.DB, b.DB), RUC = csel(right, b.UC, o.UC);
+  const cd ia = crecip(cadd(LDA, RUA));
+  Node t;
+  t.B = cmul(LDB, ia);
+  t.C = cmul(RUC, ia);
+  t.dl = cmul(cadd(LDD, RUD), ia);
+  if (active) {
+    if (right) {
+      nd = t;
+    } else {
+      // b is L, o is R
+      const cd rU = b.UC;
+      const cd rD = o.DB;
+      b.UA = cfms(rU, t.B, b.UA);
+      b.UD = cfms(rU, t.dl, b.UD);
+      b.UC = cneg(cmul(rU, t.C));
+      b.DB = cneg(cmul(rD, t.B));
+      b.DA = cfms(rD, t.C, o.DA);
+      b.DD = cfms(rD, t.dl, o.DD);
+    }
+  }
+}
+
+// Binary nesting over 2^LEVELS consecutive lanes: afterwards the lane with the low LEVELS bits
+// clear holds the merged block and every other lane the node of the joint line it owns.
+template <int LEVELS>
+__device__ __forceinline__ void tree_up(Blk& b, Node& nd, int lane) {
+  if constexpr (LEVELS > 0) tree_level_up<1>(b, nd, (lane & 1) != 0, true);
+  if constexpr (LEVELS > 1) tree_level_up<2>(b, nd, (lane & 2) != 0, (lane & 1) == 0);
+  if constexpr (LEVELS > 2) tree_level_up<4>(b, nd, (lane & 4) != 0, (lane & 3) == 0);
+  if constexpr (LEVELS > 3) tree_level_up<8>(b, nd, (lane & 8) != 0, (lane & 7) == 0);
+  if constexpr (LEVELS > 4) tree_level_up<16>(b, nd, (lane & 16) != 0, (lane & 15) == 0);
+  if constexpr (LEVELS > 5) tree_level_up<32>(b, nd, (lane & 32) != 0, (lane & 31) == 0);
+}
+
+template <int m>
+__device__ __forceinline__ void tree_level_down(cd& pJ, cd& pM, const Node& nd, bool right,
+                                                bool active) {
+  const cd oJ = xmove<m>(pJ);
+  const cd oM = xmove<m>(pM);
+  const cd pK = cfms(nd.C, oM, cfms(nd.B, oJ, nd.dl));
+  const cd back = xmove<m>(pK);
+  if (active) {
+    if (right) {
+      pJ = pK;
+      pM = oM;
+    } else {
+      pM = back;
+    }
+  }
+}
+
+// SS down the binary nesting: on entry the group's first lane holds (psi_J, psi_M) of the whole
+// span; on exit every lane holds psi at its own joint line (pJ) and at the next one (pM).
+template <int LEVELS>
+__device__ __forceinline__ void tree_down(cd& pJ, cd& pM, const Node& nd, int lane) {
+  if constexpr (LEVELS > 5) tree_level_down<32>(pJ, pM, nd, (lane & 32) != 0, (lane & 31) == 0);
+  if constexpr (LEVELS > 4) tree_level_down<16>(pJ, pM, nd, (lane & 16) != 0, (lane & 15) == 0);
+  if constexpr (LEVELS > 3) tree_level_down<8>(pJ, pM, nd, (lane & 8) != 0, (lane & 7) == 0);
+  if constexpr (LEVELS > 2) tree_level_down<4>(pJ, pM, nd, (lane & 4) != 0, (lane & 3) == 0);
+  if constexpr (LEVELS > 1) tree_level_down<2>(pJ, pM, nd, (lane & 2) != 0, (lane & 1) == 0);
+  if constexpr (LEVELS > 0) tree_level_down<1>(pJ, pM, nd, (lane & 1) != 0, true);
+}
+
+// ------------------------------------------------------------------ LDS staging per wavefront
+// A wavefront covers rows w0 .. w0+64M-1 plus one halo row on each side.  Global loads and
+// stores are coalesced (lane l touches row w0 + 64k + l); the lane-to-block transposition goes
+// through LDS, padded by one element per M rows so that lane strides of M+1 elements are free
+// of bank conflicts.
+template <int M>
+struct Stage {
+  static constexpr int QN = 64 * M + 2;       // staged rows: w0-1 .. w0+64M
+  static constexpr int QS = QN + QN / M + 2;  // padded length
+  __device__ static __forceinline__ int addr(int q) { return q + q / M; }
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace nsd

@@ -1,0 +1,498 @@
+// Kernels of the N-shaped partition solver (gfx950, FP64 complex).
+// Method: arXiv 2205.00856, Sec. 4 (Table 1, nesting Eq. (6)), Sec. 5.3 (fused explicit
+// half-step), Sec. 2 (Crank-Nicolson operator).
+#pragma once
+#include "nshaped_device.hpp"
+
+namespace nsd {
+
+enum Src : int {
+  SRC_EXPL = 0,     // explicit a, b, c, d arrays
+  SRC_EXPL_CT = 1,  // explicit arrays, conjugate-transposed matrix T^H (adjoint solve)
+  SRC_CN = 2,       // Crank-Nicolson operator assembled in-kernel from V, dx, dt (+ x E)
+  SRC_SLOTS = 3     // reduced system of the level below, read from its two slot arrays
+};
+enum Phase : int {
+  PH_SINGLE = 0,  // the tile holds the whole system: reduce, RS, SS in one pass
+  PH_REDUCE = 1,  // first pass of a multi-tile system: reduce, write the tile's slots
+  PH_SUBST = 2    // second pass: re-reduce, take the tile's joint lines from above, SS
+};
+
+struct KArgs {
+  // batch geometry
+  int64_t n;              // uniform batch: rows per system
+  int64_t ntiles;         // uniform batch: tiles per system
+  int64_t es, bs;         // uniform batch: element / batch strides (elements)
+  const int64_t* offs;    // uneven batch: CSR row offsets per system (device) or null
+  const int64_t* tbase;   // uneven multi-tile: first global tile per system (device) or null
+  const int* wg_sys;      // launch list: system of each workgroup (device) or null
+  const int* wg_tile;     // launch list: tile of each workgroup
+  // explicit sources
+  const cd *a, *b, *c, *d;
+  // Crank-Nicolson source
+  const cd* psi;          // state for the explicit half-step
+  const cd* rhs;          // given right-hand side instead of the half-step (or null)
+  const double* V;
+  const double* xg;
+  double vscale, E_mat, E_rhs, dx, dt;
+  const double* dxs;
+  // reduced-system source (level >= 2)
+  const cd* sU;           // 3 values per tile: UA, UC, UD
+  const cd* sD;           // 3 values per tile: DB, DA, DD
+  // outputs and hand-over between passes
+  cd* x;
+  cd* oU;
+  cd* oD;
+  const cd* psi_if;       // solution of the reduced system (one value per tile)
+  cd* halo_out;           // first and last state row of each tile (pass 1)
+  const cd* halo_in;
+  int* status;
+};
+
+struct Geo {
+  int64_t sys, tile, n, base, es, gt, ntile;
+};
+
+__device__ __forceinline__ Geo geometry(const KArgs& A) {
+  Geo g;
+  if (A.wg_sys) {
+    g.sys = A.wg_sys[blockIdx.x];
+    g.tile = A.wg_tile[blockIdx.x];
+  } else {
+    g.sys = blockIdx.y;
+    g.tile = blockIdx.x;
+  }
+  if (A.offs) {
+    g.base = A.offs[g.sys];
+    g.n = A.offs[g.sys + 1] - g.base;
+    g.es = 1;
+    if (A.tbase) {
+      g.gt = A.tbase[g.sys] + g.tile;
+      g.ntile = A.tbase[g.sys + 1] - A.tbase[g.sys];
+    } else {
+      g.gt = g.sys;
+      g.ntile = 1;
+    }
+  } else {
+    g.base = g.sys * A.bs;
+    g.n = A.n;
+    g.es = A.es;
+    g.gt = g.sys * A.ntiles + g.tile;
+    g.ntile = A.ntiles;
+  }
+  return g;
+}
+
+__device__ __forceinline__ double sel(bool p, double a, double b) { return p ? a : b; }
+__device__ __forceinline__ cd sel(bool p, cd a, cd b) { return csel(p, a, b); }
+
+// Fetch rows w0 + 64k + lane (k < M) and the two halo rows w0-1 (lane 0) and w0+64M (lane 1)
+// of a strided array into registers.  Loads are unconditional at a clamped row (n >= 1) and the
+// fill value is selected afterwards, so no lane takes a different path.
+template <int M, typename T>
+__device__ __forceinline__ void stage_fetch(const T* g, int64_t es, int64_t w0, int64_t n,
+                                            int lane, T fill, T (&v)[M], T& h) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int64_t r = w0 + 64 * k + lane;
+    const T t = g[(r < n ? r : n - 1) * es];
+    v[k] = sel(r < n, t, fill);
+  }
+  const int64_t rr = (lane == 0) ? w0 - 1 : w0 + 64 * M;
+  const int64_t rc = rr < 0 ? 0 : (rr < n ? rr : n - 1);
+  const T t = g[rc * es];
+  h = sel(rr >= 0 && rr < n, t, fill);
+}
+
+template <int M, typename T>
+__device__ __forceinline__ void stage_put(T* buf, int lane, const T (&v)[M], T h) {
+  using S = Stage<M>;
+#pragma unroll
+  for (int k = 0; k < M; ++k) buf[S::addr(1 + 64 * k + lane)] = v[k];
+  if (lane == 0) buf[S::addr(0)] = h;
+  if (lane == 1) buf[S::addr(S::QN - 1)] = h;
+}
+
+// Read rows J-1 .. J+M of this lane (J = w0 + lane*M) from the staged buffer.
+template <int M, typename T>
+__device__ __forceinline__ void stage_read(const T* buf, int lane, T (&v)[M + 2]) {
+  using S = Stage<M>;
+#pragma unroll
+  for (int j = 0; j < M + 2; ++j) v[j] = buf[S::addr(lane * M + j)];
+}
+
+// registers (coalesced order) -> LDS -> registers (lane-block order)
+template <int M, typename T>
+__device__ __forceinline__ void transpose_in(T* buf, int lane, const T (&v)[M], T h,
+                                             T (&out)[M + 2]) {
+  stage_put<M>(buf, lane, v, h);
+  wave_sync();
+  stage_read<M>(buf, lane, out);
+  wave_sync();
+}
+
+template <int M>
+__device__ __forceinline__ void stage_out(cd* buf, cd* g, int64_t es, int64_t w0, int64_t n,
+                                          int lane, const cd (&x)[M]) {
+  using S = Stage<M>;
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < M; ++j) buf[S::addr(lane * M + j + 1)] = x[j];
+  wave_sync();
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    int64_t r = w0 + 64 * k + lane;
+    if (r < n) g[r * es] = buf[S::addr(1 + 64 * k + lane)];
+  }
+}
+
+// ------------------------------------------------------------------ row assembly per source
+template <int M, int W, int SRC, int PH>
+__device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
+                                          int64_t J, int lane, int wave, cd (&Ar)[M],
+                                          cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M], cd& bK,
+                                          cd& first_state, cd& last_state) {
+  const int64_t n = G.n;
+  if constexpr (SRC == SRC_EXPL || SRC == SRC_EXPL_CT) {
+    const cd one = mk(1.0, 0.0), zero = czero();
+    cd ra[M], rb[M], rc[M], rd[M], ha, hb, hc, hd;
+    stage_fetch<M>(A.a + G.base, G.es, w0, n, lane, one, ra, ha);
+    stage_fetch<M>(A.b + G.base, G.es, w0, n, lane, zero, rb, hb);
+    stage_fetch<M>(A.c + G.base, G.es, w0, n, lane, zero, rc, hc);
+    stage_fetch<M>(A.d + G.base, G.es, w0, n, lane, zero, rd, hd);
+    cd va[M + 2], vb[M + 2], vc[M + 2], vd[M + 2];
+    transpose_in<M>(buf, lane, ra, ha, va);
+    transpose_in<M>(buf, lane, rb, hb, vb);
+    transpose_in<M>(buf, lane, rc, hc, vc);
+    transpose_in<M>(buf, lane, rd, hd, vd);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = J + j;
+      const bool ok = r < n;
+      if constexpr (SRC == SRC_EXPL) {
+        Ar[j] = csel(ok, va[j + 1], one);
+        Br[j] = csel(ok && r > 0, vb[j + 1], zero);
+        Cr[j] = csel(ok && r < n - 1, vc[j + 1], zero);
+      } else {
+        // row i of T^H: diagonal conj(a_i), sub conj(c_{i-1}), super conj(b_{i+1})
+        Ar[j] = csel(ok, cconj(va[j + 1]), one);
+        Br[j] = csel(ok && r > 0, cconj(vc[j]), zero);
+        Cr[j] = csel(ok && r < n - 1, cconj(vb[j + 2]), zero);
+      }
+      Dr[j] = csel(ok, vd[j + 1], zero);
+    }
+    const int64_t K = J + M;
+    if constexpr (SRC == SRC_EXPL)
+      bK = csel(K < n, vb[M + 1], zero);
+    else
+      bK = csel(K < n, cconj(vc[M]), zero);
+    first_state = last_state = zero;
+  } else if constexpr (SRC == SRC_CN) {
+    const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
+    const double tau = 0.5 * A.dt;
+    const double idx2 = 1.0 / (dx * dx);
+    const double kap = tau * 0.5 * idx2;
+    const bool given = A.rhs != nullptr;
+    const cd zero = czero();
+    cd rp[M], hp;
+    double rv[M], hv, rx[M], hx;
+    stage_fetch<M>(given ? A.rhs + G.base : A.psi + G.base, G.es, w0, n, lane, zero, rp, hp);
+    stage_fetch<M>(A.V + G.base, G.es, w0, n, lane, 0.0, rv, hv);
+    if (A.xg) stage_fetch<M>(A.xg + G.base, G.es, w0, n, lane, 0.0, rx, hx);
+    if constexpr (PH == PH_SUBST) {
+      // the neighbours' edge rows may already hold the new state: take the saved copies
+      if (!given) {
+        if (wave == 0 && lane == 0 && G.tile > 0) hp = A.halo_in[2 * (G.gt - 1) + 1];
+        if (wave == W - 1 && lane == 1 && G.tile + 1 < G.ntile) hp = A.halo_in[2 * (G.gt + 1)];
+      }
+    }
+    cd vp[M + 2];
+    transpose_in<M>(buf, lane, rp, hp, vp);
+    double vv[M + 2], xv[M + 2];
+    double* bufd = reinterpret_cast<double*>(buf);
+    transpose_in<M>(bufd, lane, rv, hv, vv);
+    if (A.xg) {
+      transpose_in<M>(bufd, lane, rx, hx, xv);
+    } else {
+#pragma unroll
+      for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = J + j;
+      const bool ok = r < n;
+      const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
+      Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
+      Br[j] = mk(0.0, (ok && r > 0) ? -kap : 0.0);
+      Cr[j] = mk(0.0, (ok && r < n - 1) ? -kap : 0.0);
+      if (given) {
+        Dr[j] = vp[j + 1];
+      } else {
+        // d = (1 - i tau (1/dx^2 + v)) psi + i kappa (psi_{j-1} + psi_{j+1})  (Sec. 2, Eq. (3))
+        const double w = tau * (idx2 + fma(xv[j + 1], A.E_rhs, A.vscale * vv[j + 1]));
+        const cd p = vp[j + 1];
+        const cd s = cadd(vp[j], vp[j + 2]);
+        Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
+      }
+    }
+    bK = mk(0.0, (J + M < n) ? -kap : 0.0);
+    first_state = vp[1];
+    last_state = vp[M];
+  } else {  // SRC_SLOTS: row k of the reduced system = U slot of tile k + D slot of tile k-1
+    const cd zero = czero();
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = J + j;
+      const bool ok = r < n;
+      const int64_t g = G.base + (ok ? r : n - 1);
+      const int64_t gp = (ok && r > 0) ? g - 1 : g;
+      const cd ua = A.sU[3 * g], uc = A.sU[3 * g + 1], ud = A.sU[3 * g + 2];
+      const cd db = A.sD[3 * gp], da = A.sD[3 * gp + 1], dd = A.sD[3 * gp + 2];
+      const bool hasp = ok && r > 0;
+      Ar[j] = csel(ok, cadd(ua, csel(hasp, da, zero)), mk(1.0, 0.0));
+      Br[j] = csel(hasp, db, zero);
+      Cr[j] = csel(ok && r < n - 1, uc, zero);
+      Dr[j] = csel(ok, cadd(ud, csel(hasp, dd, zero)), zero);
+    }
+    const int64_t K = J + M;
+    const int64_t gk = G.base + (K < n ? K - 1 : 0);
+    const cd t = A.sD[3 * gk];
+    bK = csel(K < n, t, zero);
+    first_state = last_state = zero;
+  }
+}
+
+template <int W>
+struct Log2 {
+  static constexpr int v = (W <= 1) ? 0 : 1 + Log2<W / 2>::v;
+};
+template <>
+struct Log2<1> {
+  static constexpr int v = 0;
+};
+
+// One workgroup = one tile of T = 64*W*M rows of one system.
+template <int M, int W, int SRC, int PH>
+__global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
+  using S = Stage<M>;
+  constexpr int LW = Log2<W>::v;
+  constexpr int64_t T = 64 * W * M;
+  __shared__ cd lds[W][S::QS];
+  __shared__ Blk wblk[W];
+  __shared__ cd wpsi[W][2];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const Geo G = geometry(A);
+  const int64_t t0 = G.tile * T;
+  const int64_t w0 = t0 + (int64_t)wave * 64 * M;
+  const int64_t J = w0 + (int64_t)lane * M;
+  cd* buf = lds[wave];
+
+  cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
+  load_rows<M, W, SRC, PH>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+
+  if constexpr (PH == PH_REDUCE && SRC == SRC_CN) {
+    if (A.halo_out) {
+      if (wave == 0 && lane == 0) A.halo_out[2 * G.gt] = fst;
+      if (wave == W - 1 && lane == 63) A.halo_out[2 * G.gt + 1] = lst;
+    }
+  }
+
+  Blk blk;
+  reduce_block<M>(Ar, Br, Cr, Dr, bK, blk);
+  Node nd;
+  tree_up<6>(blk, nd, lane);
+  Node ndw;
+  if constexpr (W > 1) {
+    if (lane == 0) wblk[wave] = blk;
+    __syncthreads();
+    if (wave == 0) {
+      blk = wblk[lane & (W - 1)];
+      tree_up<LW>(blk, ndw, lane);
+    }
+  }
+
+  cd pJ = czero(), pM = czero();
+  if (wave == 0 && lane == 0) {
+    if constexpr (PH == PH_REDUCE) {
+      A.oU[3 * G.gt] = blk.UA;
+      A.oU[3 * G.gt + 1] = blk.UC;
+      A.oU[3 * G.gt + 2] = blk.UD;
+      A.oD[3 * G.gt] = blk.DB;
+      A.oD[3 * G.gt + 1] = blk.DA;
+      A.oD[3 * G.gt + 2] = blk.DD;
+    } else if constexpr (PH == PH_SINGLE) {
+      // RS on the two joint lines of the tile (the bottom one lies past the system end)
+      cd ia0 = crecip(blk.UA);
+      cd r = cneg(cmul(blk.DB, ia0));
+      cd aT = cfma(r, blk.UC, cadd(mk(1.0, 0.0), blk.DA));
+      cd dT = cfma(r, blk.UD, blk.DD);
+      pM = cmul(dT, crecip(aT));
+      pJ = cmul(cfms(blk.UC, pM, blk.UD), ia0);
+    } else {
+      pJ = A.psi_if[G.gt];
+      const cd nxt = A.psi_if[(G.tile + 1 < G.ntile) ? G.gt + 1 : G.gt];
+      pM = csel(G.tile + 1 < G.ntile, nxt, czero());
+    }
+  }
+  if constexpr (PH == PH_REDUCE) return;
+
+  if constexpr (W > 1) {
+    if (wave == 0) {
+      tree_down<LW>(pJ, pM, ndw, lane);
+      if (lane < W) {
+        wpsi[lane][0] = pJ;
+        wpsi[lane][1] = pM;
+      }
+    }
+    __syncthreads();
+    pJ = wpsi[wave][0];
+    pM = wpsi[wave][1];
+  }
+  tree_down<6>(pJ, pM, nd, lane);
+
+  cd xo[M];
+  ss_block<M>(Br, Cr, Dr, pJ, pM, xo);
+
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < M; ++j) bad |= (J + j < G.n) && !cfinite(xo[j]);
+  if (__any(bad) && lane == 0) atomicOr(A.status, 1);
+
+  if constexpr (SRC == SRC_SLOTS) {
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+      if (J + j < G.n) A.x[G.base + J + j] = xo[j];
+  } else {
+    stage_out<M>(buf, A.x + G.base, G.es, w0, G.n, lane, xo);
+  }
+}
+
+// ------------------------------------------------------------------------ auxiliary kernels
+struct AuxArgs {
+  int64_t n, batch, es, bs;
+  const int64_t* offs;
+  int64_t total;  // total rows (uneven) or n*batch
+  const double* V;
+  const double* xg;
+  double vscale, E, dx, dt;
+  const double* dxs;
+  const cd* psi;
+  cd *a, *b, *c, *d;
+  // adjoint accumulation
+  const cd* lam;
+  const cd* psi_n;
+  const cd* psi_np1;
+  double* dV;
+  double* dE_part;
+  // solve gradients
+  const cd* xsol;
+  cd *ga, *gb, *gc;
+};
+
+// Locate (system, row, element) of flat index t.
+__device__ __forceinline__ bool locate(const AuxArgs& A, int64_t t, int64_t& sys, int64_t& r,
+                                       int64_t& n, int64_t& e) {
+  if (A.offs) {
+    if (t >= A.total) return false;
+    int64_t lo = 0, hi = A.batch;  // find sys with offs[sys] <= t < offs[sys+1]
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (A.offs[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    sys = lo;
+    r = t - A.offs[sys];
+    n = A.offs[sys + 1] - A.offs[sys];
+    e = t;
+  } else {
+    if (t >= A.n * A.batch) return false;
+    sys = t / A.n;
+    r = t - sys * A.n;
+    n = A.n;
+    e = sys * A.bs + r * A.es;
+  }
+  return true;
+}
+
+// a1: coefficients of T = 1 + i tau H
+__global__ void k_assemble(AuxArgs A) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  if (!locate(A, t, sys, r, n, e)) return;
+  const double dx = A.dxs ? A.dxs[sys] : A.dx;
+  const double tau = 0.5 * A.dt, idx2 = 1.0 / (dx * dx), kap = tau * 0.5 * idx2;
+  const double v = A.vscale * A.V[e] + (A.xg ? A.xg[e] * A.E : 0.0);
+  A.a[e] = mk(1.0, tau * (idx2 + v));
+  A.b[e] = mk(0.0, (r > 0) ? -kap : 0.0);
+  A.c[e] = mk(0.0, (r < n - 1) ? -kap : 0.0);
+}
+
+// a2: d = (1 - i tau H) psi
+__global__ void k_rhs(AuxArgs A) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  if (!locate(A, t, sys, r, n, e)) return;
+  const int64_t st = A.offs ? 1 : A.es;
+  const double dx = A.dxs ? A.dxs[sys] : A.dx;
+  const double tau = 0.5 * A.dt, idx2 = 1.0 / (dx * dx), kap = tau * 0.5 * idx2;
+  const double w = tau * (idx2 + A.vscale * A.V[e] + (A.xg ? A.xg[e] * A.E : 0.0));
+  const cd p = A.psi[e];
+  const cd l = csel(r > 0, A.psi[(r > 0) ? e - st : e], czero());
+  const cd h = csel(r < n - 1, A.psi[(r < n - 1) ? e + st : e], czero());
+  const cd s = cadd(l, h);
+  A.d[e] = mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y)));
+}
+
+// gradients of the solve: ga_i = -lam_i conj(x_i), gb_i = -lam_i conj(x_{i-1}), gc_i = ...
+__global__ void k_solve_grads(AuxArgs A) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  if (!locate(A, t, sys, r, n, e)) return;
+  const int64_t st = A.offs ? 1 : A.es;
+  const cd l = A.lam[e];
+  if (A.ga) A.ga[e] = cneg(cmul(l, cconj(A.xsol[e])));
+  if (A.gb) A.gb[e] = csel(r > 0, cneg(cmul(l, cconj(A.xsol[(r > 0) ? e - st : e]))), czero());
+  if (A.gc) A.gc[e] = csel(r < n - 1, cneg(cmul(l, cconj(A.xsol[(r < n - 1) ? e + st : e]))), czero());
+}
+
+// adjoint accumulation: q_j = tau Im(conj(lam_j)(psi_n,j + psi_np1,j));
+// dV_j += vscale q_j; per-block partial sums of x_j q_j (summed in a fixed order).
+__global__ __launch_bounds__(256) void k_adj_accum(AuxArgs A) {
+  __shared__ double red[256];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  double part = 0.0;
+  if (locate(A, t, sys, r, n, e)) {
+    const double tau = 0.5 * A.dt;
+    const cd l = A.lam[e];
+    const cd s = cadd(A.psi_n[e], A.psi_np1[e]);
+    const double q = tau * (l.x * s.y - l.y * s.x);
+    if (A.dV) A.dV[e] += A.vscale * q;
+    if (A.xg) part = A.xg[e] * q;
+  }
+  if (!A.dE_part) return;
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A.dE_part[blockIdx.x] = red[0];
+}
+
+// deterministic second stage: out[0] = sum of nparts partials (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_sum_partials(const double* part, int64_t nparts,
+                                                      double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace nsd

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP N-shaped path against the CPU oracle, through the C ABI.
+
+Tolerance: relative L2 <= 1e-11 on complex128 (the workloads' stated bar).  Both sides are
+FP64; differences are rounding only (the method reaches x = T^{-1} d exactly, Appendix I).
+Sizes span several tiles, ragged tails, nested interface levels and the degenerate cases
+(n = 1, one row past a tile, a tile holding the whole system).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_00856_amd as cn
+
+    cn.handle(0)
+    return torch, cn
+
+
+def rel(x, y):
+    x = np.asarray(x)
+    y = np.asarray(y)
+    return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
+
+
+def to_dev(torch, *arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ cn_tridiag_solve
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 65, 127, 128, 129, 255, 256, 257, 1000, 1024,
+                               1025, 4095, 4096, 4097, 10_000, 65_537, 1_000_003])
+@pytest.mark.parametrize("kind", ["dd", "herm"])
+def test_solve_single_system(gpu, oracle_mod, n, kind):
+    torch, cn = gpu
+    log("solve", n, kind)
+    a, b, c, d = workloads.random_system(n, 1000 + n, kind)
+    ref = oracle_mod.thomas(a, b, c, d)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x = cn.solve(ta, tb, tc, td)
+    torch.cuda.synchronize()
+    assert rel(x.cpu().numpy(), ref) <= TOL
+    assert cn.get_status() == 0
+
+
+@pytest.mark.parametrize("T,M", [(128, 2), (256, 4), (512, 4), (512, 8), (1024, 4), (1024, 8),
+                                 (2048, 4), (2048, 8), (4096, 8)])
+def test_solve_partition_sweep(gpu, oracle_mod, T, M):
+    torch, cn = gpu
+    n = 300_007
+    log("partition", T, M)
+    a, b, c, d = workloads.random_system(n, 77, "herm")
+    ref = oracle_mod.thomas(a, b, c, d)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    L = cn.Layout.contiguous(n, 1, partition=T, rows_per_thread=M)
+    x = cn.solve(ta, tb, tc, td, layout=L)
+    assert rel(x.cpu().numpy(), ref) <= TOL
+
+
+def test_solve_in_place(gpu, oracle_mod):
+    torch, cn = gpu
+    n = 70_001
+    a, b, c, d = workloads.random_system(n, 5, "dd")
+    ref = oracle_mod.thomas(a, b, c, d)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    cn.solve(ta, tb, tc, td, out=td)
+    assert rel(td.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("n,batch", [(300, 37), (5000, 9), (4096, 70), (1, 5), (129, 64)])
+def test_solve_batched_contiguous(gpu, oracle_mod, n, batch):
+    torch, cn = gpu
+    log("batched", n, batch)
+    a, b, c, d = workloads.random_system(n * batch, 3 + n, "herm")
+    offs = np.arange(batch + 1) * n
+    ref = oracle_mod.thomas_batched(offs, a, b, c, d, nthreads=8)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x = cn.solve(ta, tb, tc, td, layout=cn.Layout.contiguous(n, batch))
+    assert rel(x.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("n,batch", [(777, 50), (4096, 64), (6000, 3)])
+def test_solve_interleaved(gpu, oracle_mod, n, batch):
+    torch, cn = gpu
+    log("interleaved", n, batch)
+    a, b, c, d = workloads.random_system(n * batch, 11, "dd")
+    # element (s, i) at i*batch + s: systems interleaved
+    A, B, C, D = (v.reshape(n, batch) for v in (a, b, c, d))
+    ref = np.empty((n, batch), np.complex128)
+    for s in range(batch):
+        ref[:, s] = oracle_mod.thomas(A[:, s], B[:, s], C[:, s], D[:, s])
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x = cn.solve(ta, tb, tc, td, layout=cn.Layout.interleaved(n, batch))
+    assert rel(x.cpu().numpy().reshape(n, batch), ref) <= TOL
+
+
+def test_solve_uneven_batch(gpu, oracle_mod):
+    torch, cn = gpu
+    g = np.random.default_rng(8)
+    lengths = np.concatenate([[1, 2, 4096, 4097, 0, 65_536], g.integers(1, 20_000, 40)])
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    a, b, c, d = workloads.random_system(int(offs[-1]), 21, "herm")
+    ref = oracle_mod.thomas_batched(offs, a, b, c, d, nthreads=8)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x = cn.solve(ta, tb, tc, td, layout=cn.Layout.uneven(offs))
+    assert rel(x.cpu().numpy(), ref) <= TOL
+
+
+def test_solve_is_deterministic(gpu):
+    torch, cn = gpu
+    n = 500_000
+    a, b, c, d = workloads.random_system(n, 2, "herm")
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x1 = cn.solve(ta, tb, tc, td)
+    x2 = cn.solve(ta, tb, tc, td)
+    assert torch.equal(x1, x2)
+
+
+def test_breakdown_flag(gpu):
+    torch, cn = gpu
+    n = 5000
+    a, b, c, d = workloads.random_system(n, 2, "dd")
+    a[1234] = 0.0
+    b[1234] = 0.0
+    c[1234] = 0.0  # exactly singular row
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    cn.solve(ta, tb, tc, td)
+    assert cn.get_status() == 1
+    assert cn.get_status() == 0  # the flag clears
+
+
+# ------------------------------------------------------------------ assembly, rhs, step
+@pytest.mark.parametrize("field", [False, True])
+def test_assemble_and_rhs(gpu, oracle_mod, field):
+    torch, cn = gpu
+    n, dx, dt = 3001, 0.07, 0.013
+    inp = workloads.random_cn(n, 4, dx, dt)
+    xg = workloads.grid_1d(n, dx) if field else None
+    E = 0.21 if field else 0.0
+    a0, b0, c0 = oracle_mod.cn_coeffs(inp["V"], dx, dt, xg, E)
+    d0 = oracle_mod.cn_rhs(inp["psi"], inp["V"], dx, dt, xg, E)
+    tV, tpsi = to_dev(torch, inp["V"], inp["psi"])
+    txg = to_dev(torch, xg)[0] if field else None
+    a, b, c = cn.assemble(tV, dx, dt, E=E, xgrid=txg)
+    d = cn.rhs(tpsi, tV, dx, dt, E=E, xgrid=txg)
+    for g, r in ((a, a0), (b, b0), (c, c0), (d, d0)):
+        assert rel(g.cpu().numpy(), r) <= 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 100, 4096, 4097, 65_536, 100_003, 1 << 20])
+def test_cn_step(gpu, oracle_mod, n):
+    torch, cn = gpu
+    log("cn_step", n)
+    inp = workloads.random_cn(n, 31 + n, 0.1, 0.02)
+    ref = oracle_mod.cn_step(inp["psi"], inp["V"], 0.1, 0.02)
+    tV, tpsi = to_dev(torch, inp["V"], inp["psi"])
+    out = cn.step(tpsi, tV, 0.1, 0.02)
+    assert rel(out.cpu().numpy(), ref) <= TOL
+    cn.step(tpsi, tV, 0.1, 0.02, out=tpsi)  # in place, multi-tile halos
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+
+
+def test_cn_step_field_and_scale(gpu, oracle_mod):
+    torch, cn = gpu
+    n, dx, dt, E = 200_000, 0.05, 0.01, 0.037
+    inp = workloads.random_cn(n, 9, dx, dt)
+    xg = workloads.grid_1d(n, dx)
+    ref = oracle_mod.cn_step(inp["psi"], 0.5 * inp["V"], dx, dt, xg, E)
+    tV, tpsi, txg = to_dev(torch, inp["V"], inp["psi"], xg)
+    out = cn.step(tpsi, tV, dx, dt, E=E, xgrid=txg, v_scale=0.5)
+    assert rel(out.cpu().numpy(), ref) <= TOL
+
+
+def test_plain_1d_one_solve_and_200_steps(gpu, oracle_mod):
+    """The plain 1D workload: one materialised solve, then 200 chained steps."""
+    torch, cn = gpu
+    w = workloads.plain_1d()
+    a0, b0, c0 = oracle_mod.cn_coeffs(w["V"], w["dx"], w["dt"])
+    d0 = oracle_mod.cn_rhs(w["psi0"], w["V"], w["dx"], w["dt"])
+    x0 = oracle_mod.thomas(a0, b0, c0, d0)
+    ref = oracle_mod.cn_propagate(w["psi0"], w["V"], w["dx"], w["dt"], w["steps"])
+    tV, tpsi = to_dev(torch, w["V"], w["psi0"])
+    a, b, c = cn.assemble(tV, w["dx"], w["dt"])
+    d = cn.rhs(tpsi, tV, w["dx"], w["dt"])
+    x = cn.solve(a, b, c, d)
+    assert rel(x.cpu().numpy(), x0) <= TOL
+    cn.propagate(tpsi, tV, w["dx"], w["dt"], w["steps"])
+    out = tpsi.cpu().numpy()
+    assert rel(out, ref) <= TOL
+    norm0 = np.sum(np.abs(w["psi0"]) ** 2) * w["dx"]
+    assert abs(np.sum(np.abs(out) ** 2) * w["dx"] - norm0) <= 1e-11
+
+
+def test_cn_step_uneven_batch(gpu, oracle_mod):
+    torch, cn = gpu
+    wl = workloads.uneven_batch(batch=300, hi=20_000, steps=1, seed=5)
+    ref = oracle_mod.cn_step_batched(wl["offsets"], wl["psi0"], wl["V"], wl["dx"], wl["dt"], 8)
+    tV, tpsi, tdx = to_dev(torch, wl["V"], wl["psi0"], wl["dx"])
+    out = cn.step(tpsi, tV, 0.0, wl["dt"], dx_per_system=tdx,
+                  layout=cn.Layout.uneven(wl["offsets"]))
+    assert rel(out.cpu().numpy(), ref) <= TOL
+
+
+def test_adi_step_small(gpu, oracle_mod):
+    """Lie-split ADI step: x-lines (contiguous) then y-lines (interleaved), V/2 each."""
+    torch, cn = gpu
+    w = workloads.adi_2d(n=256, steps=3)
+    ny, nx = w["psi0"].shape
+    ref = w["psi0"]
+    for _ in range(w["steps"]):
+        ref = oracle_mod.adi_step(ref, w["V"], w["dx"], w["dy"], w["dt"], 8)
+    tV, tpsi = to_dev(torch, w["V"].ravel(), w["psi0"].ravel())
+    Lx = cn.Layout.contiguous(nx, ny)
+    Ly = cn.Layout.interleaved(ny, nx)
+    for _ in range(w["steps"]):
+        cn.step(tpsi, tV, w["dx"], w["dt"], v_scale=0.5, out=tpsi, layout=Lx)
+        cn.step(tpsi, tV, w["dy"], w["dt"], v_scale=0.5, out=tpsi, layout=Ly)
+    assert rel(tpsi.cpu().numpy().reshape(ny, nx), ref) <= TOL
+
+
+# ------------------------------------------------------------------ adjoint
+@pytest.mark.parametrize("n", [7, 4096, 100_001])
+def test_solve_adjoint(gpu, oracle_mod, n):
+    torch, cn = gpu
+    a, b, c, d = workloads.random_system(n, 17, "dd")
+    g = np.random.default_rng(3)
+    G = g.standard_normal(n) + 1j * g.standard_normal(n)
+    x = oracle_mod.thomas(a, b, c, d)
+    lam, ga, gb, gc = oracle_mod.thomas_adjoint(a, b, c, x, G)
+    ta, tb, tc, tx, tG = to_dev(torch, a, b, c, x, G)
+    gd_, ga_, gb_, gc_ = cn.solve_adjoint(ta, tb, tc, tx, tG)
+    assert rel(gd_.cpu().numpy(), lam) <= TOL
+    assert rel(ga_.cpu().numpy(), ga) <= TOL
+    assert rel(gb_.cpu().numpy(), gb) <= TOL
+    assert rel(gc_.cpu().numpy(), gc) <= TOL
+
+
+@pytest.mark.parametrize("n", [50, 5000, 300_001])
+def test_step_adjoint(gpu, oracle_mod, n):
+    torch, cn = gpu
+    dx, dt, E = 0.05, 0.01, 0.02
+    inp = workloads.random_cn(n, 12, dx, dt)
+    xg = workloads.grid_1d(n, dx)
+    g = np.random.default_rng(4)
+    G1 = g.standard_normal(n) + 1j * g.standard_normal(n)
+    p1 = oracle_mod.cn_step(inp["psi"], inp["V"], dx, dt, xg, E)
+    g0, dV, dE = oracle_mod.cn_propagate_grad(inp["psi"], inp["V"], dx, dt, 1, G1, xg, [E])
+    tV, tp0, tp1, tG, txg = to_dev(torch, inp["V"], inp["psi"], p1, G1, xg)
+    tdV = torch.zeros(n, dtype=torch.float64, device="cuda")
+    tdE = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gn = cn.step_adjoint(tp0, tp1, tG, tV, dx, dt, E=E, xgrid=txg, dV=tdV, dE_out=tdE)
+    assert rel(gn.cpu().numpy(), g0) <= TOL
+    assert rel(tdV.cpu().numpy(), dV) <= TOL
+    assert abs(tdE.cpu().numpy()[0] - dE[0]) <= TOL * max(abs(dE[0]), 1e-300) + 1e-13
