@@ -71,14 +71,23 @@ int find_cfg(int64_t T, int M) {
 
 constexpr int64_t kSingleMax = 4096;  // largest tile that solves a whole system in one pass
 
+// XCD-contiguous order of whole-system workgroups (CN_XCD_REMAP=0 turns it off)
+bool xcd_remap_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_XCD_REMAP");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 // Workgroup configuration for a system that fits one tile: the smallest tile that holds it.
 int single_cfg(int64_t n) {
   if (n <= 128) return find_cfg(128, 2);
   if (n <= 256) return find_cfg(256, 4);
   if (n <= 512) return find_cfg(512, 4);
   if (n <= 1024) return find_cfg(1024, 4);
-  if (n <= 2048) return find_cfg(2048, 4);
-  return find_cfg(4096, 4);
+  if (n <= 2048) return find_cfg(2048, 8);
+  return find_cfg(4096, 8);
 }
 
 // ------------------------------------------------------------------------------- plans
@@ -153,7 +162,7 @@ int multi_cfg(int64_t n, int64_t batch, const Knobs& k, int level) {
   }
   // enough tiles to fill the chip (>= 4 workgroups per CU when the system allows it)
   const int64_t target = 1024;
-  int64_t T = 2048;
+  int64_t T = 1024;
   while (T > 256 && batch * ((n + T - 1) / T) < target) T /= 2;
   int M = (level == 1 && k.rpt > 0) ? k.rpt : 4;
   int ci = find_cfg(T, M);
@@ -195,14 +204,20 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   char line[256];
   if (!bd.uneven) {
     const int64_t n = bd.n, batch = bd.batch;
-    const bool fits = n <= kSingleMax && (batch >= 64 || n <= 1024 || level > 1);
-    if (fits) {
-      int ci = single_cfg(n);
+    int ci_single = -1;
+    if (level == 1 && kn.partition > 0) {
+      if (n <= kn.partition) ci_single = multi_cfg(n, batch, kn, level);
+    } else if (n <= kSingleMax && (batch >= 64 || n <= 1024 || level > 1)) {
+      ci_single = single_cfg(n);
+    }
+    if (ci_single >= 0) {
+      const int ci = ci_single;
       KArgs a = base;
       a.n = n;
       a.ntiles = 1;
       a.es = bd.es;
       a.bs = bd.bs;
+      a.xcd_remap = xcd_remap_enabled() ? 1 : 0;
       add_launch(L, ci, src, nsd::PH_SINGLE, dim3(1, (unsigned)batch), level, a);
       set_common(L.back());
       snprintf(line, sizeof(line), "L%d single %s n=%lld batch=%lld; ", level, cfg_str(ci).c_str(),

@@ -157,8 +157,7 @@ __device__ __forceinline__ int xmove(int v) {
   } else if constexpr (m == 2) {
     return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
   } else if constexpr (m == 4) {
-    int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror: i ^ 7
-    return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false);    // quad_perm [3,2,1,0]: i ^ 3
+    return __builtin_amdgcn_ds_swizzle(v, 0x101F);  // bitmask mode, xor 0x04 within 32 lanes
   } else if constexpr (m == 8) {
     return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);  // row_ror:8
   } else if constexpr (m == 16) {
@@ -185,10 +184,12 @@ __device__ __forceinline__ cd xmove(cd v) {
 //          psi_K + B psi_J + C psi_M = dl
 //   JU at J: r = -UC_L: UA += r B; UC = r C; UD += r dl
 //   JD at M: r = -DB_R: DB = r B;  DA += r C; DD += r dl
-// The pair is held by two lanes; both compute the scaled row K, then the lane of L keeps the
-// merged block and the lane of R keeps the node for SS.
+// At level s the lanes with the low s bits clear take part: lane x (bit s clear) holds L and
+// lane x + 2^s holds R.  The lane of L receives R, keeps the merged block and stores the
+// scaled row K in LDS slot x + 2^s (read back by the same lane in SS).  The other lanes
+// compute the same formulas on data that is no longer needed.
 template <int m>
-__device__ __forceinline__ void tree_level_up(Blk& b, Node& nd, bool right, bool active) {
+__device__ __forceinline__ void tree_level_up(Blk& b, Node* nodes, int lane) {
   Blk o;
   o.UA = xmove<m>(b.UA);
   o.UC = xmove<m>(b.UC);
@@ -196,70 +197,60 @@ __device__ __forceinline__ void tree_level_up(Blk& b, Node& nd, bool right, bool
   o.DB = xmove<m>(b.DB);
   o.DA = xmove<m>(b.DA);
   o.DD = xmove<m>(b.DD);
-  const cd LDA = csel(right, o.DA, b.DA), RUA = csel(right, b.UA, o.UA);
-  const cd LDD = csel(right, o.DD, b.DD), RUD = csel(right, b.UD, o.UD);
-  const cd LDB = csel(right, o.DB, b.DB), RUC = csel(right, b.UC, o.UC);
-  const cd ia = crecip(cadd(LDA, RUA));
+  const cd ia = crecip(cadd(b.DA, o.UA));
   Node t;
-  t.B = cmul(LDB, ia);
-  t.C = cmul(RUC, ia);
-  t.dl = cmul(cadd(LDD, RUD), ia);
-  if (active) {
-    if (right) {
-      nd = t;
-    } else {
-      // b is L, o is R
-      const cd rU = b.UC;
-      const cd rD = o.DB;
-      b.UA = cfms(rU, t.B, b.UA);
-      b.UD = cfms(rU, t.dl, b.UD);
-      b.UC = cneg(cmul(rU, t.C));
-      b.DB = cneg(cmul(rD, t.B));
-      b.DA = cfms(rD, t.C, o.DA);
-      b.DD = cfms(rD, t.dl, o.DD);
-    }
-  }
+  t.B = cmul(b.DB, ia);
+  t.C = cmul(o.UC, ia);
+  t.dl = cmul(cadd(b.DD, o.UD), ia);
+  if ((lane & (2 * m - 1)) == 0) nodes[lane + m] = t;
+  const cd rU = b.UC;
+  const cd rD = o.DB;
+  b.UA = cfms(rU, t.B, b.UA);
+  b.UD = cfms(rU, t.dl, b.UD);
+  b.UC = cneg(cmul(rU, t.C));
+  b.DB = cneg(cmul(rD, t.B));
+  b.DA = cfms(rD, t.C, o.DA);
+  b.DD = cfms(rD, t.dl, o.DD);
 }
 
 // Binary nesting over 2^LEVELS consecutive lanes: afterwards the lane with the low LEVELS bits
-// clear holds the merged block and every other lane the node of the joint line it owns.
+// clear holds the merged block; the nodes of the eliminated joint lines are in `nodes`.
 template <int LEVELS>
-__device__ __forceinline__ void tree_up(Blk& b, Node& nd, int lane) {
-  if constexpr (LEVELS > 0) tree_level_up<1>(b, nd, (lane & 1) != 0, true);
-  if constexpr (LEVELS > 1) tree_level_up<2>(b, nd, (lane & 2) != 0, (lane & 1) == 0);
-  if constexpr (LEVELS > 2) tree_level_up<4>(b, nd, (lane & 4) != 0, (lane & 3) == 0);
-  if constexpr (LEVELS > 3) tree_level_up<8>(b, nd, (lane & 8) != 0, (lane & 7) == 0);
-  if constexpr (LEVELS > 4) tree_level_up<16>(b, nd, (lane & 16) != 0, (lane & 15) == 0);
-  if constexpr (LEVELS > 5) tree_level_up<32>(b, nd, (lane & 32) != 0, (lane & 31) == 0);
+__device__ __forceinline__ void tree_up(Blk& b, Node* nodes, int lane) {
+  if constexpr (LEVELS > 0) tree_level_up<1>(b, nodes, lane);
+  if constexpr (LEVELS > 1) tree_level_up<2>(b, nodes, lane);
+  if constexpr (LEVELS > 2) tree_level_up<4>(b, nodes, lane);
+  if constexpr (LEVELS > 3) tree_level_up<8>(b, nodes, lane);
+  if constexpr (LEVELS > 4) tree_level_up<16>(b, nodes, lane);
+  if constexpr (LEVELS > 5) tree_level_up<32>(b, nodes, lane);
 }
 
+// SS at level s: the lane of L knows (psi_J, psi_M), computes psi_K and hands (psi_K, psi_M)
+// to the lane of R.
 template <int m>
-__device__ __forceinline__ void tree_level_down(cd& pJ, cd& pM, const Node& nd, bool right,
-                                                bool active) {
-  const cd oJ = xmove<m>(pJ);
+__device__ __forceinline__ void tree_level_down(cd& pJ, cd& pM, const Node* nodes, int lane) {
+  const Node t = nodes[(lane + m) & 63];
+  const cd pK = cfms(t.C, pM, cfms(t.B, pJ, t.dl));
+  const cd oK = xmove<m>(pK);
   const cd oM = xmove<m>(pM);
-  const cd pK = cfms(nd.C, oM, cfms(nd.B, oJ, nd.dl));
-  const cd back = xmove<m>(pK);
-  if (active) {
-    if (right) {
-      pJ = pK;
-      pM = oM;
-    } else {
-      pM = back;
-    }
+  const int low = lane & (2 * m - 1);
+  if (low == m) {
+    pJ = oK;
+    pM = oM;
   }
+  if (low == 0) pM = pK;
 }
 
 // SS down the binary nesting: on entry the group's first lane holds (psi_J, psi_M) of the whole
 // span; on exit every lane holds psi at its own joint line (pJ) and at the next one (pM).
 template <int LEVELS>
-__device__ __forceinline__ void tree_down(cd& pJ, cd& pM, const Node& nd, int lane) {
-  if constexpr (LEVELS > 5) tree_level_down<32>(pJ, pM, nd, (lane & 32) != 0, (lane & 31) == 0);
-  if constexpr (LEVELS > 4) tree_level_down<16>(pJ, pM, nd, (lane & 16) != 0, (lane & 15) == 0);
-  if constexpr (LEVELS > 3) tree_level_down<8>(pJ, pM, nd, (lane & 8) != 0, (lane & 7) == 0);
-  if constexpr (LEVELS > 2) tree_level_down<4>(pJ, pM, nd, (lane & 4) != 0, (lane & 3) == 0);
-  if constexpr (LEVELS > 1) tree_level_down<2>(pJ, pM, nd, (lane & 2) != 0, (lane & 1) == 0);
-  if constexpr (LEVELS > 0) tree_level_down<1>(pJ, pM, nd, (lane & 1) != 0, true);
+__device__ __forceinline__ void tree_down(cd& pJ, cd& pM, const Node* nodes, int lane) {
+  if constexpr (LEVELS > 5) tree_level_down<32>(pJ, pM, nodes, lane);
+  if constexpr (LEVELS > 4) tree_level_down<16>(pJ, pM, nodes, lane);
+  if constexpr (LEVELS > 3) tree_level_down<8>(pJ, pM, nodes, lane);
+  if constexpr (LEVELS > 2) tree_level_down<4>(pJ, pM, nodes, lane);
+  if constexpr (LEVELS > 1) tree_level_down<2>(pJ, pM, nodes, lane);
+  if constexpr (LEVELS > 0) tree_level_down<1>(pJ, pM, nodes, lane);
 }
 
 // ------------------------------------------------------------------ LDS staging per wavefront

@@ -47,6 +47,7 @@ struct KArgs {
   cd* halo_out;           // first and last state row of each tile (pass 1)
   const cd* halo_in;
   int* status;
+  int xcd_remap;          // uniform single-tile launches: XCD-contiguous system order
 };
 
 struct Geo {
@@ -58,6 +59,12 @@ __device__ __forceinline__ Geo geometry(const KArgs& A) {
   if (A.wg_sys) {
     g.sys = A.wg_sys[blockIdx.x];
     g.tile = A.wg_tile[blockIdx.x];
+  } else if (A.xcd_remap && gridDim.x == 1) {
+    // Workgroups are handed to the 8 XCDs round-robin by linear id; give each XCD a contiguous
+    // range of systems so that neighbouring (interleaved) systems share its L2.
+    const int64_t B = gridDim.y, id = blockIdx.y, x = id & 7, q = B >> 3, r = B & 7;
+    g.sys = x * q + (x < r ? x : r) + (id >> 3);
+    g.tile = 0;
   } else {
     g.sys = blockIdx.y;
     g.tile = blockIdx.x;
@@ -280,6 +287,8 @@ __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
   __shared__ cd lds[W][S::QS];
   __shared__ Blk wblk[W];
   __shared__ cd wpsi[W][2];
+  __shared__ Node xnode[64];
+  static_assert(sizeof(cd) * Stage<M>::QS >= sizeof(Node) * 64, "node slots fit the stage buffer");
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -301,15 +310,16 @@ __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
 
   Blk blk;
   reduce_block<M>(Ar, Br, Cr, Dr, bK, blk);
-  Node nd;
-  tree_up<6>(blk, nd, lane);
-  Node ndw;
+  // the staging buffer is idle between the loads and the stores: it holds the nodes
+  Node* wnode = reinterpret_cast<Node*>(buf);
+  wave_sync();
+  tree_up<6>(blk, wnode, lane);
   if constexpr (W > 1) {
     if (lane == 0) wblk[wave] = blk;
     __syncthreads();
     if (wave == 0) {
       blk = wblk[lane & (W - 1)];
-      tree_up<LW>(blk, ndw, lane);
+      tree_up<LW>(blk, xnode, lane);
     }
   }
 
@@ -340,7 +350,7 @@ __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
 
   if constexpr (W > 1) {
     if (wave == 0) {
-      tree_down<LW>(pJ, pM, ndw, lane);
+      tree_down<LW>(pJ, pM, xnode, lane);
       if (lane < W) {
         wpsi[lane][0] = pJ;
         wpsi[lane][1] = pM;
@@ -350,7 +360,7 @@ __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
     pJ = wpsi[wave][0];
     pM = wpsi[wave][1];
   }
-  tree_down<6>(pJ, pM, nd, lane);
+  tree_down<6>(pJ, pM, wnode, lane);
 
   cd xo[M];
   ss_block<M>(Br, Cr, Dr, pJ, pM, xo);
