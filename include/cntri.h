@@ -69,7 +69,7 @@ typedef struct {
   const int64_t* offsets;
   int32_t partition;       /* rows per first-level partition (one workgroup tile); a power
                               of two in [64, 16384]; 0 = automatic                         */
-  int32_t rows_per_thread; /* rows per innermost block (4 or 8); 0 = automatic             */
+  int32_t rows_per_thread; /* rows per innermost block (2, 4 or 8); 0 = automatic          */
 } cn_layout;
 
 /* Crank-Nicolson operator of Sec. 2, Eqs. (2)-(4) on a uniform grid with Dirichlet walls:
@@ -126,7 +126,7 @@ cn_status cn_rhs(cn_handle_t handle, const cn_layout* layout, const cn_operator*
 cn_status cn_step(cn_handle_t handle, const cn_layout* layout, const cn_operator* op, double E,
                   const void* psi_in, void* psi_out, cn_stream_t stream);
 
-/* nsteps chained cn_step calls in place on psi.  E: DEVICE-free HOST array of nsteps field
+/* nsteps chained cn_step calls in place on psi.  E: HOST array of nsteps field
  * values, or NULL for no field.  If ckpt is non-NULL, the state before step k is copied to
  * ckpt + (k / K) * (rows of the layout) for every k divisible by K (K >= 1). */
 cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_operator* op,
@@ -143,6 +143,17 @@ cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_ope
 cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_operator* op,
                           double E, const void* psi_n, const void* psi_np1, const void* g_np1,
                           void* g_n, double* dV_accum, double* dE_partial, cn_stream_t stream);
+
+/* Autotuner: times the candidate tile configurations (rows per first-level partition and per
+ * innermost block) of this layout on the caller's data and keeps the fastest for later calls
+ * with the same layout whose partition and rows_per_thread are 0.  cn_mode = 0 times
+ * cn_tridiag_solve(a, b, c, d -> x); cn_mode = 1 times cn_step(op, E, psi_in = d -> psi_out = x)
+ * and ignores a, b, c.  x is overwritten and must not alias d.  A text report of the median
+ * timings is written to report (may be NULL).  Not allowed during graph capture. */
+cn_status cn_autotune(cn_handle_t handle, const cn_layout* layout, int cn_mode,
+                      const cn_operator* op, double E, const void* a, const void* b,
+                      const void* c, const void* d, void* x, char* report, int64_t report_len,
+                      cn_stream_t stream);
 
 /* Synchronises the stream, returns CN_NUMERICAL_BREAKDOWN if any kernel of this handle met a
  * non-finite result since the last call (and clears the flag), else CN_OK. */

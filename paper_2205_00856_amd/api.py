@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import CnLayout, CnOperator, check
 
 __all__ = ["Layout", "Handle", "handle", "solve", "solve_adjoint", "assemble", "rhs", "step",
-           "propagate", "step_adjoint", "get_status", "describe_plan", "reserve"]
+           "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune"]
 
 
 @dataclass
@@ -308,3 +308,29 @@ def get_status(device=None) -> int:
     dev = torch.device("cuda", h.device)
     return check(_lib.lib().cn_get_status(h.ptr, ctypes.c_void_p(
         torch.cuda.current_stream(dev).cuda_stream)), "cn_get_status")
+
+
+def autotune(layout: Layout, d, x, a=None, b=None, c=None, V=None, dx=1.0, dt=0.0, E=0.0,
+             xgrid=None, v_scale=1.0, dx_per_system=None) -> str:
+    """cn_autotune: time the candidate tiles on these buffers (cn_step if V is given, else
+    cn_tridiag_solve) and keep the fastest for later calls with this layout.  x is
+    overwritten.  Returns the timing report."""
+    cn_mode = V is not None
+    span = layout.span()
+    _need(d, torch.complex128, "d/psi", span)
+    _need(x, torch.complex128, "x", span)
+    op = None
+    if cn_mode:
+        _check_op(layout, V, xgrid, dx_per_system)
+        op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    else:
+        for t, nm in ((a, "a"), (b, "b"), (c, "c")):
+            _need(t, torch.complex128, nm, span)
+    h = handle(d.device.index)
+    Lc = layout.c()
+    buf = ctypes.create_string_buffer(8192)
+    check(_lib.lib().cn_autotune(h.ptr, ctypes.byref(Lc), int(cn_mode),
+                                 ctypes.byref(op) if op is not None else None, float(E), _ptr(a),
+                                 _ptr(b), _ptr(c), _ptr(d), _ptr(x), buf, 8192, _stream(d)),
+          "cn_autotune")
+    return buf.value.decode()

@@ -63,6 +63,24 @@ struct KernTableInit {
   }
 } g_kern_init;
 
+// persistent whole-system kernels (uneven batches)
+const void* g_pers[kNumCfg][3];
+template <int M, int W>
+void reg_pers(int ci) {
+  g_pers[ci][nsd::SRC_EXPL] = (const void*)&nsd::k_system<M, W, nsd::SRC_EXPL>;
+  g_pers[ci][nsd::SRC_EXPL_CT] = (const void*)&nsd::k_system<M, W, nsd::SRC_EXPL_CT>;
+  g_pers[ci][nsd::SRC_CN] = (const void*)&nsd::k_system<M, W, nsd::SRC_CN>;
+}
+struct PersTableInit {
+  PersTableInit() {
+    reg_pers<4, 2>(2);
+    reg_pers<4, 4>(3);
+    reg_pers<4, 8>(4);
+    reg_pers<8, 2>(7);
+    reg_pers<8, 4>(8);
+  }
+} g_pers_init;
+
 int find_cfg(int64_t T, int M) {
   for (int i = 0; i < kNumCfg; ++i)
     if (kCfgs[i].T() == T && kCfgs[i].M == M) return i;
@@ -101,7 +119,7 @@ struct Launch {
   int level;  // 1 = the caller's system
   int src, ph, cfg;
   // table offsets (bytes into plan tables) or -1
-  int64_t t_offs = -1, t_tbase = -1, t_wgs = -1, t_wgt = -1;
+  int64_t t_offs = -1, t_tbase = -1, t_wgs = -1, t_wgt = -1, t_queue = -1;
   // workspace offsets (bytes) or -1
   int64_t o_sU = -1, o_sD = -1, o_oU = -1, o_oD = -1, o_x = -1, o_psi_if = -1, o_hout = -1,
           o_hin = -1;
@@ -144,6 +162,16 @@ struct Builder {
     return (int64_t)off;
   }
 };
+
+int num_cus() {
+  static int cus = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return v > 0 ? v : 256;
+  }();
+  return cus;
+}
 
 struct BatchDesc {
   bool uneven = false;
@@ -256,14 +284,74 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     L.back().o_hin = oH;
     return;
   }
-  // uneven batch: small systems by bucket (one pass), large ones in tiles
+  // uneven batch
   const int64_t batch = bd.batch;
   const int64_t t_offs = B.add_tab(bd.offs.data(), (batch + 1) * sizeof(int64_t));
+  int64_t handled = 0;  // systems up to this length went to the persistent launch
+  if (level == 1 && src != nsd::SRC_SLOTS) {
+    // one persistent launch: whole systems from a device queue, longest first
+    int ci = -1;
+    if (kn.partition > 0) {
+      ci = find_cfg(kn.partition, kn.rpt > 0 ? kn.rpt : 4);
+      if (ci >= 0 && !g_pers[ci][src]) ci = -1;
+    }
+    if (ci < 0) ci = find_cfg(1024, 4);
+    const int64_t T = kCfgs[ci].T();
+    handled = nsd::kMaxSysTiles * T;
+    std::vector<int> sys;
+    BatchDesc rest;
+    rest.uneven = true;
+    rest.batch = batch;
+    rest.offs.assign(batch + 1, 0);
+    int64_t rest_rows = 0;
+    for (int64_t s = 0; s < batch; ++s) {
+      const int64_t len = bd.offs[s + 1] - bd.offs[s];
+      if (len > 0 && len <= nsd::kMaxSysTiles * T) sys.push_back((int)s);
+    }
+    std::stable_sort(sys.begin(), sys.end(), [&](int p, int q) {
+      return bd.offs[p + 1] - bd.offs[p] > bd.offs[q + 1] - bd.offs[q];
+    });
+    if (!sys.empty()) {
+      int per_cu = 1;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g_pers[ci][src], 64 * kCfgs[ci].W,
+                                                       0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+      const int64_t grid = std::min<int64_t>((int64_t)per_cu * num_cus(), (int64_t)sys.size());
+      Launch l;
+      l.fn = g_pers[ci][src];
+      l.grid = dim3((unsigned)grid);
+      l.threads = 64 * kCfgs[ci].W;
+      l.a = base;
+      l.a.nitems = (int)sys.size();
+      l.level = level;
+      l.src = src;
+      l.ph = -1;
+      l.cfg = ci;
+      l.t_offs = t_offs;
+      l.t_wgs = B.add_tab(sys.data(), sys.size() * sizeof(int));
+      const int zero2[2] = {0, 0};
+      l.t_queue = B.add_tab(zero2, sizeof(zero2));
+      L.push_back(l);
+      set_common(L.back());
+      snprintf(line, sizeof(line), "L%d persistent %s systems=%zu grid=%lld; ", level,
+               cfg_str(ci).c_str(), sys.size(), (long long)grid);
+      B.desc += line;
+    }
+    // systems longer than the in-workgroup limit go through the multi-workgroup path
+    bool any_long = false;
+    for (int64_t s = 0; s < batch; ++s) {
+      const int64_t len = bd.offs[s + 1] - bd.offs[s];
+      rest.offs[s + 1] = rest.offs[s];
+      if (len > nsd::kMaxSysTiles * T) any_long = true;
+    }
+    if (!any_long) return;
+    (void)rest_rows;
+  }
   std::map<int, std::vector<int>> buckets;
   std::vector<int> large;
   for (int64_t s = 0; s < batch; ++s) {
     const int64_t len = bd.offs[s + 1] - bd.offs[s];
-    if (len <= 0) continue;
+    if (len <= 0 || len <= handled) continue;
     if (len <= kSingleMax) {
       buckets[single_cfg(len)].push_back((int)s);
     } else {
@@ -356,6 +444,7 @@ struct cn_handle_s {
   size_t ws_size = 0;
   int* status = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> plans;
+  std::map<std::string, std::string> tuned;  // automatic layout key -> key of the tuned plan
 };
 
 namespace {
@@ -419,7 +508,11 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
   int64_t rows = 0, span = 0;
   cn_status st = validate(L, rows, span);
   if (st != CN_OK) return st;
-  const std::string key = plan_key(L, src);
+  std::string key = plan_key(L, src);
+  {
+    auto tk = h->tuned.find(key);
+    if (tk != h->tuned.end() && h->plans.count(tk->second)) key = tk->second;
+  }
   auto it = h->plans.find(key);
   const bool cap = s != nullptr ? capturing(s) : false;
   if (it == h->plans.end()) {
@@ -468,6 +561,7 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
       if (l.t_tbase >= 0) l.a.tbase = (const int64_t*)(tb + l.t_tbase);
       if (l.t_wgs >= 0) l.a.wg_sys = (const int*)(tb + l.t_wgs);
       if (l.t_wgt >= 0) l.a.wg_tile = (const int*)(tb + l.t_wgt);
+      if (l.t_queue >= 0) l.a.queue = (int*)(tb + l.t_queue);
     }
     it = h->plans.emplace(key, std::move(P)).first;
   }
@@ -843,6 +937,85 @@ cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* 
                        (int64_t)((P->rows + 255) / 256), dE_partial);
     if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
   }
+  return CN_OK;
+}
+
+cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_operator* op,
+                      double E, const void* a, const void* b, const void* c, const void* d,
+                      void* x, char* report, int64_t report_len, cn_stream_t stream) {
+  if (!h || !L || !d || !x || d == x) return CN_ERR_INVALID_ARG;
+  if (cn_mode && check_op(op) != CN_OK) return CN_ERR_INVALID_ARG;
+  if (!cn_mode && (!a || !b || !c)) return CN_ERR_INVALID_ARG;
+  if (L->partition != 0 || L->rows_per_thread != 0) return CN_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (capturing(s)) return CN_ERR_NOT_RESERVED;
+  const int src = cn_mode ? nsd::SRC_CN : nsd::SRC_EXPL;
+  struct Cand {
+    int T, M;
+  };
+  const Cand cands[] = {{128, 2}, {256, 4}, {512, 4}, {1024, 4}, {2048, 4}, {4096, 4},
+                        {512, 8}, {1024, 8}, {2048, 8}, {4096, 8}};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::string rep;
+  float best = 1e30f;
+  std::string best_key;
+  for (const Cand& cd_ : cands) {
+    cn_layout L2 = *L;
+    L2.partition = cd_.T;
+    L2.rows_per_thread = cd_.M;
+    if (L->offsets) {  // persistent launch: only the configurations it is built for
+      const int ci = find_cfg(cd_.T, cd_.M);
+      if (ci < 0 || !g_pers[ci][src]) continue;
+    }
+    Plan* P = nullptr;
+    if (get_plan(h, &L2, src, s, &P) != CN_OK) continue;
+    UserArgs u;
+    if (cn_mode) {
+      u.psi = (const cd*)d;
+      u.V = op->V;
+      u.xg = op->xgrid;
+      u.dxs = op->dx_per_system;
+      u.vscale = op->v_scale;
+      u.E_mat = u.E_rhs = E;
+      u.dx = op->dx;
+      u.dt = op->dt;
+    } else {
+      u.a = (const cd*)a;
+      u.b = (const cd*)b;
+      u.c = (const cd*)c;
+      u.d = (const cd*)d;
+    }
+    u.x = (cd*)x;
+    std::vector<float> ts;
+    bool ok = true;
+    for (int r = 0; r < 7 && ok; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess) ok = false;
+      if (ok && run_plan(h, P, u, s) != CN_OK) ok = false;
+      if (ok && hipEventRecord(e1, s) != hipSuccess) ok = false;
+      if (ok && hipEventSynchronize(e1) != hipSuccess) ok = false;
+      float ms = 0.f;
+      if (ok && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ok = false;
+      if (ok && r >= 2) ts.push_back(ms);
+    }
+    if (!ok) continue;
+    std::sort(ts.begin(), ts.end());
+    const float med = ts[ts.size() / 2];
+    char line[160];
+    snprintf(line, sizeof(line), "T=%d M=%d: %.4f ms; ", cd_.T, cd_.M, med);
+    rep += line;
+    if (med < best) {
+      best = med;
+      best_key = plan_key(&L2, src);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_key.empty()) return CN_ERR_UNSUPPORTED;
+  h->tuned[plan_key(L, src)] = best_key;
+  rep += "chosen: " + h->plans[best_key]->desc;
+  if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
   return CN_OK;
 }
 

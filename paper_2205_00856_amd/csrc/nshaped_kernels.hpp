@@ -48,6 +48,8 @@ struct KArgs {
   const cd* halo_in;
   int* status;
   int xcd_remap;          // uniform single-tile launches: XCD-contiguous system order
+  int* queue;             // persistent launch: [next item, workgroups done]
+  int nitems;             // persistent launch: number of systems in wg_sys
 };
 
 struct Geo {
@@ -278,25 +280,31 @@ struct Log2<1> {
   static constexpr int v = 0;
 };
 
-// One workgroup = one tile of T = 64*W*M rows of one system.
+template <int M, int W>
+struct TileSmem {
+  cd lds[W][Stage<M>::QS];  // per-wavefront staging buffer; holds the tree nodes in between
+  Blk wblk[W];
+  cd wpsi[W][2];
+  Node xnode[64];
+};
+
+// One tile of T = 64*W*M rows of one system, run by every thread of the workgroup.
+//   PH_SINGLE  the tile holds the whole system: RS on its two joint lines, then SS
+//   PH_REDUCE  writes the tile's U/D slots at index G.gt of oU/oD (and, for the CN source,
+//              its first and last state row to halo_out)
+//   PH_SUBST   takes psi at the tile's joint lines from psi_if[G.gt], psi_if[G.gt + 1]
 template <int M, int W, int SRC, int PH>
-__global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
-  using S = Stage<M>;
+__device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<M, W>& sm) {
   constexpr int LW = Log2<W>::v;
   constexpr int64_t T = 64 * W * M;
-  __shared__ cd lds[W][S::QS];
-  __shared__ Blk wblk[W];
-  __shared__ cd wpsi[W][2];
-  __shared__ Node xnode[64];
   static_assert(sizeof(cd) * Stage<M>::QS >= sizeof(Node) * 64, "node slots fit the stage buffer");
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const Geo G = geometry(A);
   const int64_t t0 = G.tile * T;
   const int64_t w0 = t0 + (int64_t)wave * 64 * M;
   const int64_t J = w0 + (int64_t)lane * M;
-  cd* buf = lds[wave];
+  cd* buf = sm.lds[wave];
 
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
   load_rows<M, W, SRC, PH>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
@@ -315,11 +323,11 @@ __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
   wave_sync();
   tree_up<6>(blk, wnode, lane);
   if constexpr (W > 1) {
-    if (lane == 0) wblk[wave] = blk;
+    if (lane == 0) sm.wblk[wave] = blk;
     __syncthreads();
     if (wave == 0) {
-      blk = wblk[lane & (W - 1)];
-      tree_up<LW>(blk, xnode, lane);
+      blk = sm.wblk[lane & (W - 1)];
+      tree_up<LW>(blk, sm.xnode, lane);
     }
   }
 
@@ -346,36 +354,146 @@ __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
       pM = csel(G.tile + 1 < G.ntile, nxt, czero());
     }
   }
-  if constexpr (PH == PH_REDUCE) return;
+  if constexpr (PH != PH_REDUCE) {
+    if constexpr (W > 1) {
+      if (wave == 0) {
+        tree_down<LW>(pJ, pM, sm.xnode, lane);
+        if (lane < W) {
+          sm.wpsi[lane][0] = pJ;
+          sm.wpsi[lane][1] = pM;
+        }
+      }
+      __syncthreads();
+      pJ = sm.wpsi[wave][0];
+      pM = sm.wpsi[wave][1];
+    }
+    tree_down<6>(pJ, pM, wnode, lane);
 
-  if constexpr (W > 1) {
-    if (wave == 0) {
-      tree_down<LW>(pJ, pM, xnode, lane);
-      if (lane < W) {
-        wpsi[lane][0] = pJ;
-        wpsi[lane][1] = pM;
+    cd xo[M];
+    ss_block<M>(Br, Cr, Dr, pJ, pM, xo);
+
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < M; ++j) bad |= (J + j < G.n) && !cfinite(xo[j]);
+    if (__any(bad) && lane == 0) atomicOr(A.status, 1);
+
+    if constexpr (SRC == SRC_SLOTS) {
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        if (J + j < G.n) A.x[G.base + J + j] = xo[j];
+    } else {
+      stage_out<M>(buf, A.x + G.base, G.es, w0, G.n, lane, xo);
+    }
+  }
+}
+
+// One workgroup = one tile of T = 64*W*M rows of one system.
+template <int M, int W, int SRC, int PH>
+__global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
+  __shared__ TileSmem<M, W> sm;
+  const Geo G = geometry(A);
+  tile_run<M, W, SRC, PH>(A, G, sm);
+}
+
+// Reduced system on the joint lines of a system's tiles (K <= 64 rows, from the two slot
+// arrays), solved by wavefront 0: lane k holds row k as a block without interior rows; the
+// binary nesting reduces it to the RS stage on rows 0 and 64 (virtual) and SS gives psi at
+// every tile joint.
+__device__ __forceinline__ void interface_solve_wave(const cd* sU, const cd* sD, cd* spsi, int K,
+                                                     int lane, Node* nodes) {
+  const bool ok = lane < K;
+  const int k = ok ? lane : 0;
+  const cd zero = czero();
+  cd a = sU[3 * k], c = sU[3 * k + 1], d = sU[3 * k + 2];
+  const int kp = k > 0 ? k - 1 : 0;
+  const cd da = sD[3 * kp + 1], dd = sD[3 * kp + 2];
+  a = csel(k > 0, cadd(a, da), a);
+  d = csel(k > 0, cadd(d, dd), d);
+  const cd bn = sD[3 * k];  // sub-diagonal of row k+1
+  Blk b;
+  b.UA = csel(ok, a, mk(1.0, 0.0));
+  b.UC = csel(lane < K - 1, c, zero);
+  b.UD = csel(ok, d, zero);
+  b.DB = csel(lane < K - 1, bn, zero);
+  b.DA = zero;
+  b.DD = zero;
+  tree_up<6>(b, nodes, lane);
+  cd pJ = zero, pM = zero;
+  if (lane == 0) {
+    cd ia0 = crecip(b.UA);
+    cd r = cneg(cmul(b.DB, ia0));
+    cd aT = cfma(r, b.UC, cadd(mk(1.0, 0.0), b.DA));
+    cd dT = cfma(r, b.UD, b.DD);
+    pM = cmul(dT, crecip(aT));
+    pJ = cmul(cfms(b.UC, pM, b.UD), ia0);
+  }
+  tree_down<6>(pJ, pM, nodes, lane);
+  if (ok) spsi[lane] = pJ;
+}
+
+constexpr int kMaxSysTiles = 64;
+
+// Persistent launch over an uneven batch: every workgroup takes whole systems from a device
+// queue (longest first, the host's order).  A system of at most one tile is solved in one
+// pass; a longer one is streamed tile by tile inside the workgroup: reduce every tile (slots
+// and edge states kept in LDS), solve the reduced system on the tile joints, then re-read each
+// tile and substitute.  The last workgroup to leave resets the queue for the next launch.
+template <int M, int W, int SRC>
+__global__ __launch_bounds__(64 * W) void k_system(KArgs A) {
+  constexpr int64_t T = 64 * W * M;
+  __shared__ TileSmem<M, W> sm;
+  __shared__ cd sU[3 * kMaxSysTiles], sD[3 * kMaxSysTiles], spsi[kMaxSysTiles],
+      shalo[2 * kMaxSysTiles];
+  __shared__ int item_s;
+  KArgs B = A;
+  B.oU = sU;
+  B.oD = sD;
+  B.psi_if = spsi;
+  B.halo_out = shalo;
+  B.halo_in = shalo;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(A.queue, 1);
+    __syncthreads();
+    const int item = item_s;
+    __syncthreads();
+    if (item >= A.nitems) break;
+    Geo G;
+    G.sys = A.wg_sys[item];
+    G.base = A.offs[G.sys];
+    G.n = A.offs[G.sys + 1] - G.base;
+    G.es = 1;
+    const int64_t K = (G.n + T - 1) / T;
+    if (K <= 1) {
+      G.tile = 0;
+      G.gt = 0;
+      G.ntile = 1;
+      tile_run<M, W, SRC, PH_SINGLE>(A, G, sm);
+    } else {
+      G.ntile = K;
+      for (int64_t t = 0; t < K; ++t) {
+        G.tile = t;
+        G.gt = t;
+        tile_run<M, W, SRC, PH_REDUCE>(B, G, sm);
+      }
+      __syncthreads();
+      if (wave == 0) interface_solve_wave(sU, sD, spsi, (int)K, lane, sm.xnode);
+      __syncthreads();
+      for (int64_t t = 0; t < K; ++t) {
+        G.tile = t;
+        G.gt = t;
+        tile_run<M, W, SRC, PH_SUBST>(B, G, sm);
       }
     }
     __syncthreads();
-    pJ = wpsi[wave][0];
-    pM = wpsi[wave][1];
   }
-  tree_down<6>(pJ, pM, wnode, lane);
-
-  cd xo[M];
-  ss_block<M>(Br, Cr, Dr, pJ, pM, xo);
-
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < M; ++j) bad |= (J + j < G.n) && !cfinite(xo[j]);
-  if (__any(bad) && lane == 0) atomicOr(A.status, 1);
-
-  if constexpr (SRC == SRC_SLOTS) {
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-      if (J + j < G.n) A.x[G.base + J + j] = xo[j];
-  } else {
-    stage_out<M>(buf, A.x + G.base, G.es, w0, G.n, lane, xo);
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(A.queue + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(A.queue, 0);
+      atomicExch(A.queue + 1, 0);
+    }
   }
 }
 

@@ -304,3 +304,65 @@ def test_graph_captured_adi_step_replays(gpu, oracle_mod):
         step(junk)  # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(psi, eager)
+
+
+# ------------------------------------------------------------------ persistent uneven launch
+def test_uneven_persistent_repeated_steps(gpu, oracle_mod):
+    """Three chained steps of one persistent launch each: the device queue resets itself."""
+    torch, cn = gpu
+    wl = workloads.uneven_batch(batch=500, lo=1, hi=65_536, steps=3, seed=9)
+    offs, dt = wl["offsets"], wl["dt"]
+    ref = wl["psi0"]
+    for _ in range(3):
+        ref = oracle_mod.cn_step_batched(offs, ref, wl["V"], wl["dx"], dt, 8)
+    tV, tpsi, tdx = to_dev(torch, wl["V"], wl["psi0"], wl["dx"])
+    L = cn.Layout.uneven(offs)
+    assert "persistent" in cn.describe_plan(L, True)
+    for _ in range(3):
+        cn.step(tpsi, tV, 0.0, dt, dx_per_system=tdx, out=tpsi, layout=L)
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("T,M", [(512, 4), (1024, 4), (2048, 4), (1024, 8), (2048, 8)])
+def test_uneven_persistent_configs_and_long_fallback(gpu, oracle_mod, T, M):
+    torch, cn = gpu
+    g = np.random.default_rng(T + M)
+    # one system longer than 64 tiles takes the multi-workgroup path in the same call
+    lengths = np.concatenate([[64 * T + 17, 3, 0, 1], g.integers(1, 64 * T, 60)])
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    a, b, c, d = workloads.random_system(int(offs[-1]), 5, "herm")
+    ref = oracle_mod.thomas_batched(offs, a, b, c, d, nthreads=8)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    L = cn.Layout.uneven(offs, partition=T, rows_per_thread=M)
+    x = cn.solve(ta, tb, tc, td, layout=L)
+    assert rel(x.cpu().numpy(), ref) <= TOL
+    gx = torch.ones_like(td)
+    lam, _, _, _ = cn.solve_adjoint(ta, tb, tc, x, gx, need_abc=False, layout=L)
+    lam_ref = np.concatenate([
+        oracle_mod.thomas_adjoint(a[o0:o1], b[o0:o1], c[o0:o1], ref[o0:o1],
+                                  np.ones(o1 - o0, complex))[0]
+        for o0, o1 in zip(offs[:-1], offs[1:]) if o1 > o0])
+    assert rel(lam.cpu().numpy(), lam_ref) <= TOL
+
+
+def test_autotune_keeps_results(gpu, oracle_mod):
+    torch, cn = gpu
+    wl = workloads.uneven_batch(batch=200, hi=30_000, steps=1, seed=12)
+    ref = oracle_mod.cn_step_batched(wl["offsets"], wl["psi0"], wl["V"], wl["dx"], wl["dt"], 8)
+    tV, tpsi, tdx = to_dev(torch, wl["V"], wl["psi0"], wl["dx"])
+    L = cn.Layout.uneven(wl["offsets"])
+    out = torch.empty_like(tpsi)
+    rep = cn.autotune(L, tpsi, out, V=tV, dt=wl["dt"], dx_per_system=tdx)
+    log(rep)
+    assert "chosen" in rep
+    out2 = cn.step(tpsi, tV, 0.0, wl["dt"], dx_per_system=tdx, layout=L)
+    assert rel(out2.cpu().numpy(), ref) <= TOL
+    n = 200_000
+    a, b, c, d = workloads.random_system(n, 3, "dd")
+    xref = oracle_mod.thomas(a, b, c, d)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x = torch.empty_like(td)
+    rep = cn.autotune(cn.Layout.contiguous(n, 1), td, x, a=ta, b=tb, c=tc)
+    log(rep)
+    x2 = cn.solve(ta, tb, tc, td)
+    assert rel(x2.cpu().numpy(), xref) <= TOL
