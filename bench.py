@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-extra", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--copy-ref", action="store_true",
+                   help="first run a plain 256 MiB device copy three times (a reference of known "
+                        "size for scaling hardware byte counters)")
     return p.parse_args()
 
 
@@ -55,6 +58,33 @@ def timed_events(torch, fn, reps):
         evs[i + 1].record()
     evs[-1].synchronize()
     return [evs[i].elapsed_time(evs[i + 1]) for i in range(reps)]
+
+
+def source_fingerprint():
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2205_00856_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(profile_name):
+    """HBM bytes per launch from the committed counter summary, or None when the kernel
+    sources have changed since the counters were taken."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", profile_name)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (\d+) sources: ([0-9a-f]+)", text)
+    if not m or m.group(2) != source_fingerprint():
+        return None
+    return float(m.group(1))
 
 
 def rel_l2(x, y):
@@ -86,6 +116,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.copy_ref:
+        src = torch.ones(1 << 24, dtype=torch.complex128, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---------------------------------------------------------------- headline: ADI 4096^2
     w = workloads.adi_2d()
@@ -126,12 +164,14 @@ def main():
         t_one = time.perf_counter() - t0
         parity = rel_l2(one, ref)
         # cpu_baseline: the oracle timed on a bounded sample (whole ADI steps of the same grid)
-        nsteps_cpu = max(1, int(args.cpu_seconds / max(t_one, 1e-3)))
+        nsteps_cpu = max(1, int(args.cpu_seconds / max(t_one, 1e-3))) if args.cpu_seconds > 0 else 0
         state = ref
         t0 = time.perf_counter()
         for _ in range(nsteps_cpu):
             state = oracle.adi_step(state, w["V"], w["dx"], w["dy"], w["dt"], nthr)
-        t_cpu = time.perf_counter() - t0
+        t_cpu = max(time.perf_counter() - t0, 1e-9)
+        if nsteps_cpu == 0:
+            nsteps_cpu, t_cpu = 1, t_one
         cpu_baseline = {
             "value": 2 * nx * ny * nsteps_cpu / t_cpu,
             "unit": "complex unknowns/s",
@@ -185,8 +225,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_tile<M=4,W=16,SRC_CN,PH_SINGLE> (fused RHS + N-shaped solve)",
+            "traffic": measured_traffic("adi_4096sq_k_tile_cn_single.md"),
+            "kernel": "k_tile<M=8,W=8,SRC_CN,PH_SINGLE> (fused RHS + N-shaped solve), "
+                      "x- and y-sweep launches averaged",
             "algorithmic_bytes_per_launch": algo_bytes,
             "launch_ms": launch_ms,
         },
@@ -280,7 +321,94 @@ def extras(torch, np, cn, workloads, dev):
                                "plan": cn.describe_plan(L, True)[:400]}
     except Exception as ex:  # noqa: BLE001
         out["uneven_batch"] = {"error": repr(ex)}
+    # ----------------------------------------------------------- differentiated propagation
+    try:
+        out["differentiated"] = differentiated(torch, np, workloads, dev)
+    except Exception as ex:  # noqa: BLE001
+        out["differentiated"] = {"error": repr(ex)}
     return out
+
+
+def differentiated(torch, np, workloads, dev):
+    """N = 2^20, 2000 steps, checkpoint every 50: forward and backward wall time (inclusive
+    ratio), gradients of |<phi|psi_T>|^2 w.r.t. V (32 coordinates) and E (32) against central
+    finite differences of the forward."""
+    from paper_2205_00856_amd import autograd as ag
+
+    w = workloads.differentiated()
+    dx, dt, K = w["dx"], w["dt"], w["ckpt"]
+    tV = torch.tensor(w["V"], device=dev, requires_grad=True)
+    tE = torch.tensor(w["E"], device=dev, requires_grad=True)
+    tx = torch.tensor(w["x"], device=dev)
+    p0 = torch.tensor(w["psi0"], device=dev)
+    phi = torch.tensor(w["phi"], device=dev)
+
+    def fwd(Vt, Et):
+        return ag.cn_propagate(p0, Vt, Et, dx, dt, xgrid=tx, K=K)
+
+    def loss_of(out):
+        return torch.abs((torch.conj(phi) * out).sum() * dx) ** 2
+
+    with torch.no_grad():
+        fwd(tV.detach(), tE.detach())  # warm-up (plans, workspace)
+    tf, tb = [], []
+    for _ in range(3):
+        tV.grad = None
+        tE.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fwd(tV, tE)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L = loss_of(out)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t3 - t2)
+    gV = tV.grad.detach().cpu().numpy()
+    gE = tE.grad.detach().cpu().numpy()
+    norm = float(torch.sum(torch.abs(out) ** 2).item() * dx)
+    # finite differences on 64 coordinates
+    rng = np.random.default_rng(2004)
+    dens = np.abs(w["psi0"]) ** 2 + np.abs(w["phi"]) ** 2
+    cand = np.nonzero(dens > 1e-6 * dens.max())[0]
+    js = rng.choice(cand, 32, replace=False)
+    ks = rng.choice(w["steps"], 32, replace=False)
+    h = 1e-4
+    num, ana = [], []
+    with torch.no_grad():
+        Vd, Ed = tV.detach(), tE.detach()
+        for j in js:
+            Vp, Vm = Vd.clone(), Vd.clone()
+            Vp[j] += h
+            Vm[j] -= h
+            num.append(float(loss_of(fwd(Vp, Ed)) - loss_of(fwd(Vm, Ed))) / (2 * h))
+            ana.append(float(gV[j]))
+        for k in ks:
+            Ep, Em = Ed.clone(), Ed.clone()
+            Ep[k] += h
+            Em[k] -= h
+            num.append(float(loss_of(fwd(Vd, Ep)) - loss_of(fwd(Vd, Em))) / (2 * h))
+            ana.append(float(gE[k]))
+    num = np.asarray(num)
+    ana = np.asarray(ana)
+    fwd_s = float(np.median(tf))
+    bwd_s = float(np.median(tb))
+    return {
+        "n": w["n"], "steps": w["steps"], "checkpoint_every": K,
+        "forward_ms": fwd_s * 1e3, "backward_ms": bwd_s * 1e3,
+        "forward_us_per_step": fwd_s * 1e6 / w["steps"],
+        "backward_us_per_step": bwd_s * 1e6 / w["steps"],
+        "adjoint_over_forward": bwd_s / fwd_s,
+        "loss": float(L.item()), "norm_T": norm,
+        "fd_rel_l2_64": float(np.linalg.norm(ana - num) / np.linalg.norm(num)),
+        "fd_max_rel_per_coord": float(np.max(np.abs(ana - num) / np.maximum(np.abs(num), 1e-300))),
+        "fd_step": h,
+        "phi_draw": list(map(float, w["phi_params"])),
+    }
 
 
 if __name__ == "__main__":

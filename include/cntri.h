@@ -144,6 +144,21 @@ cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_
                           double E, const void* psi_n, const void* psi_np1, const void* g_np1,
                           void* g_n, double* dV_accum, double* dE_partial, cn_stream_t stream);
 
+/* Reverse mode of cn_propagate with checkpoints, for a uniform layout.  ckpt holds the states
+ * that cn_propagate stored before every step k with k % K == 0 (same layout, one span each);
+ * seg is scratch for K+1 states.  On entry g is the gradient of a real loss at the final state
+ * ((d/dRe + i d/dIm) convention); on return it is the gradient at the initial state.  Each
+ * segment of K steps is recomputed forward from its checkpoint, then the adjoint recursion
+ *   lambda_k = T_k^{-H} T_{k+1} lambda_{k+1}   (lambda_{N-1} = T_{N-1}^{-H} g)
+ * runs backwards through it as Crank-Nicolson steps with dt -> -dt, accumulating
+ *   dV_accum_j += v_scale tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (may be NULL)
+ *   dE[k] = sum_j xgrid_j tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (needs xgrid; may be NULL)
+ * in fixed order; finally g = T_0 lambda_0. */
+cn_status cn_propagate_adjoint(cn_handle_t handle, const cn_layout* layout,
+                               const cn_operator* op, int64_t nsteps, const double* E,
+                               const void* ckpt, int64_t K, void* seg, void* g,
+                               double* dV_accum, double* dE, cn_stream_t stream);
+
 /* Autotuner: times the candidate tile configurations (rows per first-level partition and per
  * innermost block) of this layout on the caller's data and keeps the fastest for later calls
  * with the same layout whose partition and rows_per_thread are 0.  cn_mode = 0 times

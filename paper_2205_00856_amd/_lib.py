@@ -82,6 +82,7 @@ def lib():
         "cn_get_status": ([H, P], ctypes.c_int),
         "cn_version": ([], ctypes.c_char_p),
         "cn_describe_plan": ([H, LP, ctypes.c_int, ctypes.c_char_p, i64], ctypes.c_int),
+        "cn_propagate_adjoint": ([H, LP, OP, i64, P, P, i64, P, P, P, P, P], ctypes.c_int),
         "cn_autotune": ([H, LP, ctypes.c_int, OP, d, P, P, P, P, P, ctypes.c_char_p, i64, P],
                         ctypes.c_int),
     }
@@ -95,7 +96,8 @@ def lib():
 
 EXPORTED = ["cn_create", "cn_destroy", "cn_status_string", "cn_reserve", "cn_tridiag_solve",
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
-            "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune"]
+            "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
+            "cn_propagate_adjoint"]
 
 
 def status_string(st: int) -> str:

@@ -19,7 +19,8 @@ from . import _lib
 from ._lib import CnLayout, CnOperator, check
 
 __all__ = ["Layout", "Handle", "handle", "solve", "solve_adjoint", "assemble", "rhs", "step",
-           "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune"]
+           "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune",
+           "propagate_adjoint"]
 
 
 @dataclass
@@ -280,6 +281,36 @@ def propagate(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0, dx_per_sy
     check(_lib.lib().cn_propagate(h.ptr, ctypes.byref(Lc), ctypes.byref(op), int(nsteps), Ep,
                                   _ptr(psi), _ptr(ckpt), int(K), _stream(psi)), "cn_propagate")
     return psi
+
+
+def propagate_adjoint(ckpt, g, V, dx, dt, nsteps, K, E=None, xgrid=None, v_scale=1.0, dV=None,
+                      dE=None, seg=None, layout: Optional[Layout] = None):
+    """Reverse mode of propagate from its checkpoints (cn_propagate_adjoint).  g (in: gradient at
+    psi_T, out: gradient at psi_0) is updated in place; dV (float64) accumulates; dE (float64,
+    nsteps) is written when given (needs xgrid)."""
+    L = _layout_for(g, layout)
+    span = L.span()
+    _need(g, torch.complex128, "g", span)
+    _need(ckpt, torch.complex128, "ckpt", ((nsteps + K - 1) // K) * span)
+    _check_op(L, V, xgrid, None)
+    if seg is None:
+        seg = torch.empty((K + 1) * span, dtype=torch.complex128, device=g.device)
+    _need(seg, torch.complex128, "seg", (K + 1) * span)
+    Earr = None
+    if E is not None:
+        Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
+        if Earr.shape[0] < nsteps:
+            raise ValueError("E needs one value per step")
+    if dE is not None:
+        _need(dE, torch.float64, "dE", nsteps)
+    op = _operator(V, dx, dt, xgrid, v_scale, None)
+    h = handle(g.device.index)
+    Lc = L.c()
+    Ep = None if Earr is None else Earr.ctypes.data_as(ctypes.c_void_p)
+    check(_lib.lib().cn_propagate_adjoint(h.ptr, ctypes.byref(Lc), ctypes.byref(op), int(nsteps),
+                                          Ep, _ptr(ckpt), int(K), _ptr(seg), _ptr(g), _ptr(dV),
+                                          _ptr(dE), _stream(g)), "cn_propagate_adjoint")
+    return g
 
 
 def step_adjoint(psi_n, psi_np1, g_np1, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dV=None,

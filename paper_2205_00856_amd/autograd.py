@@ -3,8 +3,8 @@
 CNSolve      x = T^{-1} d for a tridiagonal T (a, b, c, d complex128); backward solves the
              conjugate-transposed system with the same N-shaped method (cn_tridiag_solve_adjoint).
 CNPropagate  psi_T after nsteps Crank-Nicolson steps with H_k = H_0 + diag(V + x E_k) (Sec. 2);
-             backward runs the adjoint recursion step by step (cn_step_adjoint), recomputing
-             each segment of K steps forward from a stored checkpoint.
+             backward (cn_propagate_adjoint) recomputes each segment of K steps forward from a
+             stored checkpoint and runs the adjoint recursion backwards through it.
 
 Complex gradients use torch's convention (d/dRe + i d/dIm of a real loss), for which
   grad d = T^{-H} grad x,  grad a_i = -lambda_i conj(x_i),  grad b_i = -lambda_i conj(x_{i-1}),
@@ -76,21 +76,10 @@ class CNPropagate(torch.autograd.Function):
         n = gT.shape[0]
         dev = gT.device
         dV = torch.zeros(n, dtype=torch.float64, device=dev)
-        dE = torch.zeros(nsteps, dtype=torch.float64, device=dev)
+        dE = torch.zeros(nsteps, dtype=torch.float64, device=dev) if has_x else None
         g = gT.contiguous().clone()
-        nseg = (nsteps + K - 1) // K
-        seg_states = torch.empty((K + 1, n), dtype=torch.complex128, device=dev)
-        for seg in range(nseg - 1, -1, -1):
-            k0 = seg * K
-            k1 = min(k0 + K, nsteps)
-            seg_states[0].copy_(ckpt[seg * n:(seg + 1) * n])
-            for k in range(k0, k1):  # recompute the segment forward from its checkpoint
-                api.step(seg_states[k - k0], V, dx, dt, E=float(Eh[k]), xgrid=xgrid,
-                         v_scale=v_scale, out=seg_states[k - k0 + 1])
-            for k in range(k1 - 1, k0 - 1, -1):
-                g = api.step_adjoint(seg_states[k - k0], seg_states[k - k0 + 1], g, V, dx, dt,
-                                     E=float(Eh[k]), xgrid=xgrid, v_scale=v_scale, dV=dV,
-                                     dE_out=dE[k:k + 1] if has_x else None)
+        api.propagate_adjoint(ckpt, g, V.detach(), dx, dt, nsteps, K, E=Eh, xgrid=xgrid,
+                              v_scale=v_scale, dV=dV, dE=dE)
         gE = dE.to(device=Edev, dtype=Edt) if has_x else None
         return g, dV, gE, None, None, None, None, None
 

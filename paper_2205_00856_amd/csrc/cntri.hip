@@ -136,6 +136,7 @@ struct Plan {
   int64_t o_aux = -1;   // workspace for an extra state vector (adjoint step)
   int64_t o_part = -1;  // workspace for per-block partial sums
   int64_t nparts = 0;
+  int64_t ntiles1 = 0;  // level-1 tiles of a uniform CN plan (partial sums of the adjoint)
   ~Plan() {
     if (tables) (void)hipFree(tables);
   }
@@ -545,7 +546,10 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
     if (src == nsd::SRC_CN) {
       P->o_aux = B.add_ws(rows * sizeof(cd) + 16);
       P->nparts = (rows + 255) / 256;
-      P->o_part = B.add_ws(P->nparts * sizeof(double) + 16);
+      P->o_part = B.add_ws((rows / 64 + 64) * sizeof(double));
+      for (const Launch& l : P->L)
+        if (l.level == 1 && (l.ph == nsd::PH_SINGLE || l.ph == nsd::PH_SUBST))
+          P->ntiles1 = (int64_t)l.grid.x * l.grid.y;
     }
     P->ws_bytes = B.ws;
     P->desc = B.desc;
@@ -590,6 +594,11 @@ struct UserArgs {
   const double* dxs = nullptr;
   double vscale = 1.0, E_mat = 0.0, E_rhs = 0.0, dx = 1.0, dt = 0.0;
   cd* x = nullptr;
+  const cd* acc_pa = nullptr;
+  const cd* acc_pb = nullptr;
+  double* acc_dV = nullptr;
+  double* acc_part = nullptr;
+  double acc_tau = 0.0;
 };
 
 cn_status run_plan(cn_handle_t h, Plan* P, const UserArgs& u, hipStream_t s) {
@@ -611,6 +620,11 @@ cn_status run_plan(cn_handle_t h, Plan* P, const UserArgs& u, hipStream_t s) {
       a.E_rhs = u.E_rhs;
       a.dx = u.dx;
       a.dt = u.dt;
+      a.acc_pa = u.acc_pa;
+      a.acc_pb = u.acc_pb;
+      a.acc_dV = u.acc_dV;
+      a.acc_part = u.acc_part;
+      a.acc_tau = u.acc_tau;
     }
     a.x = (l.o_x >= 0) ? (cd*)(ws + l.o_x) : u.x;
     if (l.o_sU >= 0) a.sU = (const cd*)(ws + l.o_sU);
@@ -1017,6 +1031,92 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
   rep += "chosen: " + h->plans[best_key]->desc;
   if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
   return CN_OK;
+}
+
+cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* op,
+                               int64_t nsteps, const double* E, const void* ckpt, int64_t K,
+                               void* seg, void* g, double* dV_accum, double* dE,
+                               cn_stream_t stream) {
+  if (!h || !L || !ckpt || !seg || !g || nsteps < 1 || K < 1) return CN_ERR_INVALID_ARG;
+  if (L->offsets) return CN_ERR_UNSUPPORTED;
+  cn_status st = check_op(op);
+  if (st != CN_OK) return st;
+  if (dE && !op->xgrid) return CN_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  if (st != CN_OK) return st;
+  cd* lam = (cd*)((char*)h->ws + P->o_aux);
+  double* part = (double*)((char*)h->ws + P->o_part);
+  cd* segs = (cd*)seg;
+  const int64_t span = P->span;
+  auto Ek = [&](int64_t k) { return E ? E[k] : 0.0; };
+  const int64_t nseg = (nsteps + K - 1) / K;
+  for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+    const int64_t k0 = sg * K, k1 = std::min(nsteps, k0 + K);
+    HIP_TRY(hipMemcpyAsync(segs, (const cd*)ckpt + sg * span, span * sizeof(cd),
+                           hipMemcpyDeviceToDevice, s));
+    // recompute the segment forward from its checkpoint
+    for (int64_t k = k0; k < k1; ++k) {
+      UserArgs u;
+      u.psi = segs + (k - k0) * span;
+      u.x = segs + (k - k0 + 1) * span;
+      u.V = op->V;
+      u.xg = op->xgrid;
+      u.dxs = op->dx_per_system;
+      u.vscale = op->v_scale;
+      u.dx = op->dx;
+      u.dt = op->dt;
+      u.E_mat = u.E_rhs = Ek(k);
+      st = run_plan(h, P, u, s);
+      if (st != CN_OK) return st;
+    }
+    // adjoint recursion backwards through the segment:
+    //   lambda_k = T_k^{-H} T_{k+1} lambda_{k+1}: a CN step with dt -> -dt whose explicit
+    //   half-step uses E_{k+1} and whose matrix uses E_k (T_{N-1}^{-H} g at the last step)
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      UserArgs u;
+      if (k == nsteps - 1) {
+        u.rhs = (const cd*)g;
+        u.psi = (const cd*)g;
+      } else {
+        u.psi = lam;
+      }
+      u.x = lam;
+      u.V = op->V;
+      u.xg = op->xgrid;
+      u.dxs = op->dx_per_system;
+      u.vscale = op->v_scale;
+      u.dx = op->dx;
+      u.dt = -op->dt;
+      u.E_mat = Ek(k);
+      u.E_rhs = (k + 1 < nsteps) ? Ek(k + 1) : Ek(k);
+      u.acc_pa = segs + (k - k0) * span;
+      u.acc_pb = segs + (k - k0 + 1) * span;
+      u.acc_dV = dV_accum;
+      u.acc_part = dE ? part : nullptr;
+      u.acc_tau = 0.5 * op->dt;
+      st = run_plan(h, P, u, s);
+      if (st != CN_OK) return st;
+      if (dE) {
+        hipLaunchKernelGGL(nsd::k_sum_partials, dim3(1), dim3(256), 0, s, (const double*)part,
+                           P->ntiles1, dE + k);
+        if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
+      }
+    }
+  }
+  // gradient at psi_0: G_0 = T_0 lambda_0 = (1 + i tau H_0) lambda_0
+  nsd::AuxArgs X = aux_from(L, P);
+  X.V = op->V;
+  X.xg = op->xgrid;
+  X.vscale = op->v_scale;
+  X.E = Ek(0);
+  X.dx = op->dx;
+  X.dxs = op->dx_per_system;
+  X.dt = -op->dt;
+  X.psi = lam;
+  X.d = (cd*)g;
+  return launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
 }
 
 cn_status cn_get_status(cn_handle_t h, cn_stream_t stream) {

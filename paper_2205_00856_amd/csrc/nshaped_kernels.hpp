@@ -50,6 +50,14 @@ struct KArgs {
   int xcd_remap;          // uniform single-tile launches: XCD-contiguous system order
   int* queue;             // persistent launch: [next item, workgroups done]
   int nitems;             // persistent launch: number of systems in wg_sys
+  // adjoint accumulation fused into the store of lambda (CN source, uniform batches):
+  //   q_j = acc_tau Im(conj(lambda_j) (acc_pa_j + acc_pb_j)); acc_dV_j += vscale q_j;
+  //   acc_part[tile] = sum over the tile of xg_j q_j (fixed order)
+  const cd* acc_pa;
+  const cd* acc_pb;
+  double* acc_dV;
+  double* acc_part;
+  double acc_tau;
 };
 
 struct Geo {
@@ -138,21 +146,6 @@ __device__ __forceinline__ void transpose_in(T* buf, int lane, const T (&v)[M], 
   wave_sync();
   stage_read<M>(buf, lane, out);
   wave_sync();
-}
-
-template <int M>
-__device__ __forceinline__ void stage_out(cd* buf, cd* g, int64_t es, int64_t w0, int64_t n,
-                                          int lane, const cd (&x)[M]) {
-  using S = Stage<M>;
-  wave_sync();
-#pragma unroll
-  for (int j = 0; j < M; ++j) buf[S::addr(lane * M + j + 1)] = x[j];
-  wave_sync();
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    int64_t r = w0 + 64 * k + lane;
-    if (r < n) g[r * es] = buf[S::addr(1 + 64 * k + lane)];
-  }
 }
 
 // ------------------------------------------------------------------ row assembly per source
@@ -281,12 +274,73 @@ struct Log2<1> {
 };
 
 template <int M, int W>
+struct TileSmem;
+
+template <int M, int W, int SRC>
+__device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+                                           cd* buf, int64_t w0, int lane, int wave,
+                                           const cd (&x)[M]);
+
+template <int M, int W>
 struct TileSmem {
   cd lds[W][Stage<M>::QS];  // per-wavefront staging buffer; holds the tree nodes in between
   Blk wblk[W];
   cd wpsi[W][2];
   Node xnode[64];
+  double wsum[W];
 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += xmove<1>(v);
+  v += xmove<2>(v);
+  v += xmove<4>(v);
+  v += xmove<8>(v);
+  v += xmove<16>(v);
+  v += xmove<32>(v);
+  return v;  // every lane holds the sum, added in the same order
+}
+
+// Coalesced store of the tile's solution through the LDS buffer; for the CN source the adjoint
+// accumulation (see KArgs) runs on the same coalesced rows.
+template <int M, int W, int SRC>
+__device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+                                           cd* buf, int64_t w0, int lane, int wave,
+                                           const cd (&x)[M]) {
+  using S = Stage<M>;
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < M; ++j) buf[S::addr(lane * M + j + 1)] = x[j];
+  wave_sync();
+  cd* g = A.x + G.base;
+  const bool acc = (SRC == SRC_CN) && A.acc_pa != nullptr;
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int64_t r = w0 + 64 * k + lane;
+    if (r < G.n) {
+      const cd v = buf[S::addr(1 + 64 * k + lane)];
+      const int64_t e = G.base + r * G.es;
+      g[r * G.es] = v;
+      if (acc) {
+        const cd s = cadd(A.acc_pa[e], A.acc_pb[e]);
+        const double q = A.acc_tau * (v.x * s.y - v.y * s.x);
+        if (A.acc_dV) A.acc_dV[e] += A.vscale * q;
+        if (A.xg) part = fma(A.xg[e], q, part);
+      }
+    }
+  }
+  if (acc && A.acc_part) {
+    part = wave_sum(part);
+    if (lane == 0) sm.wsum[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < W; ++w) t += sm.wsum[w];
+      A.acc_part[G.gt] = t;
+    }
+    __syncthreads();
+  }
+}
 
 // One tile of T = 64*W*M rows of one system, run by every thread of the workgroup.
 //   PH_SINGLE  the tile holds the whole system: RS on its two joint lines, then SS
@@ -382,7 +436,7 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
       for (int j = 0; j < M; ++j)
         if (J + j < G.n) A.x[G.base + J + j] = xo[j];
     } else {
-      stage_out<M>(buf, A.x + G.base, G.es, w0, G.n, lane, xo);
+      store_tile<M, W, SRC>(A, G, sm, buf, w0, lane, wave, xo);
     }
   }
 }
