@@ -290,15 +290,39 @@ def extras(torch, np, cn, workloads, dev):
     # ----------------------------------------------------------- plain 1D
     try:
         w = workloads.plain_1d()
-        psi = torch.from_numpy(w["psi0"]).to(dev)
+        psi0 = torch.from_numpy(w["psi0"]).to(dev)
         V = torch.from_numpy(w["V"]).to(dev)
         L = cn.Layout.contiguous(w["n"], 1)
-        cn.propagate(psi.clone(), V, w["dx"], w["dt"], 5)
-        ts = timed_events(torch, lambda: cn.propagate(psi, V, w["dx"], w["dt"], w["steps"]), 3)
-        med = float(np.median(ts))
-        out["plain_1d"] = {"n": w["n"], "steps": w["steps"], "ms_per_200_steps": med,
-                           "us_per_step": med * 1e3 / w["steps"],
+        cn.reserve(L)
+        # one materialised solve (a, b, c from the operator; d = explicit half-step of psi0)
+        a, b, c = cn.assemble(V, w["dx"], w["dt"])
+        d = cn.rhs(psi0, V, w["dx"], w["dt"])
+        x = torch.empty_like(d)
+        ts_solve = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), 20)
+        # 200 chained steps: eager, then captured as one graph
+        psi = psi0.clone()
+        ts_eager = timed_events(torch, lambda: cn.propagate(psi, V, w["dx"], w["dt"], w["steps"]), 3)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            cn.propagate(psi, V, w["dx"], w["dt"], 1)
+        torch.cuda.current_stream().wait_stream(side)
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            cn.propagate(psi, V, w["dx"], w["dt"], w["steps"])
+        psi.copy_(psi0)
+        gr.replay()
+        torch.cuda.synchronize()
+        norm = float(torch.sum(torch.abs(psi) ** 2).item() * w["dx"])
+        ts_graph = timed_events(torch, gr.replay, 5)
+        med = float(np.median(ts_graph))
+        out["plain_1d"] = {"n": w["n"], "steps": w["steps"],
+                           "solve_us": float(np.median(ts_solve)) * 1e3,
+                           "ms_per_200_steps_graph": med,
+                           "us_per_step_graph": med * 1e3 / w["steps"],
+                           "us_per_step_eager": float(np.median(ts_eager)) * 1e3 / w["steps"],
                            "unknowns_per_s": w["n"] * w["steps"] / (med * 1e-3),
+                           "norm_after_200": norm,
                            "plan": cn.describe_plan(L, True)}
     except Exception as ex:  # noqa: BLE001
         out["plain_1d"] = {"error": repr(ex)}

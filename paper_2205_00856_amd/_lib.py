@@ -68,6 +68,7 @@ def lib():
     i64 = ctypes.c_int64
     d = ctypes.c_double
     sig = {
+        "cn_check_layout": ([LP], ctypes.c_int),
         "cn_create": ([ctypes.POINTER(H), ctypes.c_int], ctypes.c_int),
         "cn_destroy": ([H], ctypes.c_int),
         "cn_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -94,7 +95,7 @@ def lib():
     return L
 
 
-EXPORTED = ["cn_create", "cn_destroy", "cn_status_string", "cn_reserve", "cn_tridiag_solve",
+EXPORTED = ["cn_check_layout", "cn_create", "cn_destroy", "cn_status_string", "cn_reserve", "cn_tridiag_solve",
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
             "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
             "cn_propagate_adjoint"]

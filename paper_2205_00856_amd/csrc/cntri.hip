@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -26,8 +27,8 @@ struct Cfg {
   int64_t T() const { return 64LL * W * M; }
 };
 // (rows per lane, wavefronts per workgroup); tile T = 64 W M rows
-constexpr Cfg kCfgs[] = {{2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16},
-                         {8, 1}, {8, 2}, {8, 4}, {8, 8}, {2, 2}, {2, 4}};
+constexpr Cfg kCfgs[] = {{2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 1},
+                         {8, 2}, {8, 4}, {8, 8}, {2, 2}, {2, 4}, {16, 4}, {16, 2}};
 constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 typedef void (*KFn)(KArgs);
@@ -60,6 +61,8 @@ struct KernTableInit {
     reg_cfg<8, 8>(9);
     reg_cfg<2, 2>(10);
     reg_cfg<2, 4>(11);
+    reg_cfg<16, 4>(12);
+    reg_cfg<16, 2>(13);
   }
 } g_kern_init;
 
@@ -80,6 +83,48 @@ struct PersTableInit {
     reg_pers<8, 4>(8);
   }
 } g_pers_init;
+
+// column kernels for interleaved batches (lanes across neighbouring systems); tile T = W*M
+constexpr Cfg kColCfgs[] = {{4, 8}, {8, 4}, {8, 8}, {4, 16}, {16, 4}, {8, 16}};
+constexpr int kNumColCfg = sizeof(kColCfgs) / sizeof(kColCfgs[0]);
+const void* g_cols[kNumColCfg][4][3];
+template <int M, int W, int SRC>
+void reg_col_src(int ci) {
+  g_cols[ci][SRC][nsd::PH_SINGLE] = (const void*)&nsd::k_cols<M, W, SRC, nsd::PH_SINGLE>;
+  g_cols[ci][SRC][nsd::PH_REDUCE] = (const void*)&nsd::k_cols<M, W, SRC, nsd::PH_REDUCE>;
+  g_cols[ci][SRC][nsd::PH_SUBST] = (const void*)&nsd::k_cols<M, W, SRC, nsd::PH_SUBST>;
+}
+template <int M, int W>
+void reg_col(int ci) {
+  reg_col_src<M, W, nsd::SRC_EXPL>(ci);
+  reg_col_src<M, W, nsd::SRC_EXPL_CT>(ci);
+  reg_col_src<M, W, nsd::SRC_CN>(ci);
+}
+struct ColTableInit {
+  ColTableInit() {
+    reg_col<4, 8>(0);
+    reg_col<8, 4>(1);
+    reg_col<8, 8>(2);
+    reg_col<4, 16>(3);
+    reg_col<16, 4>(4);
+    reg_col<8, 16>(5);
+  }
+} g_col_init;
+
+int col_cfg(int64_t T, int M) {
+  for (int i = 0; i < kNumColCfg; ++i)
+    if ((int64_t)kColCfgs[i].M * kColCfgs[i].W == T && (M == 0 || kColCfgs[i].M == M)) return i;
+  return -1;
+}
+
+// column kernels for interleaved batches (CN_COLS=0 turns them off)
+bool cols_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_COLS");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
 
 int find_cfg(int64_t T, int M) {
   for (int i = 0; i < kNumCfg; ++i)
@@ -233,6 +278,63 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   char line[256];
   if (!bd.uneven) {
     const int64_t n = bd.n, batch = bd.batch;
+    if (bd.bs == 1 && batch >= 64 && bd.es >= batch && src != nsd::SRC_SLOTS && cols_enabled()) {
+      int cc = -1;
+      if (level == 1 && kn.partition > 0) cc = col_cfg(kn.partition, kn.rpt);
+      if (cc < 0) cc = col_cfg(64, 8);
+      const int64_t T = (int64_t)kColCfgs[cc].M * kColCfgs[cc].W;
+      const int64_t K = (n + T - 1) / T, G = K * batch;
+      const unsigned gy = (unsigned)((batch + 63) / 64);
+      KArgs a = base;
+      a.n = n;
+      a.ntiles = K;
+      a.es = bd.es;
+      a.bs = bd.bs;
+      a.batch = batch;
+      a.nitems = (int)std::min<int64_t>(G, INT32_MAX);
+      auto add_col = [&](int ph) {
+        Launch l;
+        l.fn = g_cols[cc][src][ph];
+        l.grid = dim3((unsigned)K, gy);
+        l.threads = 64 * kColCfgs[cc].W;
+        l.a = a;
+        l.level = level;
+        l.src = src;
+        l.ph = ph;
+        l.cfg = -1;
+        L.push_back(l);
+        set_common(L.back());
+      };
+      char cs[96];
+      snprintf(cs, sizeof(cs), "T=%lld(M=%d,W=%d)", (long long)T, kColCfgs[cc].M, kColCfgs[cc].W);
+      if (K == 1) {
+        add_col(nsd::PH_SINGLE);
+        snprintf(line, sizeof(line), "L%d columns single %s n=%lld batch=%lld; ", level, cs,
+                 (long long)n, (long long)batch);
+        B.desc += line;
+        return;
+      }
+      const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
+      const int64_t oP = B.add_ws(G * sizeof(cd));
+      const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+      snprintf(line, sizeof(line), "L%d columns multi %s n=%lld batch=%lld tiles=%lld; ", level, cs,
+               (long long)n, (long long)batch, (long long)K);
+      B.desc += line;
+      add_col(nsd::PH_REDUCE);
+      L.back().o_oU = oU;
+      L.back().o_oD = oD;
+      L.back().o_hout = oH;
+      BatchDesc ib;
+      ib.uneven = true;
+      ib.batch = batch;
+      ib.offs.resize(batch + 1);
+      for (int64_t s2 = 0; s2 <= batch; ++s2) ib.offs[s2] = s2 * K;
+      plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+      add_col(nsd::PH_SUBST);
+      L.back().o_psi_if = oP;
+      L.back().o_hin = oH;
+      return;
+    }
     int ci_single = -1;
     if (level == 1 && kn.partition > 0) {
       if (n <= kn.partition) ci_single = multi_cfg(n, batch, kn, level);
@@ -469,7 +571,7 @@ cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
     if (p < 64 || p > 16384 || (p & (p - 1))) return CN_ERR_INVALID_ARG;
   }
   if (L->rows_per_thread != 0 && L->rows_per_thread != 2 && L->rows_per_thread != 4 &&
-      L->rows_per_thread != 8)
+      L->rows_per_thread != 8 && L->rows_per_thread != 16)
     return CN_ERR_INVALID_ARG;
   if (L->offsets) {
     if (L->offsets[0] != 0) return CN_ERR_INVALID_ARG;
@@ -535,10 +637,13 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
     kn.partition = L->partition;
     kn.rpt = L->rows_per_thread;
     if (kn.partition > 0) {
+      const bool columns = !L->offsets && L->batch_stride == 1 && L->batch >= 64 &&
+                           L->elem_stride >= L->batch && cols_enabled();
       const int M = kn.rpt > 0 ? kn.rpt : (kn.partition >= 512 ? 8 : 4);
-      if (find_cfg(kn.partition, M) < 0 && find_cfg(kn.partition, 4) < 0 &&
-          find_cfg(kn.partition, 8) < 0 && find_cfg(kn.partition, 2) < 0)
-        return CN_ERR_UNSUPPORTED;
+      const bool rows_ok = find_cfg(kn.partition, M) >= 0 || find_cfg(kn.partition, 4) >= 0 ||
+                           find_cfg(kn.partition, 8) >= 0 || find_cfg(kn.partition, 2) >= 0;
+      const bool cols_ok = col_cfg(kn.partition, kn.rpt) >= 0;
+      if (columns ? !cols_ok : !rows_ok) return CN_ERR_UNSUPPORTED;
     }
     plan_level(B, P->L, bd, src, 1, -1, -1, -1, kn);
     P->span = span;
@@ -549,7 +654,7 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
       P->o_part = B.add_ws((rows / 64 + 64) * sizeof(double));
       for (const Launch& l : P->L)
         if (l.level == 1 && (l.ph == nsd::PH_SINGLE || l.ph == nsd::PH_SUBST))
-          P->ntiles1 = (int64_t)l.grid.x * l.grid.y;
+          P->ntiles1 = l.a.nitems > 0 ? (int64_t)l.a.nitems : (int64_t)l.grid.x * l.grid.y;
     }
     P->ws_bytes = B.ws;
     P->desc = B.desc;
@@ -692,6 +797,11 @@ const char* cn_status_string(cn_status st) {
     case CN_ERR_NOT_RESERVED: return "CN_ERR_NOT_RESERVED";
   }
   return "unknown cn_status";
+}
+
+cn_status cn_check_layout(const cn_layout* layout) {
+  int64_t rows = 0, span = 0;
+  return validate(layout, rows, span);
 }
 
 cn_status cn_create(cn_handle_t* handle, int device) {

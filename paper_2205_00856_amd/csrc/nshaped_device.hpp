@@ -87,12 +87,18 @@ struct Node {
 };
 
 // ---------------------------------------------------------------- level 1: one lane's block
+// (i b) z for a pure imaginary i b
+__device__ __forceinline__ cd cimul(double b, cd z) { return mk(-b * z.y, b * z.x); }
+
 // Input rows J .. J+M-1 (local 0 .. M-1) as (a, b, c, d) in (A, Bt, Ct, D); bK is the
 // sub-diagonal of the next joint line K = J+M.  On return rows 1..M-1 hold the scaled reduced
-// rows (beta in Bt, gamma in Ct, delta in D) for SS; A is consumed.
-template <int M>
+// rows (beta in Bt, gamma in Ct, delta in D) for SS; A is consumed.  With IMAG the input
+// off-diagonals (b, c, bK) are pure imaginary (only their imaginary parts are read), as in
+// every Crank-Nicolson matrix with a real potential.
+template <int M, bool IMAG = false>
 __device__ __forceinline__ void reduce_block(cd (&A)[M], cd (&Bt)[M], cd (&Ct)[M], cd (&D)[M],
                                              cd bK, Blk& o) {
+  auto bmul = [](cd b, cd z) { return IMAG ? cimul(b.y, z) : cmul(b, z); };
   if constexpr (M == 1) {
     // a block without interior rows: its two joint lines are coupled directly
     o.UA = A[0];
@@ -105,25 +111,25 @@ __device__ __forceinline__ void reduce_block(cd (&A)[M], cd (&Bt)[M], cd (&Ct)[M
     // row J+1 keeps its b (coefficient of psi_J); scale it by its pivot
     {
       cd ia = crecip(A[1]);
-      Bt[1] = cmul(Bt[1], ia);
-      Ct[1] = cmul(Ct[1], ia);
+      Bt[1] = bmul(Bt[1], ia);
+      Ct[1] = bmul(Ct[1], ia);
       D[1] = cmul(D[1], ia);
     }
     // RD: i = J+2 .. K-1 with row i-1 scaled: r = -b_i
 #pragma unroll
     for (int i = 2; i < M; ++i) {
-      cd a = cfms(Bt[i], Ct[i - 1], A[i]);       // a_i - b_i gamma_{i-1}
-      cd d = cfms(Bt[i], D[i - 1], D[i]);        // d_i - b_i delta_{i-1}
-      cd b = cneg(cmul(Bt[i], Bt[i - 1]));       // -b_i beta_{i-1}
+      cd a = csub(A[i], bmul(Bt[i], Ct[i - 1]));  // a_i - b_i gamma_{i-1}
+      cd d = csub(D[i], bmul(Bt[i], D[i - 1]));   // d_i - b_i delta_{i-1}
+      cd b = cneg(bmul(Bt[i], Bt[i - 1]));        // -b_i beta_{i-1}
       cd ia = crecip(a);
       Bt[i] = cmul(b, ia);
-      Ct[i] = cmul(Ct[i], ia);
+      Ct[i] = bmul(Ct[i], ia);
       D[i] = cmul(d, ia);
     }
     // JD at K: r = -b_K (row K-1 scaled)
-    o.DB = cneg(cmul(bK, Bt[M - 1]));
-    o.DA = cneg(cmul(bK, Ct[M - 1]));
-    o.DD = cneg(cmul(bK, D[M - 1]));
+    o.DB = cneg(bmul(bK, Bt[M - 1]));
+    o.DA = cneg(bmul(bK, Ct[M - 1]));
+    o.DD = cneg(bmul(bK, D[M - 1]));
     // RU: i = K-2 .. J+1 with row i+1 final: r = -gamma_i
 #pragma unroll
     for (int i = M - 2; i >= 1; --i) {
@@ -133,9 +139,9 @@ __device__ __forceinline__ void reduce_block(cd (&A)[M], cd (&Bt)[M], cd (&Ct)[M
       Ct[i] = cneg(cmul(g, Ct[i + 1]));
     }
     // JU at J: r = -c_J (row J+1 final)
-    o.UA = cfms(Ct[0], Bt[1], A[0]);
-    o.UD = cfms(Ct[0], D[1], D[0]);
-    o.UC = cneg(cmul(Ct[0], Ct[1]));
+    o.UA = csub(A[0], bmul(Ct[0], Bt[1]));
+    o.UD = csub(D[0], bmul(Ct[0], D[1]));
+    o.UC = cneg(bmul(Ct[0], Ct[1]));
   }
 }
 
@@ -188,6 +194,22 @@ __device__ __forceinline__ cd xmove(cd v) {
 // lane x + 2^s holds R.  The lane of L receives R, keeps the merged block and stores the
 // scaled row K in LDS slot x + 2^s (read back by the same lane in SS).  The other lanes
 // compute the same formulas on data that is no longer needed.
+// b = [J, K] absorbs o = [K, M]: b becomes [J, M]; t is the scaled row K.
+__device__ __forceinline__ void merge_into(Blk& b, const Blk& o, Node& t) {
+  const cd ia = crecip(cadd(b.DA, o.UA));
+  t.B = cmul(b.DB, ia);
+  t.C = cmul(o.UC, ia);
+  t.dl = cmul(cadd(b.DD, o.UD), ia);
+  const cd rU = b.UC;
+  const cd rD = o.DB;
+  b.UA = cfms(rU, t.B, b.UA);
+  b.UD = cfms(rU, t.dl, b.UD);
+  b.UC = cneg(cmul(rU, t.C));
+  b.DB = cneg(cmul(rD, t.B));
+  b.DA = cfms(rD, t.C, o.DA);
+  b.DD = cfms(rD, t.dl, o.DD);
+}
+
 template <int m>
 __device__ __forceinline__ void tree_level_up(Blk& b, Node* nodes, int lane) {
   Blk o;
@@ -197,20 +219,9 @@ __device__ __forceinline__ void tree_level_up(Blk& b, Node* nodes, int lane) {
   o.DB = xmove<m>(b.DB);
   o.DA = xmove<m>(b.DA);
   o.DD = xmove<m>(b.DD);
-  const cd ia = crecip(cadd(b.DA, o.UA));
   Node t;
-  t.B = cmul(b.DB, ia);
-  t.C = cmul(o.UC, ia);
-  t.dl = cmul(cadd(b.DD, o.UD), ia);
+  merge_into(b, o, t);
   if ((lane & (2 * m - 1)) == 0) nodes[lane + m] = t;
-  const cd rU = b.UC;
-  const cd rD = o.DB;
-  b.UA = cfms(rU, t.B, b.UA);
-  b.UD = cfms(rU, t.dl, b.UD);
-  b.UC = cneg(cmul(rU, t.C));
-  b.DB = cneg(cmul(rD, t.B));
-  b.DA = cfms(rD, t.C, o.DA);
-  b.DD = cfms(rD, t.dl, o.DD);
 }
 
 // Binary nesting over 2^LEVELS consecutive lanes: afterwards the lane with the low LEVELS bits

@@ -58,6 +58,7 @@ struct KArgs {
   double* acc_dV;
   double* acc_part;
   double acc_tau;
+  int64_t batch;          // uniform batch size (column kernel)
 };
 
 struct Geo {
@@ -148,6 +149,88 @@ __device__ __forceinline__ void transpose_in(T* buf, int lane, const T (&v)[M], 
   wave_sync();
 }
 
+// ------------------------------------------------------------------ Crank-Nicolson rows
+// Raw coalesced loads of one wavefront's rows (state or given right-hand side, V, xgrid).
+template <int M, bool XG>
+struct CnRaw {
+  cd p[M];
+  cd hp;
+  double v[M];
+  double hv;
+  double x[XG ? M : 1];
+  double hx;
+};
+
+template <int M, bool XG>
+__device__ __forceinline__ void cn_fetch(const KArgs& A, const Geo& G, int64_t w0, int lane,
+                                         CnRaw<M, XG>& r) {
+  const cd* src = (A.rhs ? A.rhs : A.psi) + G.base;
+  stage_fetch<M>(src, G.es, w0, G.n, lane, czero(), r.p, r.hp);
+  stage_fetch<M>(A.V + G.base, G.es, w0, G.n, lane, 0.0, r.v, r.hv);
+  if constexpr (XG) {
+    if (A.xg) stage_fetch<M>(A.xg + G.base, G.es, w0, G.n, lane, 0.0, r.x, r.hx);
+  }
+}
+
+// Rows of T = 1 + i tau H and the explicit half-step d = (1 - i tau H) psi (Sec. 2, Eq. (3)),
+// fused into the reduction (Sec. 5.3).  The off-diagonals are -i kappa (pure imaginary).
+template <int M, int W, int PH, bool XG>
+__device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
+                                         int64_t J, int lane, int wave, CnRaw<M, XG>& raw,
+                                         cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
+                                         cd& bK, cd& first_state, cd& last_state) {
+  const int64_t n = G.n;
+  const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
+  const double tau = 0.5 * A.dt;
+  const double idx2 = 1.0 / (dx * dx);
+  const double kap = tau * 0.5 * idx2;
+  const bool given = A.rhs != nullptr;
+  const cd zero = czero();
+  if constexpr (PH == PH_SUBST) {
+    // the neighbours' edge rows may already hold the new state: take the saved copies
+    if (!given) {
+      if (wave == 0 && lane == 0 && G.tile > 0) raw.hp = A.halo_in[2 * (G.gt - 1) + 1];
+      if (wave == W - 1 && lane == 1 && G.tile + 1 < G.ntile) raw.hp = A.halo_in[2 * (G.gt + 1)];
+    }
+  }
+  cd vp[M + 2];
+  transpose_in<M>(buf, lane, raw.p, raw.hp, vp);
+  double vv[M + 2], xv[M + 2];
+  double* bufd = reinterpret_cast<double*>(buf);
+  transpose_in<M>(bufd, lane, raw.v, raw.hv, vv);
+  bool hasx = false;
+  if constexpr (XG) {
+    if (A.xg) {
+      hasx = true;
+      transpose_in<M>(bufd, lane, raw.x, raw.hx, xv);
+    }
+  }
+  if (!hasx) {
+#pragma unroll
+    for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int64_t r = J + j;
+    const bool ok = r < n;
+    const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
+    Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
+    Br[j] = mk(0.0, (ok && r > 0) ? -kap : 0.0);
+    Cr[j] = mk(0.0, (ok && r < n - 1) ? -kap : 0.0);
+    if (given) {
+      Dr[j] = vp[j + 1];
+    } else {
+      const double w = tau * (idx2 + fma(xv[j + 1], A.E_rhs, A.vscale * vv[j + 1]));
+      const cd p = vp[j + 1];
+      const cd s = cadd(vp[j], vp[j + 2]);
+      Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
+    }
+  }
+  bK = mk(0.0, (J + M < n) ? -kap : 0.0);
+  first_state = vp[1];
+  last_state = vp[M];
+}
+
 // ------------------------------------------------------------------ row assembly per source
 template <int M, int W, int SRC, int PH>
 __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
@@ -190,56 +273,10 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
       bK = csel(K < n, cconj(vc[M]), zero);
     first_state = last_state = zero;
   } else if constexpr (SRC == SRC_CN) {
-    const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
-    const double tau = 0.5 * A.dt;
-    const double idx2 = 1.0 / (dx * dx);
-    const double kap = tau * 0.5 * idx2;
-    const bool given = A.rhs != nullptr;
-    const cd zero = czero();
-    cd rp[M], hp;
-    double rv[M], hv, rx[M], hx;
-    stage_fetch<M>(given ? A.rhs + G.base : A.psi + G.base, G.es, w0, n, lane, zero, rp, hp);
-    stage_fetch<M>(A.V + G.base, G.es, w0, n, lane, 0.0, rv, hv);
-    if (A.xg) stage_fetch<M>(A.xg + G.base, G.es, w0, n, lane, 0.0, rx, hx);
-    if constexpr (PH == PH_SUBST) {
-      // the neighbours' edge rows may already hold the new state: take the saved copies
-      if (!given) {
-        if (wave == 0 && lane == 0 && G.tile > 0) hp = A.halo_in[2 * (G.gt - 1) + 1];
-        if (wave == W - 1 && lane == 1 && G.tile + 1 < G.ntile) hp = A.halo_in[2 * (G.gt + 1)];
-      }
-    }
-    cd vp[M + 2];
-    transpose_in<M>(buf, lane, rp, hp, vp);
-    double vv[M + 2], xv[M + 2];
-    double* bufd = reinterpret_cast<double*>(buf);
-    transpose_in<M>(bufd, lane, rv, hv, vv);
-    if (A.xg) {
-      transpose_in<M>(bufd, lane, rx, hx, xv);
-    } else {
-#pragma unroll
-      for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const int64_t r = J + j;
-      const bool ok = r < n;
-      const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
-      Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
-      Br[j] = mk(0.0, (ok && r > 0) ? -kap : 0.0);
-      Cr[j] = mk(0.0, (ok && r < n - 1) ? -kap : 0.0);
-      if (given) {
-        Dr[j] = vp[j + 1];
-      } else {
-        // d = (1 - i tau (1/dx^2 + v)) psi + i kappa (psi_{j-1} + psi_{j+1})  (Sec. 2, Eq. (3))
-        const double w = tau * (idx2 + fma(xv[j + 1], A.E_rhs, A.vscale * vv[j + 1]));
-        const cd p = vp[j + 1];
-        const cd s = cadd(vp[j], vp[j + 2]);
-        Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
-      }
-    }
-    bK = mk(0.0, (J + M < n) ? -kap : 0.0);
-    first_state = vp[1];
-    last_state = vp[M];
+    CnRaw<M, true> raw;
+    cn_fetch<M, true>(A, G, w0, lane, raw);
+    cn_build<M, W, PH, true>(A, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr, bK, first_state,
+                             last_state);
   } else {  // SRC_SLOTS: row k of the reduced system = U slot of tile k + D slot of tile k-1
     const cd zero = czero();
 #pragma unroll
@@ -342,6 +379,12 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
   }
 }
 
+template <int M, int W, int SRC, int PH>
+__device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+                                            cd* buf, int64_t w0, int64_t J, int lane, int wave,
+                                            cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
+                                            cd bK, cd fst, cd lst);
+
 // One tile of T = 64*W*M rows of one system, run by every thread of the workgroup.
 //   PH_SINGLE  the tile holds the whole system: RS on its two joint lines, then SS
 //   PH_REDUCE  writes the tile's U/D slots at index G.gt of oU/oD (and, for the CN source,
@@ -349,7 +392,6 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
 //   PH_SUBST   takes psi at the tile's joint lines from psi_if[G.gt], psi_if[G.gt + 1]
 template <int M, int W, int SRC, int PH>
 __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<M, W>& sm) {
-  constexpr int LW = Log2<W>::v;
   constexpr int64_t T = 64 * W * M;
   static_assert(sizeof(cd) * Stage<M>::QS >= sizeof(Node) * 64, "node slots fit the stage buffer");
 
@@ -362,7 +404,16 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
   load_rows<M, W, SRC, PH>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+  tile_finish<M, W, SRC, PH>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+}
 
+// Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
+template <int M, int W, int SRC, int PH>
+__device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+                                            cd* buf, int64_t w0, int64_t J, int lane, int wave,
+                                            cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
+                                            cd bK, cd fst, cd lst) {
+  constexpr int LW = Log2<W>::v;
   if constexpr (PH == PH_REDUCE && SRC == SRC_CN) {
     if (A.halo_out) {
       if (wave == 0 && lane == 0) A.halo_out[2 * G.gt] = fst;
@@ -371,7 +422,7 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
   }
 
   Blk blk;
-  reduce_block<M>(Ar, Br, Cr, Dr, bK, blk);
+  reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
   // the staging buffer is idle between the loads and the stores: it holds the nodes
   Node* wnode = reinterpret_cast<Node*>(buf);
   wave_sync();
@@ -447,6 +498,210 @@ __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
   __shared__ TileSmem<M, W> sm;
   const Geo G = geometry(A);
   tile_run<M, W, SRC, PH>(A, G, sm);
+}
+
+// ------------------------------------------------------------------ interleaved batches
+// Uniform batches whose neighbouring systems are neighbours in memory (batch_stride 1, e.g. ADI
+// y-lines): the 64 lanes of a wavefront take 64 adjacent systems, so every row is one coalesced
+// 1 KiB access.  A workgroup owns a tile of T = W*M rows of those 64 systems; wavefront w holds
+// rows w*M .. w*M+M-1 of the tile in each lane (level 1, Table 1 in registers).  Level 2 runs
+// down the W joint lines of each system inside one lane: a sequential elimination of joint lines
+// 1 .. W-1 (JU/JD on blocks with one interior joint line), every lane busy with its own system.
+template <int M, int W>
+struct ColSmem {
+  Blk blk[W][64];       // level-1 blocks; after the elimination, the node of joint line w
+  cd jpsi[W + 1][64];   // psi at the tile's joint lines
+  double wpart[W][64];  // adjoint partial sums per wavefront and system
+};
+
+// Rows r0-1 .. r0+M of one system at element base + r*es, loaded per lane (clamped, selected).
+template <int M, typename T>
+__device__ __forceinline__ void col_fetch(const T* g, int64_t es, int64_t r0, int64_t n, T fill,
+                                          T (&v)[M + 2]) {
+#pragma unroll
+  for (int j = 0; j < M + 2; ++j) {
+    const int64_t r = r0 - 1 + j;
+    const int64_t rc = r < 0 ? 0 : (r < n ? r : n - 1);
+    const T t = g[rc * es];
+    v[j] = sel(r >= 0 && r < n, t, fill);
+  }
+}
+
+template <int M, int W, int SRC, int PH>
+__global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
+  __shared__ ColSmem<M, W> sm;
+  constexpr int64_t T = (int64_t)W * M;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t sys = (int64_t)blockIdx.y * 64 + lane;
+  const bool live = sys < A.batch;
+  Geo G;
+  G.sys = live ? sys : A.batch - 1;
+  G.n = A.n;
+  G.es = A.es;
+  G.base = G.sys * A.bs;
+  G.tile = blockIdx.x;
+  G.ntile = A.ntiles;
+  G.gt = G.sys * A.ntiles + G.tile;
+  const int64_t r0 = G.tile * T + (int64_t)wave * M;
+  const int64_t n = G.n;
+  const cd zero = czero();
+  cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst = zero, lst = zero;
+  if constexpr (SRC == SRC_EXPL || SRC == SRC_EXPL_CT) {
+    cd va[M + 2], vb[M + 2], vc[M + 2], vd[M + 2];
+    col_fetch<M>(A.a + G.base, G.es, r0, n, mk(1.0, 0.0), va);
+    col_fetch<M>(A.b + G.base, G.es, r0, n, zero, vb);
+    col_fetch<M>(A.c + G.base, G.es, r0, n, zero, vc);
+    col_fetch<M>(A.d + G.base, G.es, r0, n, zero, vd);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = r0 + j;
+      const bool ok = r < n;
+      if constexpr (SRC == SRC_EXPL) {
+        Ar[j] = csel(ok, va[j + 1], mk(1.0, 0.0));
+        Br[j] = csel(ok && r > 0, vb[j + 1], zero);
+        Cr[j] = csel(ok && r < n - 1, vc[j + 1], zero);
+      } else {
+        Ar[j] = csel(ok, cconj(va[j + 1]), mk(1.0, 0.0));
+        Br[j] = csel(ok && r > 0, cconj(vc[j]), zero);
+        Cr[j] = csel(ok && r < n - 1, cconj(vb[j + 2]), zero);
+      }
+      Dr[j] = csel(ok, vd[j + 1], zero);
+    }
+    if constexpr (SRC == SRC_EXPL)
+      bK = csel(r0 + M < n, vb[M + 1], zero);
+    else
+      bK = csel(r0 + M < n, cconj(vc[M]), zero);
+  } else {  // SRC_CN
+    const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
+    const double tau = 0.5 * A.dt;
+    const double idx2 = 1.0 / (dx * dx);
+    const double kap = tau * 0.5 * idx2;
+    const bool given = A.rhs != nullptr;
+    cd vp[M + 2];
+    double vv[M + 2], xv[M + 2];
+    col_fetch<M>((given ? A.rhs : A.psi) + G.base, G.es, r0, n, zero, vp);
+    col_fetch<M>(A.V + G.base, G.es, r0, n, 0.0, vv);
+    if (A.xg) {
+      col_fetch<M>(A.xg + G.base, G.es, r0, n, 0.0, xv);
+    } else {
+#pragma unroll
+      for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
+    }
+    if constexpr (PH == PH_SUBST) {
+      // the neighbouring tiles' edge rows may already hold the new state
+      if (!given) {
+        if (wave == 0 && G.tile > 0) vp[0] = A.halo_in[2 * (G.gt - 1) + 1];
+        if (wave == W - 1 && G.tile + 1 < G.ntile) vp[M + 1] = A.halo_in[2 * (G.gt + 1)];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = r0 + j;
+      const bool ok = r < n;
+      const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
+      Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
+      Br[j] = mk(0.0, (ok && r > 0) ? -kap : 0.0);
+      Cr[j] = mk(0.0, (ok && r < n - 1) ? -kap : 0.0);
+      if (given) {
+        Dr[j] = vp[j + 1];
+      } else {
+        const double w = tau * (idx2 + fma(xv[j + 1], A.E_rhs, A.vscale * vv[j + 1]));
+        const cd p = vp[j + 1];
+        const cd s = cadd(vp[j], vp[j + 2]);
+        Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
+      }
+    }
+    bK = mk(0.0, (r0 + M < n) ? -kap : 0.0);
+    fst = vp[1];
+    lst = vp[M];
+  }
+  if constexpr (PH == PH_REDUCE && SRC == SRC_CN) {
+    if (A.halo_out && live) {
+      if (wave == 0) A.halo_out[2 * G.gt] = fst;
+      if (wave == W - 1) A.halo_out[2 * G.gt + 1] = lst;
+    }
+  }
+  Blk blk;
+  reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
+  sm.blk[wave][lane] = blk;
+  __syncthreads();
+  if (wave == 0) {
+    Blk acc = sm.blk[0][lane];
+    for (int w = 1; w < W; ++w) {
+      const Blk o = sm.blk[w][lane];
+      Node t;
+      merge_into(acc, o, t);
+      *reinterpret_cast<Node*>(&sm.blk[w][lane]) = t;
+    }
+    cd pJ = zero, pM = zero;
+    if constexpr (PH == PH_REDUCE) {
+      if (live) {
+        A.oU[3 * G.gt] = acc.UA;
+        A.oU[3 * G.gt + 1] = acc.UC;
+        A.oU[3 * G.gt + 2] = acc.UD;
+        A.oD[3 * G.gt] = acc.DB;
+        A.oD[3 * G.gt + 1] = acc.DA;
+        A.oD[3 * G.gt + 2] = acc.DD;
+      }
+    } else {
+      if constexpr (PH == PH_SINGLE) {
+        cd ia0 = crecip(acc.UA);
+        cd r = cneg(cmul(acc.DB, ia0));
+        cd aT = cfma(r, acc.UC, cadd(mk(1.0, 0.0), acc.DA));
+        cd dT = cfma(r, acc.UD, acc.DD);
+        pM = cmul(dT, crecip(aT));
+        pJ = cmul(cfms(acc.UC, pM, acc.UD), ia0);
+      } else {
+        pJ = A.psi_if[G.gt];
+        const cd nxt = A.psi_if[(G.tile + 1 < G.ntile) ? G.gt + 1 : G.gt];
+        pM = csel(G.tile + 1 < G.ntile, nxt, zero);
+      }
+      sm.jpsi[0][lane] = pJ;
+      sm.jpsi[W][lane] = pM;
+      cd right = pM;
+      for (int w = W - 1; w >= 1; --w) {
+        const Node t = *reinterpret_cast<const Node*>(&sm.blk[w][lane]);
+        right = cfms(t.C, right, cfms(t.B, pJ, t.dl));
+        sm.jpsi[w][lane] = right;
+      }
+    }
+  }
+  if constexpr (PH != PH_REDUCE) {
+    __syncthreads();
+    const cd pJ = sm.jpsi[wave][lane];
+    const cd pK = sm.jpsi[wave + 1][lane];
+    cd xo[M];
+    ss_block<M>(Br, Cr, Dr, pJ, pK, xo);
+    bool bad = false;
+    const bool acc = (SRC == SRC_CN) && A.acc_pa != nullptr;
+    double part = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = r0 + j;
+      if (live && r < n) {
+        const int64_t e = G.base + r * G.es;
+        A.x[e] = xo[j];
+        bad |= !cfinite(xo[j]);
+        if (acc) {
+          const cd s = cadd(A.acc_pa[e], A.acc_pb[e]);
+          const double q = A.acc_tau * (xo[j].x * s.y - xo[j].y * s.x);
+          if (A.acc_dV) A.acc_dV[e] += A.vscale * q;
+          if (A.xg) part = fma(A.xg[e], q, part);
+        }
+      }
+    }
+    if (__any(bad) && lane == 0) atomicOr(A.status, 1);
+    if (acc && A.acc_part) {
+      sm.wpart[wave][lane] = part;
+      __syncthreads();
+      if (wave == 0 && live) {
+        double t = 0.0;
+        for (int w = 0; w < W; ++w) t += sm.wpart[w][lane];
+        A.acc_part[G.gt] = t;
+      }
+    }
+  }
 }
 
 // Reduced system on the joint lines of a system's tiles (K <= 64 rows, from the two slot

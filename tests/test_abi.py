@@ -53,3 +53,46 @@ def test_null_handle_is_rejected_without_touching_a_gpu():
     assert st == _lib.CN_ERR_INVALID_ARG
     assert lib.cn_destroy(None) == _lib.CN_ERR_INVALID_ARG
     assert lib.cn_create(None, 0) == _lib.CN_ERR_INVALID_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcntri.so not built")
+def test_layout_errors_are_reported_on_the_host():
+    """Error paths of the boundary, forced from the host (no GPU needed)."""
+    import numpy as np
+
+    from paper_2205_00856_amd import _lib
+
+    lib = _lib.lib()
+    BAD, UNSUP, OK = _lib.CN_ERR_INVALID_ARG, _lib.CN_ERR_UNSUPPORTED, _lib.CN_OK
+
+    def L(n=10, batch=1, es=1, bs=10, offsets=None, partition=0, rpt=0):
+        x = _lib.CnLayout()
+        x.n, x.batch, x.elem_stride, x.batch_stride = n, batch, es, bs
+        x.partition, x.rows_per_thread = partition, rpt
+        if offsets is not None:
+            o = np.ascontiguousarray(offsets, dtype=np.int64)
+            x.offsets = o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            x._keep = o
+        return x
+
+    def check(layout):
+        return lib.cn_check_layout(ctypes.byref(layout))
+
+    assert lib.cn_check_layout(None) == BAD
+    assert check(L()) == OK
+    assert check(L(n=0)) == BAD
+    assert check(L(batch=0)) == BAD
+    assert check(L(es=0)) == BAD
+    assert check(L(n=10, batch=3, es=1, bs=5)) == BAD      # systems overlap
+    assert check(L(n=10, batch=3, es=3, bs=1)) == OK       # interleaved
+    assert check(L(n=10, batch=3, es=2, bs=1)) == BAD      # interleaved but overlapping
+    assert check(L(n=10, batch=3, es=1, bs=10)) == OK
+    assert check(L(offsets=[0, 5, 5, 9], batch=3)) == OK
+    assert check(L(offsets=[1, 5, 9], batch=2)) == BAD     # must start at 0
+    assert check(L(offsets=[0, 5, 4], batch=2)) == BAD     # decreasing
+    assert check(L(offsets=[0, 0], batch=1)) == BAD        # no rows at all
+    assert check(L(partition=100)) == BAD                  # not a power of two
+    assert check(L(partition=32)) == BAD
+    assert check(L(partition=1024, rpt=3)) == BAD
+    assert check(L(partition=1024, rpt=16)) == OK
+    assert check(L(n=1 << 41)) == UNSUP

@@ -366,3 +366,36 @@ def test_autotune_keeps_results(gpu, oracle_mod):
     log(rep)
     x2 = cn.solve(ta, tb, tc, td)
     assert rel(x2.cpu().numpy(), xref) <= TOL
+
+
+# ------------------------------------------------------------------ interleaved (column) kernels
+@pytest.mark.parametrize("T,M", [(64, 8), (64, 4), (64, 16), (128, 8)])
+@pytest.mark.parametrize("n,batch", [(1000, 70), (4096, 128), (33, 64)])
+def test_column_kernels(gpu, oracle_mod, T, M, n, batch):
+    torch, cn = gpu
+    log("columns", T, M, n, batch)
+    a, b, c, d = workloads.random_system(n * batch, 7 + n, "herm")
+    A, B, C, D = (v.reshape(n, batch) for v in (a, b, c, d))
+    ref = np.empty((n, batch), np.complex128)
+    lam_ref = np.empty((n, batch), np.complex128)
+    for s in range(batch):
+        ref[:, s] = oracle_mod.thomas(A[:, s], B[:, s], C[:, s], D[:, s])
+        lam_ref[:, s] = oracle_mod.thomas_adjoint(A[:, s], B[:, s], C[:, s], ref[:, s], D[:, s])[0]
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    L = cn.Layout.interleaved(n, batch, partition=T, rows_per_thread=M)
+    assert "columns" in cn.describe_plan(L)
+    x = cn.solve(ta, tb, tc, td, layout=L)
+    assert rel(x.cpu().numpy().reshape(n, batch), ref) <= TOL
+    tx = to_dev(torch, ref.ravel())[0]
+    lam, _, _, _ = cn.solve_adjoint(ta, tb, tc, tx, td, need_abc=False, layout=L)
+    assert rel(lam.cpu().numpy().reshape(n, batch), lam_ref) <= TOL
+    # CN step in place on the interleaved layout (multi-tile halos)
+    g = np.random.default_rng(n)
+    V = g.uniform(-1, 0, (n, batch))
+    psi = g.standard_normal((n, batch)) + 1j * g.standard_normal((n, batch))
+    pref = np.empty_like(psi)
+    for s in range(batch):
+        pref[:, s] = oracle_mod.cn_step(psi[:, s], V[:, s], 0.1, 0.02)
+    tV, tp = to_dev(torch, V.ravel(), psi.ravel())
+    cn.step(tp, tV, 0.1, 0.02, out=tp, layout=L)
+    assert rel(tp.cpu().numpy().reshape(n, batch), pref) <= TOL
