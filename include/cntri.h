@@ -68,7 +68,7 @@ typedef struct {
   int64_t batch_stride;
   const int64_t* offsets;
   int32_t partition;       /* rows per first-level partition (one workgroup tile); a power
-                              of two in [64, 16384]; 0 = automatic                         */
+                              of two in [32, 16384]; 0 = automatic                         */
   int32_t rows_per_thread; /* rows per innermost block (2, 4, 8 or 16); 0 = automatic      */
 } cn_layout;
 
@@ -90,7 +90,7 @@ typedef struct {
 /* Host-only check of a layout (no device access): CN_OK, or the negative status that every
  * entry point would return for it (null layout, batch < 1, n < 1, strides < 1, systems that
  * share elements, offsets not starting at 0 or decreasing, a partition that is not a power of two
- * in [64, 16384], rows_per_thread not in {0, 2, 4, 8, 16}). */
+ * in [32, 16384], rows_per_thread not in {0, 2, 4, 8, 16}). */
 cn_status cn_check_layout(const cn_layout* layout);
 
 cn_status cn_create(cn_handle_t* handle, int device);

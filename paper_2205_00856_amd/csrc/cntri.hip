@@ -134,6 +134,15 @@ int find_cfg(int64_t T, int M) {
 
 constexpr int64_t kSingleMax = 4096;  // largest tile that solves a whole system in one pass
 
+// staggered start of the first round of workgroups: CN_STAGGER=<sleep units> (default 0)
+int stagger_units() {
+  static const int v = [] {
+    const char* e = getenv("CN_STAGGER");
+    return e ? atoi(e) : 0;
+  }();
+  return v;
+}
+
 // XCD-contiguous order of whole-system workgroups (CN_XCD_REMAP=0 turns it off)
 bool xcd_remap_enabled() {
   static const bool on = [] {
@@ -281,7 +290,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     if (bd.bs == 1 && batch >= 64 && bd.es >= batch && src != nsd::SRC_SLOTS && cols_enabled()) {
       int cc = -1;
       if (level == 1 && kn.partition > 0) cc = col_cfg(kn.partition, kn.rpt);
-      if (cc < 0) cc = col_cfg(64, 8);
+      if (cc < 0) cc = col_cfg(32, 8);
       const int64_t T = (int64_t)kColCfgs[cc].M * kColCfgs[cc].W;
       const int64_t K = (n + T - 1) / T, G = K * batch;
       const unsigned gy = (unsigned)((batch + 63) / 64);
@@ -295,7 +304,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       auto add_col = [&](int ph) {
         Launch l;
         l.fn = g_cols[cc][src][ph];
-        l.grid = dim3((unsigned)K, gy);
+        l.grid = dim3((unsigned)(K * gy));
         l.threads = 64 * kColCfgs[cc].W;
         l.a = a;
         l.level = level;
@@ -568,7 +577,7 @@ cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
   if (L->batch < 1) return CN_ERR_INVALID_ARG;
   if (L->partition != 0) {
     const int64_t p = L->partition;
-    if (p < 64 || p > 16384 || (p & (p - 1))) return CN_ERR_INVALID_ARG;
+    if (p < 32 || p > 16384 || (p & (p - 1))) return CN_ERR_INVALID_ARG;
   }
   if (L->rows_per_thread != 0 && L->rows_per_thread != 2 && L->rows_per_thread != 4 &&
       L->rows_per_thread != 8 && L->rows_per_thread != 16)
@@ -740,6 +749,13 @@ cn_status run_plan(cn_handle_t h, Plan* P, const UserArgs& u, hipStream_t s) {
     if (l.o_hout >= 0) a.halo_out = (cd*)(ws + l.o_hout);
     if (l.o_hin >= 0) a.halo_in = (const cd*)(ws + l.o_hin);
     a.status = h->status;
+    if (stagger_units() > 0 && a.stagger == 0) {
+      int per_cu = 1;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, l.fn, l.threads, 0) != hipSuccess)
+        per_cu = 1;
+      a.stagger = stagger_units();
+      a.stagger_round = per_cu * num_cus();
+    }
     void* params[] = {&a};
     if (hipLaunchKernel(l.fn, l.grid, dim3(l.threads), params, 0, s) != hipSuccess)
       return CN_ERR_HIP;

@@ -59,6 +59,8 @@ struct KArgs {
   double* acc_part;
   double acc_tau;
   int64_t batch;          // uniform batch size (column kernel)
+  int stagger;            // first-round workgroups with odd (id / 8) start ~stagger*3.4 us late
+  int stagger_round;      // number of workgroups in the first round (resident at once)
 };
 
 struct Geo {
@@ -493,9 +495,21 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
 }
 
 // One workgroup = one tile of T = 64*W*M rows of one system.
+// Offsets the phases of neighbouring CUs: half of the first round of workgroups starts late,
+// so that loads of some CUs overlap arithmetic of others instead of running in lockstep.
+__device__ __forceinline__ void stagger_start(const KArgs& A) {
+  if (A.stagger > 0) {
+    const int64_t id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (id < A.stagger_round && ((id >> 3) & 1)) {
+      for (int i = 0; i < A.stagger; ++i) __builtin_amdgcn_s_sleep(127);
+    }
+  }
+}
+
 template <int M, int W, int SRC, int PH>
 __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
   __shared__ TileSmem<M, W> sm;
+  stagger_start(A);
   const Geo G = geometry(A);
   tile_run<M, W, SRC, PH>(A, G, sm);
 }
@@ -530,17 +544,22 @@ __device__ __forceinline__ void col_fetch(const T* g, int64_t es, int64_t r0, in
 template <int M, int W, int SRC, int PH>
 __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   __shared__ ColSmem<M, W> sm;
+  stagger_start(A);
   constexpr int64_t T = (int64_t)W * M;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t sys = (int64_t)blockIdx.y * 64 + lane;
+  // consecutive workgroups take neighbouring column groups of the same rows, so the rows that
+  // run concurrently are read as long contiguous runs
+  const int64_t ncg = (A.batch + 63) / 64;
+  const int64_t cg = (int64_t)blockIdx.x % ncg;
+  const int64_t sys = cg * 64 + lane;
   const bool live = sys < A.batch;
   Geo G;
   G.sys = live ? sys : A.batch - 1;
   G.n = A.n;
   G.es = A.es;
   G.base = G.sys * A.bs;
-  G.tile = blockIdx.x;
+  G.tile = (int64_t)blockIdx.x / ncg;
   G.ntile = A.ntiles;
   G.gt = G.sys * A.ntiles + G.tile;
   const int64_t r0 = G.tile * T + (int64_t)wave * M;

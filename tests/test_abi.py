@@ -92,7 +92,7 @@ def test_layout_errors_are_reported_on_the_host():
     assert check(L(offsets=[0, 5, 4], batch=2)) == BAD     # decreasing
     assert check(L(offsets=[0, 0], batch=1)) == BAD        # no rows at all
     assert check(L(partition=100)) == BAD                  # not a power of two
-    assert check(L(partition=32)) == BAD
+    assert check(L(partition=16)) == BAD
     assert check(L(partition=1024, rpt=3)) == BAD
     assert check(L(partition=1024, rpt=16)) == OK
     assert check(L(n=1 << 41)) == UNSUP
