@@ -134,15 +134,6 @@ int find_cfg(int64_t T, int M) {
 
 constexpr int64_t kSingleMax = 4096;  // largest tile that solves a whole system in one pass
 
-// staggered start of the first round of workgroups: CN_STAGGER=<sleep units> (default 0)
-int stagger_units() {
-  static const int v = [] {
-    const char* e = getenv("CN_STAGGER");
-    return e ? atoi(e) : 0;
-  }();
-  return v;
-}
-
 // XCD-contiguous order of whole-system workgroups (CN_XCD_REMAP=0 turns it off)
 bool xcd_remap_enabled() {
   static const bool on = [] {
@@ -749,13 +740,6 @@ cn_status run_plan(cn_handle_t h, Plan* P, const UserArgs& u, hipStream_t s) {
     if (l.o_hout >= 0) a.halo_out = (cd*)(ws + l.o_hout);
     if (l.o_hin >= 0) a.halo_in = (const cd*)(ws + l.o_hin);
     a.status = h->status;
-    if (stagger_units() > 0 && a.stagger == 0) {
-      int per_cu = 1;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, l.fn, l.threads, 0) != hipSuccess)
-        per_cu = 1;
-      a.stagger = stagger_units();
-      a.stagger_round = per_cu * num_cus();
-    }
     void* params[] = {&a};
     if (hipLaunchKernel(l.fn, l.grid, dim3(l.threads), params, 0, s) != hipSuccess)
       return CN_ERR_HIP;

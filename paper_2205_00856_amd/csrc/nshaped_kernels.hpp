@@ -59,8 +59,6 @@ struct KArgs {
   double* acc_part;
   double acc_tau;
   int64_t batch;          // uniform batch size (column kernel)
-  int stagger;            // first-round workgroups with odd (id / 8) start ~stagger*3.4 us late
-  int stagger_round;      // number of workgroups in the first round (resident at once)
 };
 
 struct Geo {
@@ -495,21 +493,9 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
 }
 
 // One workgroup = one tile of T = 64*W*M rows of one system.
-// Offsets the phases of neighbouring CUs: half of the first round of workgroups starts late,
-// so that loads of some CUs overlap arithmetic of others instead of running in lockstep.
-__device__ __forceinline__ void stagger_start(const KArgs& A) {
-  if (A.stagger > 0) {
-    const int64_t id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (id < A.stagger_round && ((id >> 3) & 1)) {
-      for (int i = 0; i < A.stagger; ++i) __builtin_amdgcn_s_sleep(127);
-    }
-  }
-}
-
 template <int M, int W, int SRC, int PH>
 __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
   __shared__ TileSmem<M, W> sm;
-  stagger_start(A);
   const Geo G = geometry(A);
   tile_run<M, W, SRC, PH>(A, G, sm);
 }
@@ -544,7 +530,6 @@ __device__ __forceinline__ void col_fetch(const T* g, int64_t es, int64_t r0, in
 template <int M, int W, int SRC, int PH>
 __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   __shared__ ColSmem<M, W> sm;
-  stagger_start(A);
   constexpr int64_t T = (int64_t)W * M;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
