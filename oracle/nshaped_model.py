@@ -168,3 +168,78 @@ def uniform_joints(n, p):
     J = list(range(0, n - 1, p))
     J.append(n - 1)
     return J
+
+
+def rd_form_block(a, b, c, d):
+    """One block J = 0 .. K = m of the rows (a, b, c, d), reduced the way a lane of the GPU path
+    does it (the RD form):
+
+      RD   row i = 1 .. m-1 is eliminated downwards and scaled by its pivot, giving
+           psi_i + beta_i psi_J + gamma_i psi_{i+1} = delta_i   (Table 1, RD);
+      JD   row K takes r = -b_K times RD row m-1 (Table 1, JD);
+      RU   is needed only for JU, which uses row J+1 after RU:  psi_1 + bf psi_J + gf psi_K = df.
+           Substituting the RD rows into one another gives that row as a forward sum,
+           psi_1 = sum_k P_k (delta_k - beta_k psi_J) + P_m psi_K,  P_1 = 1, P_{k+1} = -gamma_k P_k,
+           so bf = sum_k P_k beta_k, df = sum_k P_k delta_k, gf = -P_m;
+      JU   row J takes r = -c_J times that row (Table 1, JU).
+
+    Returns (UA, UC, UD, DB, DA, DD, delta) with
+      UA psi_J + UC psi_K = UD          (row J with its own coefficients folded in),
+      DB psi_J + DA psi_K = DD          (what the block adds to row K, besides row K itself),
+    and the RD right-hand sides delta_1 .. delta_{m-1}."""
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    c = np.asarray(c, np.complex128)
+    d = np.asarray(d, np.complex128)
+    m = a.shape[0] - 1
+    if m < 2:
+        return a[0], c[0], d[0], b[m], 0.0, 0.0, np.zeros(0, np.complex128)
+    beta = np.zeros(m, np.complex128)
+    gamma = np.zeros(m, np.complex128)
+    delta = np.zeros(m, np.complex128)
+    piv = a[1]
+    beta[1], gamma[1], delta[1] = b[1] / piv, c[1] / piv, d[1] / piv
+    for i in range(2, m):
+        piv = a[i] - b[i] * gamma[i - 1]
+        beta[i] = -b[i] * beta[i - 1] / piv
+        gamma[i] = c[i] / piv
+        delta[i] = (d[i] - b[i] * delta[i - 1]) / piv
+    P = 1.0 + 0.0j
+    bf = df = 0.0j
+    for k in range(1, m):
+        bf += P * beta[k]
+        df += P * delta[k]
+        P = -gamma[k] * P
+    gf = -P
+    UA = a[0] - c[0] * bf
+    UC = -c[0] * gf
+    UD = d[0] - c[0] * df
+    DB = -b[m] * beta[m - 1]
+    DA = -b[m] * gamma[m - 1]
+    DD = -b[m] * delta[m - 1]
+    return UA, UC, UD, DB, DA, DD, delta[1:]
+
+
+def rd_form_substitute(a, b, c, delta, psi_J, psi_K):
+    """SS of the RD form: given psi_J and psi_K, the interior rows of the block follow from the
+    RD rows by substitution upwards, psi_i = delta_i - beta_i psi_J - gamma_i psi_{i+1},
+    i = m-1 .. 1 (beta_i, gamma_i recomputed from the matrix as in rd_form_block)."""
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    c = np.asarray(c, np.complex128)
+    m = a.shape[0] - 1
+    psi = np.zeros(m + 1, np.complex128)
+    psi[0], psi[m] = psi_J, psi_K
+    if m < 2:
+        return psi
+    beta = np.zeros(m, np.complex128)
+    gamma = np.zeros(m, np.complex128)
+    piv = a[1]
+    beta[1], gamma[1] = b[1] / piv, c[1] / piv
+    for i in range(2, m):
+        piv = a[i] - b[i] * gamma[i - 1]
+        beta[i] = -b[i] * beta[i - 1] / piv
+        gamma[i] = c[i] / piv
+    for i in range(m - 1, 0, -1):
+        psi[i] = delta[i - 1] - beta[i] * psi_J - gamma[i] * psi[i + 1]
+    return psi

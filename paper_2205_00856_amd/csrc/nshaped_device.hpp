@@ -145,6 +145,101 @@ __device__ __forceinline__ void reduce_block(cd (&A)[M], cd (&Bt)[M], cd (&Ct)[M
   }
 }
 
+// Off-diagonals of a Crank-Nicolson block: rows J .. J+M-1 of a system of n rows, each coupled
+// to its neighbours by -i kappa, except across the system ends and on padding rows past n.
+struct CnEdges {
+  int64_t J, n;
+  double kap;
+  // imaginary parts of the sub- and super-diagonal of local row i
+  __device__ __forceinline__ double b(int i) const {
+    const int64_t r = J + i;
+    return (r < n && r > 0) ? -kap : 0.0;
+  }
+  __device__ __forceinline__ double c(int i) const {
+    const int64_t r = J + i;
+    return (r < n - 1) ? -kap : 0.0;
+  }
+};
+
+// Level 1 with substitution along the RD rows (Crank-Nicolson blocks, M >= 2).  ay holds the
+// imaginary parts of the diagonal (real parts 1), e the off-diagonals, bK the imaginary part of
+// the sub-diagonal of the next joint line.  RD and JD are reduce_block's operations; rows
+// 1..M-1 keep their RD form
+//     psi_i + beta_i psi_J + gamma_i psi_{i+1} = delta_i
+// with only delta_i retained (in D): beta_i and gamma_i depend on the matrix alone and are
+// recomputed by ss_block_rd, so a lane carries one complex value per row across the nesting
+// levels instead of three.  RU only has to deliver the final row J+1 for JU; unrolled, that row
+// is the forward sum  psi_{J+1} = sum_k P_k (delta_k - beta_k psi_J) + P_M psi_K  with P_1 = 1,
+// P_{k+1} = -gamma_k P_k, accumulated here during RD, so no RD row is held for a backward pass.
+template <int M>
+__device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const CnEdges& e,
+                                                cd (&D)[M], double bK, Blk& o) {
+  static_assert(M >= 2, "blocks with interior rows");
+  cd beta, gam;
+  {
+    const cd ia = crecip(mk(1.0, ay[1]));
+    beta = cimul(e.b(1), ia);
+    gam = cimul(e.c(1), ia);
+    D[1] = cmul(D[1], ia);
+  }
+  cd fb = beta, fd = D[1], P = cneg(gam);
+#pragma unroll
+  for (int i = 2; i < M; ++i) {
+    const double bi = e.b(i);
+    const cd a = csub(mk(1.0, ay[i]), cimul(bi, gam));
+    const cd d = csub(D[i], cimul(bi, D[i - 1]));
+    const cd b = cneg(cimul(bi, beta));
+    const cd ia = crecip(a);
+    beta = cmul(b, ia);
+    gam = cimul(e.c(i), ia);
+    D[i] = cmul(d, ia);
+    fb = cfma(P, beta, fb);
+    fd = cfma(P, D[i], fd);
+    P = cneg(cmul(P, gam));
+  }
+  // JD at K (row K-1 scaled)
+  o.DB = cneg(cimul(bK, beta));
+  o.DA = cneg(cimul(bK, gam));
+  o.DD = cneg(cimul(bK, D[M - 1]));
+  // JU at J with row J+1 final: beta = fb, gamma = -P, delta = fd
+  const double c0 = e.c(0);
+  o.UA = csub(mk(1.0, ay[0]), cimul(c0, fb));
+  o.UD = csub(D[0], cimul(c0, fd));
+  o.UC = cimul(c0, P);
+}
+
+// SS along the RD rows of reduce_block_rd: with psi_J and psi_K = psi_{J+M} known,
+//   psi_i = delta_i - beta_i psi_J - gamma_i psi_{i+1},  i = M-1 down to 1,
+// where beta_i and gamma_i are recomputed from ay and e with reduce_block_rd's operations.
+template <int M>
+__device__ __forceinline__ void ss_block_rd(const double (&ay)[M], const CnEdges& e,
+                                            const cd (&D)[M], cd pJ, cd pK, cd (&x)[M]) {
+  cd gam[M], dp[M];
+  cd beta;
+  {
+    const cd ia = crecip(mk(1.0, ay[1]));
+    beta = cimul(e.b(1), ia);
+    gam[1] = cimul(e.c(1), ia);
+    dp[1] = cfms(beta, pJ, D[1]);
+  }
+#pragma unroll
+  for (int i = 2; i < M; ++i) {
+    const double bi = e.b(i);
+    const cd a = csub(mk(1.0, ay[i]), cimul(bi, gam[i - 1]));
+    const cd ia = crecip(a);
+    beta = cmul(cneg(cimul(bi, beta)), ia);
+    gam[i] = cimul(e.c(i), ia);
+    dp[i] = cfms(beta, pJ, D[i]);
+  }
+  x[0] = pJ;
+  cd nx = pK;
+#pragma unroll
+  for (int i = M - 1; i >= 1; --i) {
+    nx = cfms(gam[i], nx, dp[i]);
+    x[i] = nx;
+  }
+}
+
 // SS on the lane's block: psi_i = delta_i - beta_i psi_J - gamma_i psi_K.
 template <int M>
 __device__ __forceinline__ void ss_block(const cd (&Bt)[M], const cd (&Ct)[M], const cd (&D)[M],

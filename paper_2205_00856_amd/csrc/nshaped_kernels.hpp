@@ -172,23 +172,54 @@ __device__ __forceinline__ void cn_fetch(const KArgs& A, const Geo& G, int64_t w
   }
 }
 
+// Magnitude of the off-diagonals of T = 1 + i tau H: tau / (2 dx^2) with tau = dt / 2.
+__device__ __forceinline__ double cn_kappa(double dt, double dx) {
+  return (0.5 * dt) * 0.5 * (1.0 / (dx * dx));
+}
+
 // Rows of T = 1 + i tau H and the explicit half-step d = (1 - i tau H) psi (Sec. 2, Eq. (3)),
 // fused into the reduction (Sec. 5.3).  The off-diagonals are -i kappa (pure imaginary).
+// vp holds psi at rows J-1 .. J+M of this lane (zero outside the system), vv and xv hold V and
+// xgrid at the same rows (only J .. J+M-1 are read).
+template <int M>
+__device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx, int64_t J,
+                                        const cd (&vp)[M + 2], const double (&vv)[M + 2],
+                                        const double (&xv)[M + 2], cd (&Ar)[M], cd (&Br)[M],
+                                        cd (&Cr)[M], cd (&Dr)[M], cd& bK) {
+  const int64_t n = G.n;
+  const double tau = 0.5 * A.dt;
+  const double idx2 = 1.0 / (dx * dx);
+  const double kap = cn_kappa(A.dt, dx);
+  const bool given = A.rhs != nullptr;
+  const cd zero = czero();
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int64_t r = J + j;
+    const bool ok = r < n;
+    const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
+    Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
+    Br[j] = mk(0.0, (ok && r > 0) ? -kap : 0.0);
+    Cr[j] = mk(0.0, (ok && r < n - 1) ? -kap : 0.0);
+    if (given) {
+      Dr[j] = vp[j + 1];
+    } else {
+      const double w = tau * (idx2 + fma(xv[j + 1], A.E_rhs, A.vscale * vv[j + 1]));
+      const cd p = vp[j + 1];
+      const cd s = cadd(vp[j], vp[j + 2]);
+      Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
+    }
+  }
+  bK = mk(0.0, (J + M < n) ? -kap : 0.0);
+}
+
 template <int M, int W, int PH, bool XG>
 __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
                                          int64_t J, int lane, int wave, CnRaw<M, XG>& raw,
                                          cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
                                          cd& bK, cd& first_state, cd& last_state) {
-  const int64_t n = G.n;
-  const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
-  const double tau = 0.5 * A.dt;
-  const double idx2 = 1.0 / (dx * dx);
-  const double kap = tau * 0.5 * idx2;
-  const bool given = A.rhs != nullptr;
-  const cd zero = czero();
   if constexpr (PH == PH_SUBST) {
     // the neighbours' edge rows may already hold the new state: take the saved copies
-    if (!given) {
+    if (A.rhs == nullptr) {
       if (wave == 0 && lane == 0 && G.tile > 0) raw.hp = A.halo_in[2 * (G.gt - 1) + 1];
       if (wave == W - 1 && lane == 1 && G.tile + 1 < G.ntile) raw.hp = A.halo_in[2 * (G.gt + 1)];
     }
@@ -209,24 +240,7 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
 #pragma unroll
     for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
   }
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    const int64_t r = J + j;
-    const bool ok = r < n;
-    const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
-    Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
-    Br[j] = mk(0.0, (ok && r > 0) ? -kap : 0.0);
-    Cr[j] = mk(0.0, (ok && r < n - 1) ? -kap : 0.0);
-    if (given) {
-      Dr[j] = vp[j + 1];
-    } else {
-      const double w = tau * (idx2 + fma(xv[j + 1], A.E_rhs, A.vscale * vv[j + 1]));
-      const cd p = vp[j + 1];
-      const cd s = cadd(vp[j], vp[j + 2]);
-      Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
-    }
-  }
-  bK = mk(0.0, (J + M < n) ? -kap : 0.0);
+  cn_rows<M>(A, G, A.dxs ? A.dxs[G.sys] : A.dx, J, vp, vv, xv, Ar, Br, Cr, Dr, bK);
   first_state = vp[1];
   last_state = vp[M];
 }
@@ -351,11 +365,15 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
   cd* g = A.x + G.base;
   const bool acc = (SRC == SRC_CN) && A.acc_pa != nullptr;
   double part = 0.0;
+  // recompute the row addresses here instead of keeping those of the loads alive across the
+  // whole tile (the empty asm hides that they are equal)
+  int sl = lane;
+  asm volatile("" : "+v"(sl));
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const int64_t r = w0 + 64 * k + lane;
+    const int64_t r = w0 + 64 * k + sl;
     if (r < G.n) {
-      const cd v = buf[S::addr(1 + 64 * k + lane)];
+      const cd v = buf[S::addr(1 + 64 * k + sl)];
       const int64_t e = G.base + r * G.es;
       g[r * G.es] = v;
       if (acc) {
@@ -407,13 +425,24 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
   tile_finish<M, W, SRC, PH>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
 }
 
-// Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
+// Everything after the rows of the tile are assembled up to SS: level-1 sweeps, nesting, top,
+// substitution.  wnode holds this wavefront's 64 tree nodes; sm provides wblk, xnode and wpsi for
+// the levels across wavefronts.  For PH != PH_REDUCE, xo returns this lane's rows J .. J+M-1.
+// Crank-Nicolson tiles that substitute (M >= 4) take reduce_block_rd / ss_block_rd: keep holds
+// 64 * M doubles of this wavefront's LDS for the diagonals between the two, and kap is the
+// off-diagonal magnitude (tau / (2 dx^2)) that ss_block_rd recomputes the couplings from.
 template <int M, int W, int SRC, int PH>
-__device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
-                                            cd* buf, int64_t w0, int64_t J, int lane, int wave,
-                                            cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
-                                            cd bK, cd fst, cd lst) {
+struct RdSubst {
+  static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M >= 4;
+};
+
+template <int M, int W, int SRC, int PH, typename SM>
+__device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, Node* wnode,
+                                          double* keep, double kap, int64_t J, int lane, int wave,
+                                          cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
+                                          cd bK, cd fst, cd lst, cd (&xo)[M]) {
   constexpr int LW = Log2<W>::v;
+  constexpr bool RD = RdSubst<M, W, SRC, PH>::on;
   if constexpr (PH == PH_REDUCE && SRC == SRC_CN) {
     if (A.halo_out) {
       if (wave == 0 && lane == 0) A.halo_out[2 * G.gt] = fst;
@@ -422,10 +451,18 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
   }
 
   Blk blk;
-  reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
-  // the staging buffer is idle between the loads and the stores: it holds the nodes
-  Node* wnode = reinterpret_cast<Node*>(buf);
+  const CnEdges edges{J, G.n, kap};
   wave_sync();
+  if constexpr (RD) {
+    double ay[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) ay[j] = Ar[j].y;
+#pragma unroll
+    for (int j = 1; j < M; ++j) keep[j * 64 + lane] = ay[j];
+    reduce_block_rd<M>(ay, edges, Dr, bK.y, blk);
+  } else {
+    reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
+  }
   tree_up<6>(blk, wnode, lane);
   if constexpr (W > 1) {
     if (lane == 0) sm.wblk[wave] = blk;
@@ -473,15 +510,51 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
       pM = sm.wpsi[wave][1];
     }
     tree_down<6>(pJ, pM, wnode, lane);
-
-    cd xo[M];
-    ss_block<M>(Br, Cr, Dr, pJ, pM, xo);
-
-    bool bad = false;
+    if constexpr (RD) {
+      double ay[M];
+      ay[0] = 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) bad |= (J + j < G.n) && !cfinite(xo[j]);
-    if (__any(bad) && lane == 0) atomicOr(A.status, 1);
+      for (int j = 1; j < M; ++j) ay[j] = keep[j * 64 + lane];
+      ss_block_rd<M>(ay, edges, Dr, pJ, pM, xo);
+    } else {
+      ss_block<M>(Br, Cr, Dr, pJ, pM, xo);
+    }
+  }
+}
 
+// Raises the status flag when a row of this lane is not finite.
+template <int M>
+__device__ __forceinline__ void check_rows(const KArgs& A, const Geo& G, int64_t J, int lane,
+                                           const cd (&xo)[M]) {
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < M; ++j) bad |= (J + j < G.n) && !cfinite(xo[j]);
+  if (__any(bad) && lane == 0) atomicOr(A.status, 1);
+}
+
+// Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
+template <int M, int W, int SRC, int PH>
+__device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+                                            cd* buf, int64_t w0, int64_t J, int lane, int wave,
+                                            cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
+                                            cd bK, cd fst, cd lst) {
+  // the staging buffer is idle between the loads and the stores: it holds the nodes and, for
+  // substitution along the RD rows, the diagonals after them
+  Node* wnode = reinterpret_cast<Node*>(buf);
+  double* keep = reinterpret_cast<double*>(wnode + 64);
+  static_assert(!RdSubst<M, W, SRC, PH>::on ||
+                    sizeof(Node) * 64 + sizeof(double) * 64 * M <= sizeof(cd) * Stage<M>::QS,
+                "nodes and diagonals fit the stage buffer");
+  double kap = 0.0;
+  if constexpr (RdSubst<M, W, SRC, PH>::on) {
+    const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
+    kap = cn_kappa(A.dt, dx);
+  }
+  cd xo[M];
+  tile_core<M, W, SRC, PH>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
+                           lst, xo);
+  if constexpr (PH != PH_REDUCE) {
+    check_rows<M>(A, G, J, lane, xo);
     if constexpr (SRC == SRC_SLOTS) {
 #pragma unroll
       for (int j = 0; j < M; ++j)

@@ -230,6 +230,53 @@ def test_adi_step_small(gpu, oracle_mod):
     assert rel(tpsi.cpu().numpy().reshape(ny, nx), ref) <= TOL
 
 
+# ------------------------------------------------------------------ uniform batches of CN steps
+# Contiguous CN steps of many systems of 1024 < n <= 4096 (whole systems in one workgroup, the
+# ADI x-sweep path): per-system dx, ragged n (whole lane blocks past the end at n = 1032, 4000),
+# in place, and V 8 bytes off a 16-byte boundary.
+@pytest.mark.parametrize("n,batch", [(4096, 600), (2048, 1100), (1032, 1030), (4000, 520)])
+def test_cn_step_uniform_batch(gpu, oracle_mod, n, batch):
+    torch, cn = gpu
+    log("cn_step uniform batch", n, batch)
+    dt = 0.02
+    rng = np.random.default_rng(1234 + n)
+    psi = workloads.complex_normal(rng, n * batch)
+    V = rng.uniform(-2.0, 2.0, n * batch)
+    dxs = rng.uniform(0.05, 0.2, batch)
+    offs = np.arange(batch + 1, dtype=np.int64) * n
+    ref = oracle_mod.cn_step_batched(offs, psi, V, dxs, dt, 8)
+    L = cn.Layout.contiguous(n, batch)
+    assert "single" in cn.describe_plan(L, cn_mode=True)
+    tV, tpsi, tdx = to_dev(torch, V, psi, dxs)
+    out = cn.step(tpsi, tV, 0.0, dt, dx_per_system=tdx, layout=L)
+    assert rel(out.cpu().numpy(), ref) <= TOL
+    cn.step(tpsi, tV, 0.0, dt, dx_per_system=tdx, out=tpsi, layout=L)  # in place
+    assert torch.equal(tpsi, out)
+    Vpad = torch.empty(n * batch + 1, dtype=torch.float64, device="cuda")
+    Vpad[1:] = tV
+    out2 = cn.step(to_dev(torch, psi)[0], Vpad[1:], 0.0, dt, dx_per_system=tdx, layout=L)
+    assert rel(out2.cpu().numpy(), ref) <= TOL
+
+
+def test_cn_step_uniform_batch_repeated(gpu, oracle_mod):
+    """Five chained in-place steps of 4096 x 4096 rows at one dx (the ADI x-sweep shape at
+    half the lines), against the oracle stepping each line."""
+    torch, cn = gpu
+    n, batch, dx, dt = 4096, 2048, 0.1, 0.01
+    rng = np.random.default_rng(99)
+    psi = workloads.complex_normal(rng, n * batch)
+    V = rng.uniform(0.0, 5.0, n * batch)
+    offs = np.arange(batch + 1, dtype=np.int64) * n
+    ref = psi
+    for _ in range(5):
+        ref = oracle_mod.cn_step_batched(offs, ref, V, np.full(batch, dx), dt, 8)
+    L = cn.Layout.contiguous(n, batch)
+    tV, tpsi = to_dev(torch, V, psi)
+    for _ in range(5):
+        cn.step(tpsi, tV, dx, dt, out=tpsi, layout=L)
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+
+
 # ------------------------------------------------------------------ adjoint
 @pytest.mark.parametrize("n", [7, 4096, 100_001])
 def test_solve_adjoint(gpu, oracle_mod, n):

@@ -75,3 +75,35 @@ def test_cn_pivots_have_real_part_at_least_one(oracle_mod):
     x, piv = nm.solve(a, b, c, d, J, [nm.uniform_joints(len(J), 4)], return_pivots=True)
     assert min(np.real(piv)) >= 1.0 - 1e-12
     assert rel(x, oracle_mod.thomas(a, b, c, d)) <= 1e-13
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 8, 17])
+@pytest.mark.parametrize("kind", ["dd", "herm", "cn"])
+def test_rd_form_slots_equal_table1_stages(oracle_mod, m, kind):
+    """The RD form of one block (RD, JD, the forward sum standing for RU, JU) produces the same
+    two joint rows as Table 1's four stages on that block, and its substitution along the RD
+    rows gives the interior solution."""
+    n = m + 1
+    if kind == "cn":
+        w = workloads.plain_1d(n=n)
+        a, b, c = oracle_mod.cn_coeffs(w["V"], w["dx"], w["dt"])
+        d = oracle_mod.cn_rhs(w["psi0"], w["V"], w["dx"], w["dt"])
+    else:
+        a, b, c, d = workloads.random_system(n, 500 + m, kind)
+    b = np.array(b, np.complex128)
+    c = np.array(c, np.complex128)
+    b[0] = 0.0
+    c[-1] = 0.0
+    ra, rb, rc, rd_, _ = nm._stages_one_level(np.array(a, np.complex128), b.copy(), c.copy(),
+                                              np.array(d, np.complex128), [0, m])
+    UA, UC, UD, DB, DA, DD, delta = nm.rd_form_block(a, b, c, d)
+    scale = np.max(np.abs([ra[0], rc[0], rd_[0], rb[1], ra[1], rd_[1]]))
+    got = np.array([UA, UC, UD, DB, a[m] + DA, d[m] + DD])
+    want = np.array([ra[0], rc[0], rd_[0], rb[1], ra[1], rd_[1]])
+    assert np.max(np.abs(got - want)) <= 1e-13 * scale
+    # the 2x2 joint system, then the interior rows by substitution along the RD rows
+    M2 = np.array([[UA, UC], [DB, a[m] + DA]])
+    psiJK = np.linalg.solve(M2, np.array([UD, d[m] + DD]))
+    psi = nm.rd_form_substitute(a, b, c, delta, psiJK[0], psiJK[1])
+    ref = oracle_mod.thomas(a, b, c, d)
+    assert rel(psi, ref) <= 1e-13
