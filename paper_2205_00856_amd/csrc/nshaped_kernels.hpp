@@ -4,6 +4,8 @@
 #pragma once
 #include "nshaped_device.hpp"
 
+#include <type_traits>
+
 namespace nsd {
 
 enum Src : int {
@@ -428,12 +430,14 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 // Everything after the rows of the tile are assembled up to SS: level-1 sweeps, nesting, top,
 // substitution.  wnode holds this wavefront's 64 tree nodes; sm provides wblk, xnode and wpsi for
 // the levels across wavefronts.  For PH != PH_REDUCE, xo returns this lane's rows J .. J+M-1.
-// Crank-Nicolson tiles that substitute (M >= 4) take reduce_block_rd / ss_block_rd: keep holds
-// 64 * M doubles of this wavefront's LDS for the diagonals between the two, and kap is the
-// off-diagonal magnitude (tau / (2 dx^2)) that ss_block_rd recomputes the couplings from.
+// Crank-Nicolson tiles of M = 8 rows per lane that substitute take reduce_block_rd /
+// ss_block_rd (fewer registers, so two 512-lane workgroups fit a CU; with fewer rows per lane
+// the extra arithmetic buys no occupancy): keep holds 64 * M doubles of this wavefront's LDS for
+// the diagonals between the two, and kap is the off-diagonal magnitude (tau / (2 dx^2)) that
+// ss_block_rd recomputes the couplings from.
 template <int M, int W, int SRC, int PH>
 struct RdSubst {
-  static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M >= 4;
+  static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M == 8;
 };
 
 template <int M, int W, int SRC, int PH, typename SM>
@@ -587,17 +591,26 @@ struct ColSmem {
   double wpart[W][64];  // adjoint partial sums per wavefront and system
 };
 
-// Rows r0-1 .. r0+M of one system at element base + r*es, loaded per lane (clamped, selected).
+// Rows r0-1 .. r0+M of this lane's system, loaded clamped and selected.  The row base
+// g + r*es is the same for the whole wavefront (r0 is uniform), the lane adds its byte offset
+// bofs: the loads take a scalar base and one 32-bit vector offset, no 64-bit address per row.
 template <int M, typename T>
-__device__ __forceinline__ void col_fetch(const T* g, int64_t es, int64_t r0, int64_t n, T fill,
-                                          T (&v)[M + 2]) {
+__device__ __forceinline__ void col_fetch(const T* g, uint32_t bofs, int64_t es, int64_t r0,
+                                          int64_t n, T fill, T (&v)[M + 2]) {
 #pragma unroll
   for (int j = 0; j < M + 2; ++j) {
     const int64_t r = r0 - 1 + j;
     const int64_t rc = r < 0 ? 0 : (r < n ? r : n - 1);
-    const T t = g[rc * es];
+    const T t = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(g + rc * es) + bofs);
     v[j] = sel(r >= 0 && r < n, t, fill);
   }
+}
+
+// element (row r) of this lane's system in an interleaved array: scalar row base + lane offset
+template <typename T>
+__device__ __forceinline__ T& col_at(T* g, uint32_t bofs, int64_t r, int64_t es) {
+  typedef typename std::conditional<std::is_const<T>::value, const char, char>::type B;
+  return *reinterpret_cast<T*>(reinterpret_cast<B*>(g + r * es) + bofs);
 }
 
 template <int M, int W, int SRC, int PH>
@@ -605,13 +618,18 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   __shared__ ColSmem<M, W> sm;
   constexpr int64_t T = (int64_t)W * M;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // consecutive workgroups take neighbouring column groups of the same rows, so the rows that
   // run concurrently are read as long contiguous runs
   const int64_t ncg = (A.batch + 63) / 64;
   const int64_t cg = (int64_t)blockIdx.x % ncg;
   const int64_t sys = cg * 64 + lane;
   const bool live = sys < A.batch;
+  // the batch stride is 1: system s starts at element s; lanes address their system as the
+  // column group's first element plus a byte offset
+  const int64_t c0 = cg * 64;
+  const uint32_t ob16 = (uint32_t)((live ? lane : A.batch - 1 - c0) * 16);
+  const uint32_t ob8 = ob16 / 2;
   Geo G;
   G.sys = live ? sys : A.batch - 1;
   G.n = A.n;
@@ -626,10 +644,10 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst = zero, lst = zero;
   if constexpr (SRC == SRC_EXPL || SRC == SRC_EXPL_CT) {
     cd va[M + 2], vb[M + 2], vc[M + 2], vd[M + 2];
-    col_fetch<M>(A.a + G.base, G.es, r0, n, mk(1.0, 0.0), va);
-    col_fetch<M>(A.b + G.base, G.es, r0, n, zero, vb);
-    col_fetch<M>(A.c + G.base, G.es, r0, n, zero, vc);
-    col_fetch<M>(A.d + G.base, G.es, r0, n, zero, vd);
+    col_fetch<M>(A.a + c0, ob16, G.es, r0, n, mk(1.0, 0.0), va);
+    col_fetch<M>(A.b + c0, ob16, G.es, r0, n, zero, vb);
+    col_fetch<M>(A.c + c0, ob16, G.es, r0, n, zero, vc);
+    col_fetch<M>(A.d + c0, ob16, G.es, r0, n, zero, vd);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const int64_t r = r0 + j;
@@ -653,14 +671,14 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
     const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
     const double tau = 0.5 * A.dt;
     const double idx2 = 1.0 / (dx * dx);
-    const double kap = tau * 0.5 * idx2;
+    const double kap = cn_kappa(A.dt, dx);
     const bool given = A.rhs != nullptr;
     cd vp[M + 2];
     double vv[M + 2], xv[M + 2];
-    col_fetch<M>((given ? A.rhs : A.psi) + G.base, G.es, r0, n, zero, vp);
-    col_fetch<M>(A.V + G.base, G.es, r0, n, 0.0, vv);
+    col_fetch<M>((given ? A.rhs : A.psi) + c0, ob16, G.es, r0, n, zero, vp);
+    col_fetch<M>(A.V + c0, ob8, G.es, r0, n, 0.0, vv);
     if (A.xg) {
-      col_fetch<M>(A.xg + G.base, G.es, r0, n, 0.0, xv);
+      col_fetch<M>(A.xg + c0, ob8, G.es, r0, n, 0.0, xv);
     } else {
 #pragma unroll
       for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
@@ -757,14 +775,13 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
     for (int j = 0; j < M; ++j) {
       const int64_t r = r0 + j;
       if (live && r < n) {
-        const int64_t e = G.base + r * G.es;
-        A.x[e] = xo[j];
+        col_at(A.x + c0, ob16, r, G.es) = xo[j];
         bad |= !cfinite(xo[j]);
         if (acc) {
-          const cd s = cadd(A.acc_pa[e], A.acc_pb[e]);
+          const cd s = cadd(col_at(A.acc_pa + c0, ob16, r, G.es), col_at(A.acc_pb + c0, ob16, r, G.es));
           const double q = A.acc_tau * (xo[j].x * s.y - xo[j].y * s.x);
-          if (A.acc_dV) A.acc_dV[e] += A.vscale * q;
-          if (A.xg) part = fma(A.xg[e], q, part);
+          if (A.acc_dV) col_at(A.acc_dV + c0, ob8, r, G.es) += A.vscale * q;
+          if (A.xg) part = fma(col_at(A.xg + c0, ob8, r, G.es), q, part);
         }
       }
     }
