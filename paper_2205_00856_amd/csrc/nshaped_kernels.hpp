@@ -336,11 +336,23 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
 
 template <int M, int W>
 struct TileSmem {
+  // Partial blocks left by the nesting levels inside each wavefront (64 / W per wavefront) and,
+  // on the way down, psi at their two joint lines: kept in the idle tail of each staging buffer
+  // (after the tree nodes and, for M = 8, the diagonals) when they fit there.
+  static constexpr int kPer = 64 / W;
+  static constexpr size_t kOff = sizeof(Node) * 64 + (M == 8 ? sizeof(double) * 64 * M : 0);
+  static constexpr bool kInStage =
+      W > 1 && kOff + sizeof(Blk) * kPer <= sizeof(cd) * Stage<M>::QS;
   cd lds[W][Stage<M>::QS];  // per-wavefront staging buffer; holds the tree nodes in between
-  Blk wblk[W];
-  cd wpsi[W][2];
+  Blk xblk[(W > 1 && !kInStage) ? 64 : 1];
   Node xnode[64];
   double wsum[W];
+  __device__ __forceinline__ Blk* part(int w, int k) {
+    if constexpr (kInStage)
+      return reinterpret_cast<Blk*>(reinterpret_cast<char*>(lds[w]) + kOff) + k;
+    else
+      return &xblk[w * kPer + k];
+  }
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -428,8 +440,8 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 }
 
 // Everything after the rows of the tile are assembled up to SS: level-1 sweeps, nesting, top,
-// substitution.  wnode holds this wavefront's 64 tree nodes; sm provides wblk, xnode and wpsi for
-// the levels across wavefronts.  For PH != PH_REDUCE, xo returns this lane's rows J .. J+M-1.
+// substitution.  wnode holds this wavefront's 64 tree nodes; sm provides the partial blocks and
+// the nodes (xnode) of the levels across wavefronts.  For PH != PH_REDUCE, xo returns this lane's rows J .. J+M-1.
 // Crank-Nicolson tiles of M = 8 rows per lane that substitute take reduce_block_rd /
 // ss_block_rd (fewer registers, so two 512-lane workgroups fit a CU; with fewer rows per lane
 // the extra arithmetic buys no occupancy): keep holds 64 * M doubles of this wavefront's LDS for
@@ -467,13 +479,20 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
   } else {
     reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
   }
-  tree_up<6>(blk, wnode, lane);
-  if constexpr (W > 1) {
-    if (lane == 0) sm.wblk[wave] = blk;
+  if constexpr (W == 1) {
+    tree_up<6>(blk, wnode, lane);
+  } else {
+    // The 64 W lane blocks of the tile are nested in 6 + log2 W binary levels.  The lowest
+    // log2 W run inside every wavefront and leave 64 / W partial blocks each (lanes 0, W, 2W..);
+    // wavefront 0 takes the resulting 64 blocks through the remaining six.  Same critical
+    // path as six levels per wavefront followed by log2 W across them, but W log2 W + 6
+    // wavefront-levels of work instead of 6 W + log2 W.
+    tree_up<LW>(blk, wnode, lane);
+    if ((lane & (W - 1)) == 0) *sm.part(wave, lane >> LW) = blk;
     __syncthreads();
     if (wave == 0) {
-      blk = sm.wblk[lane & (W - 1)];
-      tree_up<LW>(blk, sm.xnode, lane);
+      blk = *sm.part(lane >> (6 - LW), lane & (64 / W - 1));
+      tree_up<6>(blk, sm.xnode, lane);
     }
   }
 
@@ -501,19 +520,22 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
     }
   }
   if constexpr (PH != PH_REDUCE) {
-    if constexpr (W > 1) {
+    if constexpr (W == 1) {
+      tree_down<6>(pJ, pM, wnode, lane);
+    } else {
       if (wave == 0) {
-        tree_down<LW>(pJ, pM, sm.xnode, lane);
-        if (lane < W) {
-          sm.wpsi[lane][0] = pJ;
-          sm.wpsi[lane][1] = pM;
-        }
+        tree_down<6>(pJ, pM, sm.xnode, lane);
+        cd* q = reinterpret_cast<cd*>(sm.part(lane >> (6 - LW), lane & (64 / W - 1)));
+        q[0] = pJ;
+        q[1] = pM;
       }
       __syncthreads();
-      pJ = sm.wpsi[wave][0];
-      pM = sm.wpsi[wave][1];
+      // every lane reads the pair of its group; the leading lanes' copies start the levels
+      const cd* q = reinterpret_cast<const cd*>(sm.part(wave, lane >> LW));
+      pJ = q[0];
+      pM = q[1];
+      tree_down<LW>(pJ, pM, wnode, lane);
     }
-    tree_down<6>(pJ, pM, wnode, lane);
     if constexpr (RD) {
       double ay[M];
       ay[0] = 0.0;
