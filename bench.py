@@ -8,9 +8,13 @@ lines, each a full CN step (explicit half-step fused into the N-shaped solve).  
 one captured hipGraph.  value = solved complex unknowns per second (2 x 4096^2 per step).
 
 Also reported (extra): the 2^28-unknown explicit solve with its partition sweep, the plain 1D
-workload (N = 65536, one solve + 200 steps) and the uneven batch (10^4 systems, 50 steps).
+workload (N = 65536, one solve + 200 steps), the uneven batch (10^4 systems, 50 steps) and the
+differentiated propagation (2^20 x 2000 steps), each with the oracle timed beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--cpu-seconds S]
+                       [--copy-ref] [--only-large]
+  --cpu-seconds 0 skips the oracle's full 100-step run of the headline grid (about 15 s on 16
+  threads; the baseline and parity then use one step); --only-large times only the 2^28 solve.
 """
 from __future__ import annotations
 
@@ -42,6 +46,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-extra", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--only-large", action="store_true",
+                   help="time only the 2^28 explicit solve (automatic plan), for profiling")
     p.add_argument("--copy-ref", action="store_true",
                    help="first run a plain 256 MiB device copy three times (a reference of known "
                         "size for scaling hardware byte counters)")
@@ -125,6 +131,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.only_large:
+        print(json.dumps(large_system(torch, np, cn, dev, sweep=False)), flush=True)
+        return
+
     # ---------------------------------------------------------------- headline: ADI 4096^2
     w = workloads.adi_2d()
     ny, nx = w["psi0"].shape
@@ -148,37 +158,44 @@ def main():
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         adi_step()
-    # parity of one captured step against the oracle
+    # parity against the oracle: one captured step, and the workload's full run of w["steps"]
+    # replays from psi0 (the oracle's timed run of the same steps is the cpu_baseline)
     psi.copy_(psi0)
     graph.replay()
     torch.cuda.synchronize()
     one = psi.cpu().numpy().reshape(ny, nx)
-    parity = None
+    psi.copy_(psi0)
+    for _ in range(w["steps"]):
+        graph.replay()
+    torch.cuda.synchronize()
+    full = psi.cpu().numpy().reshape(ny, nx)
+    norm_full = float(np.sum(np.abs(full) ** 2) * w["dx"] * w["dy"])
+    parity = parity_full = None
     cpu_baseline = None
     nthr = cpu_threads()
     try:
         import oracle
 
         t0 = time.perf_counter()
-        ref = oracle.adi_step(w["psi0"], w["V"], w["dx"], w["dy"], w["dt"], nthr)
-        t_one = time.perf_counter() - t0
-        parity = rel_l2(one, ref)
-        # cpu_baseline: the oracle timed on a bounded sample (whole ADI steps of the same grid)
-        nsteps_cpu = max(1, int(args.cpu_seconds / max(t_one, 1e-3))) if args.cpu_seconds > 0 else 0
-        state = ref
-        t0 = time.perf_counter()
-        for _ in range(nsteps_cpu):
-            state = oracle.adi_step(state, w["V"], w["dx"], w["dy"], w["dt"], nthr)
-        t_cpu = max(time.perf_counter() - t0, 1e-9)
-        if nsteps_cpu == 0:
-            nsteps_cpu, t_cpu = 1, t_one
+        state = oracle.adi_step(w["psi0"], w["V"], w["dx"], w["dy"], w["dt"], nthr)
+        t_cpu = time.perf_counter() - t0
+        parity = rel_l2(one, state)
+        nsteps_cpu = 1
+        if args.cpu_seconds > 0:
+            # the whole run (100 steps of the 4096^2 grid, about 15 s on 16 threads)
+            t0 = time.perf_counter()
+            for _ in range(w["steps"] - 1):
+                state = oracle.adi_step(state, w["V"], w["dx"], w["dy"], w["dt"], nthr)
+            t_cpu += time.perf_counter() - t0
+            nsteps_cpu = w["steps"]
+            parity_full = rel_l2(full, state)
         cpu_baseline = {
-            "value": 2 * nx * ny * nsteps_cpu / t_cpu,
+            "value": 2 * nx * ny * nsteps_cpu / max(t_cpu, 1e-9),
             "unit": "complex unknowns/s",
             "cores": nthr,
             "kind": "oracle",
-            "sample": f"{nsteps_cpu} full ADI steps of the 4096x4096 grid (serial FP64 Thomas per "
-                      f"line, lines spread over {nthr} threads), {t_cpu:.1f} s",
+            "sample": f"{nsteps_cpu} full ADI steps of the 4096x4096 grid from psi0 (serial FP64 "
+                      f"Thomas per line, lines spread over {nthr} threads), {t_cpu:.1f} s",
         }
     except Exception as ex:  # noqa: BLE001 - the baseline leg must not hide the GPU result
         log("cpu baseline / parity leg failed:", repr(ex))
@@ -236,6 +253,9 @@ def main():
         },
         "cpu_baseline": cpu_baseline,
         "parity_rel_l2_first_step": parity,
+        "parity_rel_l2_after_steps": parity_full,
+        "parity_steps": w["steps"],
+        "norm_drift_after_steps": abs(norm_full - 1.0),
         "norm_after": norm,
     }
 
@@ -244,49 +264,85 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def large_system(torch, np, cn, dev, sweep=True):
+    """The 2^28-unknown explicit solve (a, b, c from the config-0 stencil with dx = 0.01,
+    dt = 0.02, V ~ U(-1, 0); d complex normal, drawn with torch's seeded device generator),
+    timed with the automatic plan and over the partition sweep."""
+    N = 1 << 28
+    g = torch.Generator(device=dev)
+    g.manual_seed(1002)
+    V = torch.rand(N, dtype=torch.float64, device=dev, generator=g) - 1.0
+    a, b, c = cn.assemble(V, 0.01, 0.02)
+    del V
+    d = torch.empty(N, dtype=torch.complex128, device=dev)
+    d.real.normal_(generator=g)
+    d.imag.normal_(generator=g)
+    x = torch.empty_like(d)
+    rows = []
+    parts = (0, 128, 256, 512, 1024, 2048, 4096) if sweep else (0,)
+    for T in parts:
+        M = 2 if T == 128 else (0 if T == 0 else 4)
+        L = cn.Layout.contiguous(N, 1, partition=T, rows_per_thread=M)
+        cn.solve(a, b, c, d, out=x, layout=L)
+        ts = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), 10)
+        med = float(np.median(ts))
+        rows.append({"partition": T, "rows_per_thread": M, "ms_median": med,
+                     "ms_min": float(np.min(ts)),
+                     "GBps_144": BYTES_PER_UNKNOWN_SOLVE_2PASS * N / (med * 1e-3) / 1e9,
+                     "plan": cn.describe_plan(L)})
+    r = a * x
+    r[1:] += b[1:] * x[:-1]
+    r[:-1] += c[:-1] * x[1:]
+    resid = float(torch.linalg.norm(r - d) / torch.linalg.norm(d))
+    del r, a, b, c, d, x
+    auto = rows[0]
+    out = {
+        "unknowns_per_solve": N,
+        "auto_ms": auto["ms_median"],
+        "auto_unknowns_per_s": N / (auto["ms_median"] * 1e-3),
+        "auto_frac_of_peak_144B": auto["GBps_144"] / HBM_PEAK_GBS,
+        "auto_frac_of_peak_80B": BYTES_PER_UNKNOWN_SOLVE_MIN * N / (auto["ms_median"] * 1e-3)
+                                 / 1e9 / HBM_PEAK_GBS,
+        "residual_rel": resid,
+        "paper_optimum_single_level_partition": math.sqrt(N),
+        "sweep": rows,
+    }
+    if sweep:
+        out["cpu_baseline"] = oracle_timed(
+            "serial FP64 Thomas on a 2^24-row system of the same distribution (1 thread)",
+            lambda o: _thomas_sample(np, o, 1 << 24), 1 << 24, out["auto_unknowns_per_s"])
+    return out
+
+
+def _thomas_sample(np, o, n):
+    g = np.random.default_rng(1002)
+    V = g.uniform(-1.0, 0.0, n)
+    a, b, c = o.cn_coeffs(V, 0.01, 0.02)
+    d = g.standard_normal(n) + 1j * g.standard_normal(n)
+    return lambda: o.thomas(a, b, c, d)
+
+
+def oracle_timed(sample, make, units, gpu_units_per_s, threads=1):
+    """The oracle timed on a bounded sample of a workload (make(oracle) returns the call)."""
+    try:
+        import oracle
+
+        fn = make(oracle)
+        t0 = time.perf_counter()
+        fn()
+        t = max(time.perf_counter() - t0, 1e-9)
+        return {"value": units / t, "unit": "complex unknowns/s", "cores": threads,
+                "kind": "oracle", "sample": f"{sample}, {t:.2f} s",
+                "gpu_over_oracle": gpu_units_per_s / (units / t)}
+    except Exception as ex:  # noqa: BLE001
+        return {"error": repr(ex)}
+
+
 def extras(torch, np, cn, workloads, dev):
     out = {}
     # ----------------------------------------------------------- 2^28 explicit solve
     try:
-        N = 1 << 28
-        g = torch.Generator(device=dev)
-        g.manual_seed(1002)
-        V = torch.rand(N, dtype=torch.float64, device=dev, generator=g) - 1.0
-        a, b, c = cn.assemble(V, 0.01, 0.02)
-        del V
-        d = torch.empty(N, dtype=torch.complex128, device=dev)
-        d.real.normal_(generator=g)
-        d.imag.normal_(generator=g)
-        x = torch.empty_like(d)
-        sweep = []
-        for T in (0, 128, 256, 512, 1024, 2048, 4096):
-            M = 2 if T == 128 else (0 if T == 0 else 4)
-            L = cn.Layout.contiguous(N, 1, partition=T, rows_per_thread=M)
-            cn.solve(a, b, c, d, out=x, layout=L)
-            ts = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), 10)
-            med = float(np.median(ts))
-            row = {"partition": T, "rows_per_thread": M, "ms_median": med,
-                   "ms_min": float(np.min(ts)),
-                   "GBps_144": BYTES_PER_UNKNOWN_SOLVE_2PASS * N / (med * 1e-3) / 1e9,
-                   "plan": cn.describe_plan(L)}
-            sweep.append(row)
-        r = a * x
-        r[1:] += b[1:] * x[:-1]
-        r[:-1] += c[:-1] * x[1:]
-        resid = float(torch.linalg.norm(r - d) / torch.linalg.norm(d))
-        del r, a, b, c, d, x
-        auto = sweep[0]
-        out["large_system_2^28"] = {
-            "unknowns_per_solve": N,
-            "auto_ms": auto["ms_median"],
-            "auto_unknowns_per_s": N / (auto["ms_median"] * 1e-3),
-            "auto_frac_of_peak_144B": auto["GBps_144"] / HBM_PEAK_GBS,
-            "auto_frac_of_peak_80B": BYTES_PER_UNKNOWN_SOLVE_MIN * N / (auto["ms_median"] * 1e-3)
-                                     / 1e9 / HBM_PEAK_GBS,
-            "residual_rel": resid,
-            "paper_optimum_single_level_partition": math.sqrt(N),
-            "sweep": sweep,
-        }
+        out["large_system_2^28"] = large_system(torch, np, cn, dev, sweep=True)
         torch.cuda.empty_cache()
     except Exception as ex:  # noqa: BLE001
         out["large_system_2^28"] = {"error": repr(ex)}
@@ -317,6 +373,7 @@ def extras(torch, np, cn, workloads, dev):
         gr.replay()
         torch.cuda.synchronize()
         norm = float(torch.sum(torch.abs(psi) ** 2).item() * w["dx"])
+        psi200 = psi.cpu().numpy()
         ts_graph = timed_events(torch, gr.replay, 5)
         med = float(np.median(ts_graph))
         out["plain_1d"] = {"n": w["n"], "steps": w["steps"],
@@ -327,6 +384,14 @@ def extras(torch, np, cn, workloads, dev):
                            "unknowns_per_s": w["n"] * w["steps"] / (med * 1e-3),
                            "norm_after_200": norm,
                            "plan": cn.describe_plan(L, True)}
+        ref = {}
+        out["plain_1d"]["cpu_baseline"] = oracle_timed(
+            "200 CN steps of the 65536-row system (serial FP64 Thomas, 1 thread)",
+            lambda o: (lambda: ref.setdefault("x", o.cn_propagate(w["psi0"], w["V"], w["dx"],
+                                                                  w["dt"], w["steps"]))),
+            w["n"] * w["steps"], out["plain_1d"]["unknowns_per_s"])
+        if "x" in ref:
+            out["plain_1d"]["parity_rel_l2_200"] = rel_l2(psi200, ref["x"])
     except Exception as ex:  # noqa: BLE001
         out["plain_1d"] = {"error": repr(ex)}
     # ----------------------------------------------------------- uneven batch
@@ -338,6 +403,7 @@ def extras(torch, np, cn, workloads, dev):
         dxs = torch.from_numpy(wl["dx"]).to(dev)
         rows = int(wl["offsets"][-1])
         cn.reserve(L)
+        first = cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, layout=L).cpu().numpy()
         cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi, layout=L)
         ts = timed_events(torch, lambda: cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi,
                                                  layout=L), wl["steps"])
@@ -346,6 +412,16 @@ def extras(torch, np, cn, workloads, dev):
                                "ms_per_step": med, "unknowns_per_s": rows / (med * 1e-3),
                                "GBps_40": BYTES_PER_UNKNOWN_STEP * rows / (med * 1e-3) / 1e9,
                                "plan": cn.describe_plan(L, True)[:400]}
+        nthr = cpu_threads()
+        ref = {}
+        out["uneven_batch"]["cpu_baseline"] = oracle_timed(
+            f"one CN step of all 10^4 systems (serial FP64 Thomas per system, {nthr} threads)",
+            lambda o: (lambda: ref.setdefault("x", o.cn_step_batched(
+                wl["offsets"], wl["psi0"], wl["V"], wl["dx"], wl["dt"], nthr))),
+            rows, out["uneven_batch"]["unknowns_per_s"], nthr)
+        if "x" in ref:
+            out["uneven_batch"]["parity_rel_l2_first_step"] = rel_l2(first, ref["x"])
+        del first, ref
     except Exception as ex:  # noqa: BLE001
         out["uneven_batch"] = {"error": repr(ex)}
     # ----------------------------------------------------------- differentiated propagation
@@ -424,7 +500,24 @@ def differentiated(torch, np, workloads, dev):
     ana = np.asarray(ana)
     fwd_s = float(np.median(tf))
     bwd_s = float(np.median(tb))
+    # the oracle beside it on a bounded sample: the first 50 steps of the same propagation,
+    # and the GPU's 50-step state against it
+    import paper_2205_00856_amd as cn
+
+    ns = 50
+    p50 = p0.clone()
+    cn.propagate(p50, tV.detach(), dx, dt, ns, E=np.ascontiguousarray(w["E"][:ns]), xgrid=tx)
+    p50 = p50.cpu().numpy()
+    ref = {}
+    cpu = oracle_timed(
+        f"the first {ns} of the {w['steps']} steps (serial FP64 Thomas with the field term, "
+        f"1 thread)",
+        lambda o: (lambda: ref.setdefault("x", o.cn_propagate(w["psi0"], w["V"], dx, dt, ns,
+                                                              xgrid=w["x"], E=w["E"][:ns]))),
+        w["n"] * ns, w["n"] * w["steps"] / fwd_s)
     return {
+        "cpu_baseline": cpu,
+        "parity_rel_l2_50_steps": rel_l2(p50, ref["x"]) if "x" in ref else None,
         "n": w["n"], "steps": w["steps"], "checkpoint_every": K,
         "forward_ms": fwd_s * 1e3, "backward_ms": bwd_s * 1e3,
         "forward_us_per_step": fwd_s * 1e6 / w["steps"],
