@@ -147,17 +147,19 @@ __device__ __forceinline__ void reduce_block(cd (&A)[M], cd (&Bt)[M], cd (&Ct)[M
 
 // Off-diagonals of a Crank-Nicolson block: rows J .. J+M-1 of a system of n rows, each coupled
 // to its neighbours by -i kappa, except across the system ends and on padding rows past n.
+// IN: the caller knows every row of the block and both neighbours lie inside the system.
+template <bool IN>
 struct CnEdges {
   int64_t J, n;
   double kap;
   // imaginary parts of the sub- and super-diagonal of local row i
   __device__ __forceinline__ double b(int i) const {
     const int64_t r = J + i;
-    return (r < n && r > 0) ? -kap : 0.0;
+    return (IN || (r < n && r > 0)) ? -kap : 0.0;
   }
   __device__ __forceinline__ double c(int i) const {
     const int64_t r = J + i;
-    return (r < n - 1) ? -kap : 0.0;
+    return (IN || r < n - 1) ? -kap : 0.0;
   }
 };
 
@@ -171,8 +173,8 @@ struct CnEdges {
 // levels instead of three.  RU only has to deliver the final row J+1 for JU; unrolled, that row
 // is the forward sum  psi_{J+1} = sum_k P_k (delta_k - beta_k psi_J) + P_M psi_K  with P_1 = 1,
 // P_{k+1} = -gamma_k P_k, accumulated here during RD, so no RD row is held for a backward pass.
-template <int M>
-__device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const CnEdges& e,
+template <int M, typename E>
+__device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const E& e,
                                                 cd (&D)[M], double bK, Blk& o) {
   static_assert(M >= 2, "blocks with interior rows");
   cd beta, gam;
@@ -211,8 +213,8 @@ __device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const CnE
 // SS along the RD rows of reduce_block_rd: with psi_J and psi_K = psi_{J+M} known,
 //   psi_i = delta_i - beta_i psi_J - gamma_i psi_{i+1},  i = M-1 down to 1,
 // where beta_i and gamma_i are recomputed from ay and e with reduce_block_rd's operations.
-template <int M>
-__device__ __forceinline__ void ss_block_rd(const double (&ay)[M], const CnEdges& e,
+template <int M, typename E>
+__device__ __forceinline__ void ss_block_rd(const double (&ay)[M], const E& e,
                                             const cd (&D)[M], cd pJ, cd pK, cd (&x)[M]) {
   cd gam[M], dp[M];
   cd beta;

@@ -106,22 +106,46 @@ __device__ __forceinline__ Geo geometry(const KArgs& A) {
 __device__ __forceinline__ double sel(bool p, double a, double b) { return p ? a : b; }
 __device__ __forceinline__ cd sel(bool p, cd a, cd b) { return csel(p, a, b); }
 
+// Interior wavefronts: every row a wavefront touches, its two halo rows included, lies strictly
+// inside the system (w0 >= 1 and w0 + 64 M <= n - 1).  Their rows need no clamping and no edge
+// selects; IN = true compiles that path, IN = false the general one.
+template <bool IN>
+__device__ __forceinline__ bool row_in(int64_t r, int64_t n) {
+  return IN || r < n;
+}
+template <bool IN>
+__device__ __forceinline__ bool row_pos(int64_t r) {
+  return IN || r > 0;
+}
+template <bool IN>
+__device__ __forceinline__ bool row_notlast(int64_t r, int64_t n) {
+  return IN || r < n - 1;
+}
+
 // Fetch rows w0 + 64k + lane (k < M) and the two halo rows w0-1 (lane 0) and w0+64M (lane 1)
 // of a strided array into registers.  Loads are unconditional at a clamped row (n >= 1) and the
 // fill value is selected afterwards, so no lane takes a different path.
-template <int M, typename T>
+template <int M, bool IN, typename T>
 __device__ __forceinline__ void stage_fetch(const T* g, int64_t es, int64_t w0, int64_t n,
                                             int lane, T fill, T (&v)[M], T& h) {
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     const int64_t r = w0 + 64 * k + lane;
-    const T t = g[(r < n ? r : n - 1) * es];
-    v[k] = sel(r < n, t, fill);
+    if constexpr (IN) {
+      v[k] = sel(true, g[r * es], fill);  // a fresh value (a plain copy defeats promotion)
+    } else {
+      const T t = g[(r < n ? r : n - 1) * es];
+      v[k] = sel(r < n, t, fill);
+    }
   }
   const int64_t rr = (lane == 0) ? w0 - 1 : w0 + 64 * M;
-  const int64_t rc = rr < 0 ? 0 : (rr < n ? rr : n - 1);
-  const T t = g[rc * es];
-  h = sel(rr >= 0 && rr < n, t, fill);
+  if constexpr (IN) {
+    h = sel(true, g[rr * es], fill);
+  } else {
+    const int64_t rc = rr < 0 ? 0 : (rr < n ? rr : n - 1);
+    const T t = g[rc * es];
+    h = sel(rr >= 0 && rr < n, t, fill);
+  }
 }
 
 template <int M, typename T>
@@ -163,14 +187,14 @@ struct CnRaw {
   double hx;
 };
 
-template <int M, bool XG>
+template <int M, bool XG, bool IN>
 __device__ __forceinline__ void cn_fetch(const KArgs& A, const Geo& G, int64_t w0, int lane,
                                          CnRaw<M, XG>& r) {
   const cd* src = (A.rhs ? A.rhs : A.psi) + G.base;
-  stage_fetch<M>(src, G.es, w0, G.n, lane, czero(), r.p, r.hp);
-  stage_fetch<M>(A.V + G.base, G.es, w0, G.n, lane, 0.0, r.v, r.hv);
+  stage_fetch<M, IN>(src, G.es, w0, G.n, lane, czero(), r.p, r.hp);
+  stage_fetch<M, IN>(A.V + G.base, G.es, w0, G.n, lane, 0.0, r.v, r.hv);
   if constexpr (XG) {
-    if (A.xg) stage_fetch<M>(A.xg + G.base, G.es, w0, G.n, lane, 0.0, r.x, r.hx);
+    if (A.xg) stage_fetch<M, IN>(A.xg + G.base, G.es, w0, G.n, lane, 0.0, r.x, r.hx);
   }
 }
 
@@ -183,7 +207,7 @@ __device__ __forceinline__ double cn_kappa(double dt, double dx) {
 // fused into the reduction (Sec. 5.3).  The off-diagonals are -i kappa (pure imaginary).
 // vp holds psi at rows J-1 .. J+M of this lane (zero outside the system), vv and xv hold V and
 // xgrid at the same rows (only J .. J+M-1 are read).
-template <int M>
+template <int M, bool IN>
 __device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx, int64_t J,
                                         const cd (&vp)[M + 2], const double (&vv)[M + 2],
                                         const double (&xv)[M + 2], cd (&Ar)[M], cd (&Br)[M],
@@ -197,11 +221,11 @@ __device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx,
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const int64_t r = J + j;
-    const bool ok = r < n;
+    const bool ok = row_in<IN>(r, n);
     const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
     Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
-    Br[j] = mk(0.0, (ok && r > 0) ? -kap : 0.0);
-    Cr[j] = mk(0.0, (ok && r < n - 1) ? -kap : 0.0);
+    Br[j] = mk(0.0, (ok && row_pos<IN>(r)) ? -kap : 0.0);
+    Cr[j] = mk(0.0, (ok && row_notlast<IN>(r, n)) ? -kap : 0.0);
     if (given) {
       Dr[j] = vp[j + 1];
     } else {
@@ -211,10 +235,10 @@ __device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx,
       Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
     }
   }
-  bK = mk(0.0, (J + M < n) ? -kap : 0.0);
+  bK = mk(0.0, row_in<IN>(J + M, n) ? -kap : 0.0);
 }
 
-template <int M, int W, int PH, bool XG>
+template <int M, int W, int PH, bool XG, bool IN>
 __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
                                          int64_t J, int lane, int wave, CnRaw<M, XG>& raw,
                                          cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
@@ -242,13 +266,13 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
 #pragma unroll
     for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
   }
-  cn_rows<M>(A, G, A.dxs ? A.dxs[G.sys] : A.dx, J, vp, vv, xv, Ar, Br, Cr, Dr, bK);
+  cn_rows<M, IN>(A, G, A.dxs ? A.dxs[G.sys] : A.dx, J, vp, vv, xv, Ar, Br, Cr, Dr, bK);
   first_state = vp[1];
   last_state = vp[M];
 }
 
 // ------------------------------------------------------------------ row assembly per source
-template <int M, int W, int SRC, int PH>
+template <int M, int W, int SRC, int PH, bool IN>
 __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
                                           int64_t J, int lane, int wave, cd (&Ar)[M],
                                           cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M], cd& bK,
@@ -257,10 +281,10 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
   if constexpr (SRC == SRC_EXPL || SRC == SRC_EXPL_CT) {
     const cd one = mk(1.0, 0.0), zero = czero();
     cd ra[M], rb[M], rc[M], rd[M], ha, hb, hc, hd;
-    stage_fetch<M>(A.a + G.base, G.es, w0, n, lane, one, ra, ha);
-    stage_fetch<M>(A.b + G.base, G.es, w0, n, lane, zero, rb, hb);
-    stage_fetch<M>(A.c + G.base, G.es, w0, n, lane, zero, rc, hc);
-    stage_fetch<M>(A.d + G.base, G.es, w0, n, lane, zero, rd, hd);
+    stage_fetch<M, IN>(A.a + G.base, G.es, w0, n, lane, one, ra, ha);
+    stage_fetch<M, IN>(A.b + G.base, G.es, w0, n, lane, zero, rb, hb);
+    stage_fetch<M, IN>(A.c + G.base, G.es, w0, n, lane, zero, rc, hc);
+    stage_fetch<M, IN>(A.d + G.base, G.es, w0, n, lane, zero, rd, hd);
     cd va[M + 2], vb[M + 2], vc[M + 2], vd[M + 2];
     transpose_in<M>(buf, lane, ra, ha, va);
     transpose_in<M>(buf, lane, rb, hb, vb);
@@ -269,30 +293,32 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const int64_t r = J + j;
-      const bool ok = r < n;
+      const bool ok = row_in<IN>(r, n);
+      const bool pos = ok && row_pos<IN>(r), notlast = ok && row_notlast<IN>(r, n);
+      // (with IN the selects fold to their first operand)
       if constexpr (SRC == SRC_EXPL) {
         Ar[j] = csel(ok, va[j + 1], one);
-        Br[j] = csel(ok && r > 0, vb[j + 1], zero);
-        Cr[j] = csel(ok && r < n - 1, vc[j + 1], zero);
+        Br[j] = csel(pos, vb[j + 1], zero);
+        Cr[j] = csel(notlast, vc[j + 1], zero);
       } else {
         // row i of T^H: diagonal conj(a_i), sub conj(c_{i-1}), super conj(b_{i+1})
         Ar[j] = csel(ok, cconj(va[j + 1]), one);
-        Br[j] = csel(ok && r > 0, cconj(vc[j]), zero);
-        Cr[j] = csel(ok && r < n - 1, cconj(vb[j + 2]), zero);
+        Br[j] = csel(pos, cconj(vc[j]), zero);
+        Cr[j] = csel(notlast, cconj(vb[j + 2]), zero);
       }
       Dr[j] = csel(ok, vd[j + 1], zero);
     }
     const int64_t K = J + M;
     if constexpr (SRC == SRC_EXPL)
-      bK = csel(K < n, vb[M + 1], zero);
+      bK = csel(row_in<IN>(K, n), vb[M + 1], zero);
     else
-      bK = csel(K < n, cconj(vc[M]), zero);
+      bK = csel(row_in<IN>(K, n), cconj(vc[M]), zero);
     first_state = last_state = zero;
   } else if constexpr (SRC == SRC_CN) {
     CnRaw<M, true> raw;
-    cn_fetch<M, true>(A, G, w0, lane, raw);
-    cn_build<M, W, PH, true>(A, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr, bK, first_state,
-                             last_state);
+    cn_fetch<M, true, IN>(A, G, w0, lane, raw);
+    cn_build<M, W, PH, true, IN>(A, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr, bK,
+                                 first_state, last_state);
   } else {  // SRC_SLOTS: row k of the reduced system = U slot of tile k + D slot of tile k-1
     const cd zero = czero();
 #pragma unroll
@@ -329,7 +355,7 @@ struct Log2<1> {
 template <int M, int W>
 struct TileSmem;
 
-template <int M, int W, int SRC>
+template <int M, int W, int SRC, bool IN>
 __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                            cd* buf, int64_t w0, int lane, int wave,
                                            const cd (&x)[M]);
@@ -367,7 +393,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Coalesced store of the tile's solution through the LDS buffer; for the CN source the adjoint
 // accumulation (see KArgs) runs on the same coalesced rows.
-template <int M, int W, int SRC>
+template <int M, int W, int SRC, bool IN>
 __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                            cd* buf, int64_t w0, int lane, int wave,
                                            const cd (&x)[M]) {
@@ -386,7 +412,7 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     const int64_t r = w0 + 64 * k + sl;
-    if (r < G.n) {
+    if (row_in<IN>(r, G.n)) {
       const cd v = buf[S::addr(1 + 64 * k + sl)];
       const int64_t e = G.base + r * G.es;
       g[r * G.es] = v;
@@ -411,7 +437,7 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
   }
 }
 
-template <int M, int W, int SRC, int PH>
+template <int M, int W, int SRC, int PH, bool IN>
 __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                             cd* buf, int64_t w0, int64_t J, int lane, int wave,
                                             cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
@@ -435,8 +461,16 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
   cd* buf = sm.lds[wave];
 
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
-  load_rows<M, W, SRC, PH>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
-  tile_finish<M, W, SRC, PH>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+  // wavefront-uniform choice between the interior path and the general one
+  if (SRC != SRC_SLOTS && w0 >= 1 && G.n >= w0 + 64 * M + 1) {
+    load_rows<M, W, SRC, PH, true>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+    tile_finish<M, W, SRC, PH, true>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
+                                     lst);
+  } else {
+    load_rows<M, W, SRC, PH, false>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+    tile_finish<M, W, SRC, PH, false>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
+                                      lst);
+  }
 }
 
 // Everything after the rows of the tile are assembled up to SS: level-1 sweeps, nesting, top,
@@ -452,7 +486,7 @@ struct RdSubst {
   static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M == 8;
 };
 
-template <int M, int W, int SRC, int PH, typename SM>
+template <int M, int W, int SRC, int PH, bool IN, typename SM>
 __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, Node* wnode,
                                           double* keep, double kap, int64_t J, int lane, int wave,
                                           cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
@@ -467,7 +501,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
   }
 
   Blk blk;
-  const CnEdges edges{J, G.n, kap};
+  const CnEdges<IN> edges{J, G.n, kap};
   wave_sync();
   if constexpr (RD) {
     double ay[M];
@@ -549,17 +583,17 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
 }
 
 // Raises the status flag when a row of this lane is not finite.
-template <int M>
+template <int M, bool IN>
 __device__ __forceinline__ void check_rows(const KArgs& A, const Geo& G, int64_t J, int lane,
                                            const cd (&xo)[M]) {
   bool bad = false;
 #pragma unroll
-  for (int j = 0; j < M; ++j) bad |= (J + j < G.n) && !cfinite(xo[j]);
+  for (int j = 0; j < M; ++j) bad |= row_in<IN>(J + j, G.n) && !cfinite(xo[j]);
   if (__any(bad) && lane == 0) atomicOr(A.status, 1);
 }
 
 // Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
-template <int M, int W, int SRC, int PH>
+template <int M, int W, int SRC, int PH, bool IN>
 __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                             cd* buf, int64_t w0, int64_t J, int lane, int wave,
                                             cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
@@ -577,16 +611,16 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
     kap = cn_kappa(A.dt, dx);
   }
   cd xo[M];
-  tile_core<M, W, SRC, PH>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
-                           lst, xo);
+  tile_core<M, W, SRC, PH, IN>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
+                               lst, xo);
   if constexpr (PH != PH_REDUCE) {
-    check_rows<M>(A, G, J, lane, xo);
+    check_rows<M, IN>(A, G, J, lane, xo);
     if constexpr (SRC == SRC_SLOTS) {
 #pragma unroll
       for (int j = 0; j < M; ++j)
         if (J + j < G.n) A.x[G.base + J + j] = xo[j];
     } else {
-      store_tile<M, W, SRC>(A, G, sm, buf, w0, lane, wave, xo);
+      store_tile<M, W, SRC, IN>(A, G, sm, buf, w0, lane, wave, xo);
     }
   }
 }
