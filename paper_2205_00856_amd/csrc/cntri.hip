@@ -281,7 +281,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     if (bd.bs == 1 && batch >= 64 && bd.es >= batch && src != nsd::SRC_SLOTS && cols_enabled()) {
       int cc = -1;
       if (level == 1 && kn.partition > 0) cc = col_cfg(kn.partition, kn.rpt);
-      if (cc < 0) cc = col_cfg(32, 8);
+      if (cc < 0) cc = col_cfg(64, 16);
       const int64_t T = (int64_t)kColCfgs[cc].M * kColCfgs[cc].W;
       const int64_t K = (n + T - 1) / T, G = K * batch;
       const unsigned gy = (unsigned)((batch + 63) / 64);
