@@ -697,6 +697,10 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   const int64_t r0 = G.tile * T + (int64_t)wave * M;
   const int64_t n = G.n;
   const cd zero = czero();
+  // a Crank-Nicolson reduce pass keeps nothing for substitution: the forward-sum form of RU
+  // (reduce_block_rd) then needs no row of the lane held for a backward sweep
+  constexpr bool RDR = SRC == SRC_CN && PH == PH_REDUCE && M >= 2;
+  double kap = 0.0;
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst = zero, lst = zero;
   if constexpr (SRC == SRC_EXPL || SRC == SRC_EXPL_CT) {
     cd va[M + 2], vb[M + 2], vc[M + 2], vd[M + 2];
@@ -727,7 +731,7 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
     const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
     const double tau = 0.5 * A.dt;
     const double idx2 = 1.0 / (dx * dx);
-    const double kap = cn_kappa(A.dt, dx);
+    kap = cn_kappa(A.dt, dx);
     const bool given = A.rhs != nullptr;
     cd vp[M + 2];
     double vv[M + 2], xv[M + 2];
@@ -774,7 +778,14 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
     }
   }
   Blk blk;
-  reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
+  if constexpr (RDR) {
+    double ay[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) ay[j] = Ar[j].y;
+    reduce_block_rd<M>(ay, CnEdges<false>{r0, n, kap}, Dr, bK.y, blk);
+  } else {
+    reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
+  }
   sm.blk[wave][lane] = blk;
   __syncthreads();
   if (wave == 0) {
