@@ -418,10 +418,17 @@ def extras(torch, np, cn, workloads, dev):
         ts = timed_events(torch, lambda: cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi,
                                                  layout=L), wl["steps"])
         med = float(np.median(ts))
+        # the fixed-plan baseline: one persistent launch over all systems (1024-row tiles)
+        Lp = cn.Layout.uneven(wl["offsets"], partition=1024, rows_per_thread=4)
+        cn.reserve(Lp)
+        tsp = timed_events(torch, lambda: cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs,
+                                                  out=psi, layout=Lp), 10)
         out["uneven_batch"] = {"systems": wl["batch"], "rows": rows, "steps": wl["steps"],
                                "ms_per_step": med, "unknowns_per_s": rows / (med * 1e-3),
                                "GBps_40": BYTES_PER_UNKNOWN_STEP * rows / (med * 1e-3) / 1e9,
-                               "plan": cn.describe_plan(L, True)[:400]}
+                               "plan": cn.describe_plan(L, True)[:400],
+                               "persistent_plan_ms_per_step": float(np.median(tsp)),
+                               "persistent_plan": cn.describe_plan(Lp, True)[:200]}
         nthr = cpu_threads()
         ref = {}
         out["uneven_batch"]["cpu_baseline"] = oracle_timed(

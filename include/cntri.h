@@ -68,7 +68,10 @@ typedef struct {
   int64_t batch_stride;
   const int64_t* offsets;
   int32_t partition;       /* rows per first-level partition (one workgroup tile); a power
-                              of two in [32, 16384]; 0 = automatic                         */
+                              of two in [32, 16384]; 0 = automatic.  Uneven batches: 0 =
+                              one launch per length class for systems of up to 4096 rows
+                              and two passes over 2048-row tiles for longer ones; > 0 = one
+                              persistent launch over all systems with that tile            */
   int32_t rows_per_thread; /* rows per innermost block (2, 4, 8 or 16); 0 = automatic      */
 } cn_layout;
 
@@ -165,9 +168,10 @@ cn_status cn_propagate_adjoint(cn_handle_t handle, const cn_layout* layout,
                                const void* ckpt, int64_t K, void* seg, void* g,
                                double* dV_accum, double* dE, cn_stream_t stream);
 
-/* Autotuner: times the candidate tile configurations (rows per first-level partition and per
- * innermost block) of this layout on the caller's data and keeps the fastest for later calls
- * with the same layout whose partition and rows_per_thread are 0.  cn_mode = 0 times
+/* Autotuner: times the automatic plan and the candidate tile configurations (rows per
+ * first-level partition and per innermost block; for uneven batches the persistent launches)
+ * of this layout on the caller's data and keeps the fastest for later calls with the same
+ * layout whose partition and rows_per_thread are 0.  cn_mode = 0 times
  * cn_tridiag_solve(a, b, c, d -> x); cn_mode = 1 times cn_step(op, E, psi_in = d -> psi_out = x)
  * and ignores a, b, c.  x is overwritten and must not alias d.  A text report of the median
  * timings is written to report (may be NULL).  Not allowed during graph capture. */

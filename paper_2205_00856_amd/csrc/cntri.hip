@@ -134,6 +134,15 @@ int find_cfg(int64_t T, int M) {
 
 constexpr int64_t kSingleMax = 4096;  // largest tile that solves a whole system in one pass
 
+// persistent launch for uneven batches (CN_PERSIST=0 turns it off)
+bool persist_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_PERSIST");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 // XCD-contiguous order of whole-system workgroups (CN_XCD_REMAP=0 turns it off)
 bool xcd_remap_enabled() {
   static const bool on = [] {
@@ -391,13 +400,11 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   const int64_t batch = bd.batch;
   const int64_t t_offs = B.add_tab(bd.offs.data(), (batch + 1) * sizeof(int64_t));
   int64_t handled = 0;  // systems up to this length went to the persistent launch
-  if (level == 1 && src != nsd::SRC_SLOTS) {
-    // one persistent launch: whole systems from a device queue, longest first
-    int ci = -1;
-    if (kn.partition > 0) {
-      ci = find_cfg(kn.partition, kn.rpt > 0 ? kn.rpt : 4);
-      if (ci >= 0 && !g_pers[ci][src]) ci = -1;
-    }
+  if (level == 1 && src != nsd::SRC_SLOTS && kn.partition > 0 && persist_enabled()) {
+    // with an explicit partition: one persistent launch, whole systems from a device queue,
+    // longest first (configurations without a persistent kernel use T = 1024, M = 4)
+    int ci = find_cfg(kn.partition, kn.rpt > 0 ? kn.rpt : 4);
+    if (ci >= 0 && !g_pers[ci][src]) ci = -1;
     if (ci < 0) ci = find_cfg(1024, 4);
     const int64_t T = kCfgs[ci].T();
     handled = nsd::kMaxSysTiles * T;
@@ -484,7 +491,11 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     maxlen = std::max(maxlen, bd.offs[s + 1] - bd.offs[s]);
     nl += bd.offs[s + 1] - bd.offs[s];
   }
-  int ci = multi_cfg(nl / (int64_t)large.size(), (int64_t)large.size(), kn, level);
+  // automatic plan of a caller's uneven batch: the long systems are solved two-pass over
+  // 2048-row tiles of 8 rows per lane (measured best for lengths up to 65536)
+  int ci = (level == 1 && kn.partition == 0 && src != nsd::SRC_SLOTS)
+               ? find_cfg(2048, 8)
+               : multi_cfg(nl / (int64_t)large.size(), (int64_t)large.size(), kn, level);
   const int64_t T = kCfgs[ci].T();
   std::vector<int64_t> tbase(batch + 1, 0);
   std::vector<int> wgs, wgt;
@@ -548,6 +559,8 @@ struct cn_handle_s {
   int* status = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> plans;
   std::map<std::string, std::string> tuned;  // automatic layout key -> key of the tuned plan
+  double* rows_buf = nullptr;  // per-step partial sums of one checkpoint segment
+  size_t rows_cap = 0;         // doubles
 };
 
 namespace {
@@ -830,6 +843,7 @@ cn_status cn_destroy(cn_handle_t h) {
   (void)hipDeviceSynchronize();
   h->plans.clear();
   if (h->ws) (void)hipFree(h->ws);
+  if (h->rows_buf) (void)hipFree(h->rows_buf);
   if (h->status) (void)hipFree(h->status);
   delete h;
   return CN_OK;
@@ -1077,8 +1091,8 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
   struct Cand {
     int T, M;
   };
-  const Cand cands[] = {{128, 2}, {256, 4}, {512, 4}, {1024, 4}, {2048, 4}, {4096, 4},
-                        {512, 8}, {1024, 8}, {2048, 8}, {4096, 8}};
+  const Cand cands[] = {{0, 0},    {128, 2},  {256, 4},  {512, 4},  {1024, 4}, {2048, 4},
+                        {4096, 4}, {512, 8},  {1024, 8}, {2048, 8}, {4096, 8}};
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -1089,7 +1103,7 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
     cn_layout L2 = *L;
     L2.partition = cd_.T;
     L2.rows_per_thread = cd_.M;
-    if (L->offsets) {  // persistent launch: only the configurations it is built for
+    if (L->offsets && cd_.T > 0) {  // persistent launch: only the configurations it is built for
       const int ci = find_cfg(cd_.T, cd_.M);
       if (ci < 0 || !g_pers[ci][src]) continue;
     }
@@ -1127,7 +1141,10 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
     std::sort(ts.begin(), ts.end());
     const float med = ts[ts.size() / 2];
     char line[160];
-    snprintf(line, sizeof(line), "T=%d M=%d: %.4f ms; ", cd_.T, cd_.M, med);
+    if (cd_.T > 0)
+      snprintf(line, sizeof(line), "T=%d M=%d: %.4f ms; ", cd_.T, cd_.M, med);
+    else
+      snprintf(line, sizeof(line), "automatic: %.4f ms; ", med);
     rep += line;
     if (med < best) {
       best = med;
@@ -1157,9 +1174,26 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   st = get_plan(h, L, nsd::SRC_CN, s, &P);
   if (st != CN_OK) return st;
   cd* lam = (cd*)((char*)h->ws + P->o_aux);
-  double* part = (double*)((char*)h->ws + P->o_part);
   cd* segs = (cd*)seg;
   const int64_t span = P->span;
+  // dE: every step of a segment writes its row of per-tile partials; one launch per segment
+  // sums the rows (the same fixed order as one sum per step)
+  double* part = nullptr;
+  if (dE) {
+    const size_t need = (size_t)std::min<int64_t>(K, nsteps) * (size_t)P->ntiles1;
+    if (h->rows_cap < need) {
+      if (capturing(s)) return CN_ERR_NOT_RESERVED;
+      if (h->rows_buf) {
+        if (hipDeviceSynchronize() != hipSuccess) return CN_ERR_HIP;
+        (void)hipFree(h->rows_buf);
+        h->rows_buf = nullptr;
+        h->rows_cap = 0;
+      }
+      if (hipMalloc(&h->rows_buf, need * sizeof(double)) != hipSuccess) return CN_ERR_NO_MEMORY;
+      h->rows_cap = need;
+    }
+    part = h->rows_buf;
+  }
   auto Ek = [&](int64_t k) { return E ? E[k] : 0.0; };
   const int64_t nseg = (nsteps + K - 1) / K;
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
@@ -1204,15 +1238,15 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
       u.acc_pa = segs + (k - k0) * span;
       u.acc_pb = segs + (k - k0 + 1) * span;
       u.acc_dV = dV_accum;
-      u.acc_part = dE ? part : nullptr;
+      u.acc_part = dE ? part + (k - k0) * P->ntiles1 : nullptr;
       u.acc_tau = 0.5 * op->dt;
       st = run_plan(h, P, u, s);
       if (st != CN_OK) return st;
-      if (dE) {
-        hipLaunchKernelGGL(nsd::k_sum_partials, dim3(1), dim3(256), 0, s, (const double*)part,
-                           P->ntiles1, dE + k);
-        if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
-      }
+    }
+    if (dE) {
+      hipLaunchKernelGGL(nsd::k_sum_partials, dim3((unsigned)(k1 - k0)), dim3(256), 0, s,
+                         (const double*)part, P->ntiles1, dE + k0);
+      if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
     }
   }
   // gradient at psi_0: G_0 = T_0 lambda_0 = (1 + i tau H_0) lambda_0

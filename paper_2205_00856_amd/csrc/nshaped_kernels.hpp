@@ -1078,10 +1078,13 @@ __global__ __launch_bounds__(256) void k_adj_accum(AuxArgs A) {
   if (threadIdx.x == 0) A.dE_part[blockIdx.x] = red[0];
 }
 
-// deterministic second stage: out[0] = sum of nparts partials (one workgroup, fixed order)
+// deterministic second stage: workgroup r sets out[r] = sum of the nparts partials in row r of
+// part (rows of nparts values), in a fixed order
 __global__ __launch_bounds__(256) void k_sum_partials(const double* part, int64_t nparts,
                                                       double* out) {
   __shared__ double red[256];
+  part += (int64_t)blockIdx.x * nparts;
+  out += blockIdx.x;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < nparts; i += 256) s += part[i];
   red[threadIdx.x] = s;

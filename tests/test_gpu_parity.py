@@ -258,6 +258,38 @@ def test_cn_step_uniform_batch(gpu, oracle_mod, n, batch):
     assert rel(out2.cpu().numpy(), ref) <= TOL
 
 
+# Interior wavefronts (every row and both halo rows inside the system) run a second compiled
+# path without clamps or edge selects.  In a 4096-row tile (8 wavefronts of 512 rows) the last
+# wavefront turns interior at n = 3585; the sizes straddle that and the first wavefront's edge,
+# for the fused CN step and for the explicit solve (single tile and two-pass tiles).
+@pytest.mark.parametrize("n", [3584, 3585, 3586, 4095, 4096])
+def test_interior_wavefront_boundary_cn(gpu, oracle_mod, n):
+    torch, cn = gpu
+    log("interior boundary cn", n)
+    batch, dt = 64, 0.02
+    rng = np.random.default_rng(77 + n)
+    psi = workloads.complex_normal(rng, n * batch)
+    V = rng.uniform(-2.0, 2.0, n * batch)
+    dxs = rng.uniform(0.05, 0.2, batch)
+    offs = np.arange(batch + 1, dtype=np.int64) * n
+    ref = oracle_mod.cn_step_batched(offs, psi, V, dxs, dt, 8)
+    tV, tpsi, tdx = to_dev(torch, V, psi, dxs)
+    out = cn.step(tpsi, tV, 0.0, dt, dx_per_system=tdx, layout=cn.Layout.contiguous(n, batch))
+    assert rel(out.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("n,T,M", [(3585, 4096, 8), (3584, 4096, 8), (5 * 1024 + 1, 1024, 4),
+                                   (5 * 1024 - 1, 1024, 4), (2048 + 257, 2048, 8)])
+def test_interior_wavefront_boundary_solve(gpu, oracle_mod, n, T, M):
+    torch, cn = gpu
+    log("interior boundary solve", n, T, M)
+    a, b, c, d = workloads.random_system(n, 300 + n, "herm")
+    ref = oracle_mod.thomas(a, b, c, d)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x = cn.solve(ta, tb, tc, td, layout=cn.Layout.contiguous(n, 1, partition=T, rows_per_thread=M))
+    assert rel(x.cpu().numpy(), ref) <= TOL
+
+
 def test_cn_step_uniform_batch_repeated(gpu, oracle_mod):
     """Five chained in-place steps of 4096 x 4096 rows at one dx (the ADI x-sweep shape at
     half the lines), against the oracle stepping each line."""
@@ -354,8 +386,10 @@ def test_graph_captured_adi_step_replays(gpu, oracle_mod):
 
 
 # ------------------------------------------------------------------ persistent uneven launch
-def test_uneven_persistent_repeated_steps(gpu, oracle_mod):
-    """Three chained steps of one persistent launch each: the device queue resets itself."""
+@pytest.mark.parametrize("partition", [1024, 0])
+def test_uneven_repeated_steps(gpu, oracle_mod, partition):
+    """Three chained in-place steps: one persistent launch each (partition 1024; its device
+    queue resets itself), or the automatic per-length launches with two-pass long systems."""
     torch, cn = gpu
     wl = workloads.uneven_batch(batch=500, lo=1, hi=65_536, steps=3, seed=9)
     offs, dt = wl["offsets"], wl["dt"]
@@ -363,8 +397,9 @@ def test_uneven_persistent_repeated_steps(gpu, oracle_mod):
     for _ in range(3):
         ref = oracle_mod.cn_step_batched(offs, ref, wl["V"], wl["dx"], dt, 8)
     tV, tpsi, tdx = to_dev(torch, wl["V"], wl["psi0"], wl["dx"])
-    L = cn.Layout.uneven(offs)
-    assert "persistent" in cn.describe_plan(L, True)
+    L = cn.Layout.uneven(offs, partition=partition, rows_per_thread=4 if partition else 0)
+    plan = cn.describe_plan(L, True)
+    assert ("persistent" in plan) == (partition > 0), plan
     for _ in range(3):
         cn.step(tpsi, tV, 0.0, dt, dx_per_system=tdx, out=tpsi, layout=L)
     assert rel(tpsi.cpu().numpy(), ref) <= TOL
@@ -401,7 +436,7 @@ def test_autotune_keeps_results(gpu, oracle_mod):
     out = torch.empty_like(tpsi)
     rep = cn.autotune(L, tpsi, out, V=tV, dt=wl["dt"], dx_per_system=tdx)
     log(rep)
-    assert "chosen" in rep
+    assert "chosen" in rep and "automatic" in rep
     out2 = cn.step(tpsi, tV, 0.0, wl["dt"], dx_per_system=tdx, layout=L)
     assert rel(out2.cpu().numpy(), ref) <= TOL
     n = 200_000
