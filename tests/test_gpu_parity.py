@@ -141,6 +141,81 @@ def test_breakdown_flag(gpu):
     assert cn.get_status() == 0  # the flag clears
 
 
+def test_breakdown_flag_nan_rhs(gpu):
+    """A NaN in d propagates to x; the status flag reports it and the call itself succeeds."""
+    torch, cn = gpu
+    a, b, c, d = workloads.random_system(3000, 4, "dd")
+    d[1777] = np.nan
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    x = cn.solve(ta, tb, tc, td)
+    assert not torch.isfinite(x).all()
+    assert cn.get_status() == 1
+    assert cn.get_status() == 0
+
+
+@pytest.mark.parametrize("n,batch,es,bs", [(1000, 5, 3, 3100), (300, 6, 2, 700),
+                                          (700, 70, 77, 1), (33, 64, 70, 1)])
+def test_solve_strided_with_padding(gpu, oracle_mod, n, batch, es, bs):
+    """Row stride > 1 with gaps between systems, and interleaved systems with padding columns;
+    the padding elements must stay untouched."""
+    torch, cn = gpu
+    log("strided", n, batch, es, bs)
+    span = (batch - 1) * bs + (n - 1) * es + 1
+    rng = np.random.default_rng(n + es)
+    a, b, c, d = workloads.random_system(n * batch, 40 + n, "herm")
+    idx = (np.arange(batch)[:, None] * bs + np.arange(n)[None, :] * es).ravel()
+    bufs = []
+    for v in (a, b, c, d):
+        full = workloads.complex_normal(rng, span)
+        full[idx] = v
+        bufs.append(full)
+    offs = np.arange(batch + 1) * n
+    ref = oracle_mod.thomas_batched(offs, a, b, c, d, nthreads=8)
+    ta, tb, tc, td = to_dev(torch, *bufs)
+    x0 = workloads.complex_normal(rng, span)
+    tx = to_dev(torch, x0)[0]
+    L = cn.Layout(n=n, batch=batch, elem_stride=es, batch_stride=bs)
+    cn.solve(ta, tb, tc, td, out=tx, layout=L)
+    out = tx.cpu().numpy()
+    assert rel(out[idx], ref) <= TOL
+    pad = np.setdiff1d(np.arange(span), idx)
+    assert np.array_equal(out[pad], x0[pad])
+
+
+def test_capture_without_reserve_is_refused(gpu):
+    """A layout whose plan or workspace does not exist yet cannot be used inside a graph
+    capture: the call returns CN_ERR_NOT_RESERVED and launches nothing."""
+    torch, cn = gpu
+    from paper_2205_00856_amd import _lib
+
+    n = 12_345  # a layout no other test plans
+    rng = np.random.default_rng(5)
+    psi = to_dev(torch, workloads.complex_normal(rng, n))[0]
+    V = to_dev(torch, rng.uniform(-1, 0, n))[0]
+    out = torch.empty_like(psi)
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    err = None
+    try:
+        with torch.cuda.graph(g, stream=side):
+            cn.step(psi, V, 0.1, 0.01, out=out, layout=cn.Layout.contiguous(n, 1))
+    except _lib.CnError as ex:
+        err = ex
+    except RuntimeError as ex:  # the capture context may wrap the library error
+        err = ex
+    assert err is not None and "NOT_RESERVED" in str(err)
+    torch.cuda.synchronize()
+    # after cn.reserve the same call captures and replays
+    cn.reserve(cn.Layout.contiguous(n, 1))
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=side):
+        cn.step(psi, V, 0.1, 0.01, out=out, layout=cn.Layout.contiguous(n, 1))
+    g2.replay()
+    torch.cuda.synchronize()
+    ref = cn.step(psi, V, 0.1, 0.01, layout=cn.Layout.contiguous(n, 1))
+    assert torch.equal(out, ref)
+
+
 # ------------------------------------------------------------------ assembly, rhs, step
 @pytest.mark.parametrize("field", [False, True])
 def test_assemble_and_rhs(gpu, oracle_mod, field):
