@@ -162,7 +162,12 @@ cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_
  * runs backwards through it as Crank-Nicolson steps with dt -> -dt, accumulating
  *   dV_accum_j += v_scale tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (may be NULL)
  *   dE[k] = sum_j xgrid_j tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (needs xgrid; may be NULL)
- * in fixed order; finally g = T_0 lambda_0. */
+ * in fixed order; finally g = T_0 lambda_0.  With two or more segments and a stream that is
+ * not being captured, the recompute of segment s-1 runs on a second stream of the handle while
+ * the recursion runs through segment s; the handle then keeps a second segment buffer and a
+ * second workspace (allocated on first use).  The results are the same in either form; the
+ * call is ordered on the caller's stream as usual.  Under graph capture the segments run one
+ * after the other on the caller's stream. */
 cn_status cn_propagate_adjoint(cn_handle_t handle, const cn_layout* layout,
                                const cn_operator* op, int64_t nsteps, const double* E,
                                const void* ckpt, int64_t K, void* seg, void* g,

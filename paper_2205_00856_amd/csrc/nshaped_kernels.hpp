@@ -409,18 +409,42 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
   // whole tile (the empty asm hides that they are equal)
   int sl = lane;
   asm volatile("" : "+v"(sl));
+  if (!acc) {
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const int64_t r = w0 + 64 * k + sl;
-    if (row_in<IN>(r, G.n)) {
-      const cd v = buf[S::addr(1 + 64 * k + sl)];
+    for (int k = 0; k < M; ++k) {
+      const int64_t r = w0 + 64 * k + sl;
+      if (row_in<IN>(r, G.n)) g[r * G.es] = buf[S::addr(1 + 64 * k + sl)];
+    }
+  } else {
+    // all loads of the tile's rows first: the stores below may alias them as far as the
+    // compiler knows, which would otherwise cost one memory round trip per row
+    cd s[M];
+    double dv[M], xv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int64_t r = w0 + 64 * k + sl;
       const int64_t e = G.base + r * G.es;
-      g[r * G.es] = v;
-      if (acc) {
-        const cd s = cadd(A.acc_pa[e], A.acc_pb[e]);
-        const double q = A.acc_tau * (v.x * s.y - v.y * s.x);
-        if (A.acc_dV) A.acc_dV[e] += A.vscale * q;
-        if (A.xg) part = fma(A.xg[e], q, part);
+      cd sk = czero();
+      double d0 = 0.0, x0 = 0.0;
+      if (row_in<IN>(r, G.n)) {
+        sk = cadd(A.acc_pa[e], A.acc_pb[e]);
+        if (A.acc_dV) d0 = A.acc_dV[e];
+        if (A.xg) x0 = A.xg[e];
+      }
+      s[k] = sk;
+      dv[k] = d0;
+      xv[k] = x0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int64_t r = w0 + 64 * k + sl;
+      if (row_in<IN>(r, G.n)) {
+        const cd v = buf[S::addr(1 + 64 * k + sl)];
+        const int64_t e = G.base + r * G.es;
+        g[r * G.es] = v;
+        const double q = A.acc_tau * (v.x * s[k].y - v.y * s[k].x);
+        if (A.acc_dV) A.acc_dV[e] = dv[k] + A.vscale * q;
+        if (A.xg) part = fma(xv[k], q, part);
       }
     }
   }

@@ -61,9 +61,10 @@ def test_cnsolve_gradcheck(gpu):
     assert torch.autograd.gradcheck(f, args, eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
-def test_cnpropagate_matches_oracle_reverse_mode(gpu, oracle_mod):
+@pytest.mark.parametrize("n,steps,K", [(6000, 45, 7), (1 << 20, 5, 2)])
+def test_cnpropagate_matches_oracle_reverse_mode(gpu, oracle_mod, n, steps, K):
     torch, cn, ag = gpu
-    n, dx, dt, steps, K = 6000, 0.05, 0.01, 45, 7
+    dx, dt = 0.05, 0.01
     x = workloads.grid_1d(n, dx)
     V = workloads.softcore(x)
     E = np.random.default_rng(2).normal(0, 0.05, steps)

@@ -401,7 +401,7 @@ def test_solve_adjoint(gpu, oracle_mod, n):
     assert rel(gc_.cpu().numpy(), gc) <= TOL
 
 
-@pytest.mark.parametrize("n", [50, 5000, 300_001])
+@pytest.mark.parametrize("n", [50, 5000, 300_001, 1 << 20])
 def test_step_adjoint(gpu, oracle_mod, n):
     torch, cn = gpu
     dx, dt, E = 0.05, 0.01, 0.02
@@ -458,6 +458,51 @@ def test_graph_captured_adi_step_replays(gpu, oracle_mod):
         step(junk)  # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(psi, eager)
+
+
+def test_propagate_adjoint_overlapped_equals_captured(gpu):
+    """Reverse mode run eagerly (the recompute of the next segment overlapped on a second
+    stream) and replayed from a graph capture (segments one after the other on the captured
+    stream) give the same bits for g, dV and dE; eager work runs between the replays."""
+    torch, cn = gpu
+    n, dx, dt, steps, K = 50_000, 0.05, 0.01, 23, 5
+    rng = np.random.default_rng(21)
+    x = workloads.grid_1d(n, dx)
+    V = workloads.softcore(x)
+    E = rng.normal(0, 0.05, steps)
+    tV, tx, tpsi = to_dev(torch, V, x, workloads.gaussian(x, 0.0, 5.0, 1.0, dx))
+    gT = to_dev(torch, workloads.complex_normal(rng, n))[0]
+    L = cn.Layout.contiguous(n, 1)
+    ckpt = torch.empty(((steps + K - 1) // K) * n, dtype=torch.complex128, device="cuda")
+    cn.propagate(tpsi.clone(), tV, dx, dt, steps, E=E, xgrid=tx, ckpt=ckpt, K=K, layout=L)
+    seg = torch.empty((K + 1) * n, dtype=torch.complex128, device="cuda")
+
+    def fresh():
+        return (gT.clone(), torch.zeros(n, dtype=torch.float64, device="cuda"),
+                torch.zeros(steps, dtype=torch.float64, device="cuda"))
+
+    def run(g, dV, dE):
+        cn.propagate_adjoint(ckpt, g, tV, dx, dt, steps, K, E=E, xgrid=tx, dV=dV, dE=dE,
+                             seg=seg, layout=L)
+
+    ge, dVe, dEe = fresh()
+    run(ge, dVe, dEe)
+    torch.cuda.synchronize()
+    gc, dVc, dEc = fresh()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        run(gc, dVc, dEc)
+    for _ in range(3):
+        gc.copy_(gT)
+        dVc.zero_()
+        dEc.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        run(*fresh())  # eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.equal(gc, ge) and torch.equal(dVc, dVe) and torch.equal(dEc, dEe)
 
 
 # ------------------------------------------------------------------ persistent uneven launch
