@@ -153,6 +153,15 @@ bool bwd_overlap_enabled() {
   return on;
 }
 
+// second passes take their tiles in reverse order (CN_REV=0 turns it off)
+bool rev_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_REV");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 // XCD-contiguous order of whole-system workgroups (CN_XCD_REMAP=0 turns it off)
 bool xcd_remap_enabled() {
   static const bool on = [] {
@@ -274,6 +283,7 @@ void add_launch(std::vector<Launch>& L, int ci, int src, int ph, dim3 grid, int 
   l.grid = grid;
   l.threads = 64 * kCfgs[ci].W;
   l.a = a;
+  l.a.rev = (ph == nsd::PH_SUBST && rev_enabled()) ? 1 : 0;
   l.level = level;
   l.src = src;
   l.ph = ph;
@@ -321,6 +331,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
         l.grid = dim3((unsigned)(K * gy));
         l.threads = 64 * kColCfgs[cc].W;
         l.a = a;
+        l.a.rev = (ph == nsd::PH_SUBST && rev_enabled()) ? 1 : 0;
         l.level = level;
         l.src = src;
         l.ph = ph;

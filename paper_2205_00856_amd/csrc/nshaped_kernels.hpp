@@ -61,6 +61,8 @@ struct KArgs {
   double* acc_part;
   double acc_tau;
   int64_t batch;          // uniform batch size (column kernel)
+  int rev;                // workgroups take their tiles in reverse launch order (second pass:
+                          // the tiles the first pass read last are still in the memory-side cache)
 };
 
 struct Geo {
@@ -69,9 +71,11 @@ struct Geo {
 
 __device__ __forceinline__ Geo geometry(const KArgs& A) {
   Geo g;
+  const unsigned bx = A.rev ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+  const unsigned by = A.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   if (A.wg_sys) {
-    g.sys = A.wg_sys[blockIdx.x];
-    g.tile = A.wg_tile[blockIdx.x];
+    g.sys = A.wg_sys[bx];
+    g.tile = A.wg_tile[bx];
   } else if (A.xcd_remap && gridDim.x == 1) {
     // Workgroups are handed to the 8 XCDs round-robin by linear id; give each XCD a contiguous
     // range of systems so that neighbouring (interleaved) systems share its L2.
@@ -79,8 +83,8 @@ __device__ __forceinline__ Geo geometry(const KArgs& A) {
     g.sys = x * q + (x < r ? x : r) + (id >> 3);
     g.tile = 0;
   } else {
-    g.sys = blockIdx.y;
-    g.tile = blockIdx.x;
+    g.sys = by;
+    g.tile = bx;
   }
   if (A.offs) {
     g.base = A.offs[g.sys];
@@ -702,7 +706,8 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   // consecutive workgroups take neighbouring column groups of the same rows, so the rows that
   // run concurrently are read as long contiguous runs
   const int64_t ncg = (A.batch + 63) / 64;
-  const int64_t cg = (int64_t)blockIdx.x % ncg;
+  const int64_t bid = A.rev ? (int64_t)(gridDim.x - 1 - blockIdx.x) : (int64_t)blockIdx.x;
+  const int64_t cg = bid % ncg;
   const int64_t sys = cg * 64 + lane;
   const bool live = sys < A.batch;
   // the batch stride is 1: system s starts at element s; lanes address their system as the
@@ -715,7 +720,7 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   G.n = A.n;
   G.es = A.es;
   G.base = G.sys * A.bs;
-  G.tile = (int64_t)blockIdx.x / ncg;
+  G.tile = bid / ncg;
   G.ntile = A.ntiles;
   G.gt = G.sys * A.ntiles + G.tile;
   const int64_t r0 = G.tile * T + (int64_t)wave * M;
