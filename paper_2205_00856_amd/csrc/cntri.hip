@@ -153,7 +153,8 @@ bool bwd_overlap_enabled() {
   return on;
 }
 
-// second passes take their tiles in reverse order (CN_REV=0 turns it off)
+// second passes take their tiles in reverse order (CN_REV=0 turns it off) when the level holds
+// at least 2^21 rows; smaller levels stay in the XCDs' L2 between the passes anyway
 bool rev_enabled() {
   static const bool on = [] {
     const char* e = getenv("CN_REV");
@@ -161,6 +162,7 @@ bool rev_enabled() {
   }();
   return on;
 }
+int rev_for(int64_t rows) { return (rev_enabled() && rows >= ((int64_t)1 << 21)) ? 1 : 0; }
 
 // XCD-contiguous order of whole-system workgroups (CN_XCD_REMAP=0 turns it off)
 bool xcd_remap_enabled() {
@@ -283,7 +285,6 @@ void add_launch(std::vector<Launch>& L, int ci, int src, int ph, dim3 grid, int 
   l.grid = grid;
   l.threads = 64 * kCfgs[ci].W;
   l.a = a;
-  l.a.rev = (ph == nsd::PH_SUBST && rev_enabled()) ? 1 : 0;
   l.level = level;
   l.src = src;
   l.ph = ph;
@@ -331,8 +332,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
         l.grid = dim3((unsigned)(K * gy));
         l.threads = 64 * kColCfgs[cc].W;
         l.a = a;
-        l.a.rev = (ph == nsd::PH_SUBST && rev_enabled()) ? 1 : 0;
-        l.level = level;
+              l.level = level;
         l.src = src;
         l.ph = ph;
         l.cfg = -1;
@@ -365,6 +365,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       for (int64_t s2 = 0; s2 <= batch; ++s2) ib.offs[s2] = s2 * K;
       plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
       add_col(nsd::PH_SUBST);
+      L.back().a.rev = rev_for(n * batch);
       L.back().o_psi_if = oP;
       L.back().o_hin = oH;
       return;
@@ -416,6 +417,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     for (int64_t s = 0; s <= batch; ++s) ib.offs[s] = s * K;
     plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
     add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)K, (unsigned)batch), level, a);
+    L.back().a.rev = rev_for(n * batch);
     set_common(L.back());
     L.back().o_psi_if = oP;
     L.back().o_hin = oH;
@@ -566,6 +568,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
   add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)wgs.size()), level, a);
   set_common(L.back());
+  L.back().a.rev = rev_for(nl);
   L.back().t_offs = t_offs;
   L.back().t_tbase = t_tb;
   L.back().t_wgs = t_s;

@@ -61,18 +61,31 @@ struct KArgs {
   double* acc_part;
   double acc_tau;
   int64_t batch;          // uniform batch size (column kernel)
-  int rev;                // workgroups take their tiles in reverse launch order (second pass:
-                          // the tiles the first pass read last are still in the memory-side cache)
+  int rev;                // workgroups take their tiles in reverse launch order, by rounds of 8
+                          // (second pass: the tiles the first pass read last are still cached)
 };
 
 struct Geo {
   int64_t sys, tile, n, base, es, gt, ntile;
 };
 
+// Launch position of a second-pass workgroup: the launch order reversed in rounds of 8.
+// Workgroups go to the 8 XCDs round-robin by linear id, so each tile keeps the XCD (and the L2)
+// of its first pass while the tiles that pass read last come first.
+__device__ __forceinline__ int64_t rev_linear(int64_t L, int64_t G) {
+  const int64_t Q = G >> 3;
+  if (L >= 8 * Q) return L;
+  return 8 * (Q - 1 - (L >> 3)) + (L & 7);
+}
+
 __device__ __forceinline__ Geo geometry(const KArgs& A) {
   Geo g;
-  const unsigned bx = A.rev ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
-  const unsigned by = A.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
+  int64_t bx = blockIdx.x, by = blockIdx.y;
+  if (A.rev) {
+    const int64_t L = rev_linear(bx + by * gridDim.x, (int64_t)gridDim.x * gridDim.y);
+    bx = L % gridDim.x;
+    by = L / gridDim.x;
+  }
   if (A.wg_sys) {
     g.sys = A.wg_sys[bx];
     g.tile = A.wg_tile[bx];
@@ -706,7 +719,7 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   // consecutive workgroups take neighbouring column groups of the same rows, so the rows that
   // run concurrently are read as long contiguous runs
   const int64_t ncg = (A.batch + 63) / 64;
-  const int64_t bid = A.rev ? (int64_t)(gridDim.x - 1 - blockIdx.x) : (int64_t)blockIdx.x;
+  const int64_t bid = A.rev ? rev_linear(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   const int64_t cg = bid % ncg;
   const int64_t sys = cg * 64 + lane;
   const bool live = sys < A.batch;

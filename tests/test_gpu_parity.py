@@ -41,7 +41,7 @@ def log(*a):
 
 # ------------------------------------------------------------------ cn_tridiag_solve
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 65, 127, 128, 129, 255, 256, 257, 1000, 1024,
-                               1025, 4095, 4096, 4097, 10_000, 65_537, 1_000_003])
+                               1025, 4095, 4096, 4097, 10_000, 65_537, 1_000_003, 3_000_017])
 @pytest.mark.parametrize("kind", ["dd", "herm"])
 def test_solve_single_system(gpu, oracle_mod, n, kind):
     torch, cn = gpu
@@ -234,7 +234,7 @@ def test_assemble_and_rhs(gpu, oracle_mod, field):
         assert rel(g.cpu().numpy(), r) <= 1e-14
 
 
-@pytest.mark.parametrize("n", [1, 2, 100, 4096, 4097, 65_536, 100_003, 1 << 20])
+@pytest.mark.parametrize("n", [1, 2, 100, 4096, 4097, 65_536, 100_003, 1 << 20, 2_100_003])
 def test_cn_step(gpu, oracle_mod, n):
     torch, cn = gpu
     log("cn_step", n)
