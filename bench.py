@@ -418,6 +418,20 @@ def extras(torch, np, cn, workloads, dev):
         ts = timed_events(torch, lambda: cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi,
                                                  layout=L), wl["steps"])
         med = float(np.median(ts))
+        # the same 50 steps as one cn_propagate call (two-pass systems fused across steps),
+        # against 50 single steps from the same state
+        p0 = psi.clone()
+        pstep = p0.clone()
+        for _ in range(wl["steps"]):
+            cn.step(pstep, V, 0.0, wl["dt"], dx_per_system=dxs, out=pstep, layout=L)
+        pprop = p0.clone()
+        cn.propagate(pprop, V, 0.0, wl["dt"], wl["steps"], dx_per_system=dxs, layout=L)
+        prop_vs_steps = rel_l2(pprop.cpu().numpy(), pstep.cpu().numpy())
+        del pstep
+        tsq = timed_events(torch, lambda: cn.propagate(pprop, V, 0.0, wl["dt"], wl["steps"],
+                                                       dx_per_system=dxs, layout=L), 3)
+        med_prop = float(np.median(tsq)) / wl["steps"]
+        del pprop, p0
         # the fixed-plan baseline: one persistent launch over all systems (1024-row tiles)
         Lp = cn.Layout.uneven(wl["offsets"], partition=1024, rows_per_thread=4)
         cn.reserve(Lp)
@@ -427,6 +441,8 @@ def extras(torch, np, cn, workloads, dev):
                                "ms_per_step": med, "unknowns_per_s": rows / (med * 1e-3),
                                "GBps_40": BYTES_PER_UNKNOWN_STEP * rows / (med * 1e-3) / 1e9,
                                "plan": cn.describe_plan(L, True)[:400],
+                               "ms_per_step_propagate": med_prop,
+                               "propagate_vs_single_steps_rel_l2": prop_vs_steps,
                                "persistent_plan_ms_per_step": float(np.median(tsp)),
                                "persistent_plan": cn.describe_plan(Lp, True)[:200]}
         nthr = cpu_threads()

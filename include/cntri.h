@@ -137,7 +137,12 @@ cn_status cn_step(cn_handle_t handle, const cn_layout* layout, const cn_operator
 
 /* nsteps chained cn_step calls in place on psi.  E: HOST array of nsteps field
  * values, or NULL for no field.  If ckpt is non-NULL, the state before step k is copied to
- * ckpt + (k / K) * (rows of the layout) for every k divisible by K (K >= 1). */
+ * ckpt + (k / K) * (rows of the layout) for every k divisible by K (K >= 1).
+ * Systems solved in two passes (longer than one tile) run one fused pass per step: the
+ * substitution of step k and the reduction of step k+1 (whose joint rows take the left
+ * neighbour's explicit half-step term in the reduced system instead).  The result equals the
+ * chain of cn_step calls up to rounding (not bit for bit); CN_FUSE=0 in the environment turns
+ * the fusion off. */
 cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_operator* op,
                        int64_t nsteps, const double* E, void* psi, void* ckpt, int64_t K,
                        cn_stream_t stream);

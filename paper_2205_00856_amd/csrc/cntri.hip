@@ -32,13 +32,15 @@ constexpr Cfg kCfgs[] = {{2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 1}
 constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 typedef void (*KFn)(KArgs);
-const void* g_kern[kNumCfg][4][3];
+const void* g_kern[kNumCfg][4][4];
 
 template <int M, int W, int SRC>
 void reg_src(int ci) {
   g_kern[ci][SRC][nsd::PH_SINGLE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_SINGLE>;
   g_kern[ci][SRC][nsd::PH_REDUCE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_REDUCE>;
   g_kern[ci][SRC][nsd::PH_SUBST] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_SUBST>;
+  if constexpr (SRC == nsd::SRC_CN)
+    g_kern[ci][SRC][nsd::PH_FUSE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_FUSE>;
 }
 template <int M, int W>
 void reg_cfg(int ci) {
@@ -198,6 +200,7 @@ struct Launch {
   // workspace offsets (bytes) or -1
   int64_t o_sU = -1, o_sD = -1, o_oU = -1, o_oD = -1, o_x = -1, o_psi_if = -1, o_hout = -1,
           o_hin = -1;
+  int64_t o_hout2 = -1;  // second edge-row array of a Crank-Nicolson first pass (PH_FUSE chains)
 };
 
 struct Plan {
@@ -397,6 +400,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
     const int64_t oP = B.add_ws(G * sizeof(cd));
     const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+    const int64_t oH2 = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
     KArgs a = base;
     a.n = n;
     a.ntiles = K;
@@ -410,6 +414,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     L.back().o_oU = oU;
     L.back().o_oD = oD;
     L.back().o_hout = oH;
+    L.back().o_hout2 = oH2;
     BatchDesc ib;
     ib.uneven = true;
     ib.batch = batch;
@@ -417,7 +422,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     for (int64_t s = 0; s <= batch; ++s) ib.offs[s] = s * K;
     plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
     add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)K, (unsigned)batch), level, a);
-    L.back().a.rev = rev_for(n * batch);
+    L.back().a.rev = batch == 1 ? rev_for(n) : 0;  // one-dimensional grids only
     set_common(L.back());
     L.back().o_psi_if = oP;
     L.back().o_hin = oH;
@@ -545,6 +550,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
   const int64_t oP = B.add_ws(G * sizeof(cd));
   const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+  const int64_t oH2 = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
   const int64_t t_tb = B.add_tab(tbase.data(), (batch + 1) * sizeof(int64_t));
   const int64_t t_s = B.add_tab(wgs.data(), wgs.size() * sizeof(int));
   const int64_t t_t = B.add_tab(wgt.data(), wgt.size() * sizeof(int));
@@ -561,6 +567,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   L.back().o_oU = oU;
   L.back().o_oD = oD;
   L.back().o_hout = oH;
+  L.back().o_hout2 = oH2;
   BatchDesc ib;
   ib.uneven = true;
   ib.batch = batch;
@@ -755,44 +762,177 @@ struct UserArgs {
   double acc_tau = 0.0;
 };
 
+// Kernel arguments of one launch of a plan for the caller's arrays u and workspace ws.
+KArgs plan_args(cn_handle_t h, const Launch& l, const UserArgs& u, char* ws) {
+  KArgs a = l.a;
+  if (l.level == 1) {
+    a.a = u.a;
+    a.b = u.b;
+    a.c = u.c;
+    a.d = u.d;
+    a.psi = u.psi;
+    a.rhs = u.rhs;
+    a.V = u.V;
+    a.xg = u.xg;
+    a.dxs = u.dxs;
+    a.vscale = u.vscale;
+    a.E_mat = u.E_mat;
+    a.E_rhs = u.E_rhs;
+    a.dx = u.dx;
+    a.dt = u.dt;
+    a.acc_pa = u.acc_pa;
+    a.acc_pb = u.acc_pb;
+    a.acc_dV = u.acc_dV;
+    a.acc_part = u.acc_part;
+    a.acc_tau = u.acc_tau;
+  }
+  a.x = (l.o_x >= 0) ? (cd*)(ws + l.o_x) : u.x;
+  if (l.o_sU >= 0) a.sU = (const cd*)(ws + l.o_sU);
+  if (l.o_sD >= 0) a.sD = (const cd*)(ws + l.o_sD);
+  if (l.o_oU >= 0) a.oU = (cd*)(ws + l.o_oU);
+  if (l.o_oD >= 0) a.oD = (cd*)(ws + l.o_oD);
+  if (l.o_psi_if >= 0) a.psi_if = (const cd*)(ws + l.o_psi_if);
+  if (l.o_hout >= 0) a.halo_out = (cd*)(ws + l.o_hout);
+  if (l.o_hin >= 0) a.halo_in = (const cd*)(ws + l.o_hin);
+  a.status = h->status;
+  return a;
+}
+
+cn_status launch_k(const void* fn, const Launch& l, KArgs& a, hipStream_t s) {
+  void* params[] = {&a};
+  if (hipLaunchKernel(fn, l.grid, dim3(l.threads), params, 0, s) != hipSuccess) return CN_ERR_HIP;
+  return CN_OK;
+}
+
 cn_status run_plan(cn_handle_t h, Plan* P, const UserArgs& u, hipStream_t s,
                    void* ws_base = nullptr) {
   char* ws = (char*)(ws_base ? ws_base : h->ws);
   for (const Launch& l : P->L) {
-    KArgs a = l.a;
+    KArgs a = plan_args(h, l, u, ws);
+    cn_status st = launch_k(l.fn, l, a, s);
+    if (st != CN_OK) return st;
+  }
+  return CN_OK;
+}
+
+// Cross-step fusion of a Crank-Nicolson sequence (Sec. 5.3 fuses the explicit half-step into
+// the solve; here the solve's second pass also takes the next step's first pass).  A plan
+// qualifies when its level-1 launches are whole-system tiles plus one two-pass group (first
+// pass, the levels of its reduced system, second pass) of row tiles.
+struct FusePlan {
+  bool ok = false;
+  int red = -1, sub = -1;
+  std::vector<int> singles, mids;
+};
+
+FusePlan fuse_plan(const Plan* P) {
+  FusePlan f;
+  for (int i = 0; i < (int)P->L.size(); ++i) {
+    const Launch& l = P->L[i];
     if (l.level == 1) {
-      a.a = u.a;
-      a.b = u.b;
-      a.c = u.c;
-      a.d = u.d;
-      a.psi = u.psi;
-      a.rhs = u.rhs;
-      a.V = u.V;
-      a.xg = u.xg;
-      a.dxs = u.dxs;
-      a.vscale = u.vscale;
-      a.E_mat = u.E_mat;
-      a.E_rhs = u.E_rhs;
-      a.dx = u.dx;
-      a.dt = u.dt;
-      a.acc_pa = u.acc_pa;
-      a.acc_pb = u.acc_pb;
-      a.acc_dV = u.acc_dV;
-      a.acc_part = u.acc_part;
-      a.acc_tau = u.acc_tau;
+      if (l.cfg < 0 || l.src != nsd::SRC_CN) return f;
+      if (l.ph == nsd::PH_SINGLE && l.fn == g_kern[l.cfg][l.src][nsd::PH_SINGLE] && f.red < 0) {
+        f.singles.push_back(i);
+      } else if (l.ph == nsd::PH_REDUCE && f.red < 0 && l.o_hout2 >= 0 &&
+                 l.fn == g_kern[l.cfg][l.src][nsd::PH_REDUCE]) {
+        f.red = i;
+      } else if (l.ph == nsd::PH_SUBST && f.red >= 0 && f.sub < 0 &&
+                 l.fn == g_kern[l.cfg][l.src][nsd::PH_SUBST] && l.cfg == P->L[f.red].cfg) {
+        f.sub = i;
+      } else {
+        return f;
+      }
+    } else {
+      if (f.red < 0 || f.sub >= 0) return f;
+      f.mids.push_back(i);
     }
-    a.x = (l.o_x >= 0) ? (cd*)(ws + l.o_x) : u.x;
-    if (l.o_sU >= 0) a.sU = (const cd*)(ws + l.o_sU);
-    if (l.o_sD >= 0) a.sD = (const cd*)(ws + l.o_sD);
-    if (l.o_oU >= 0) a.oU = (cd*)(ws + l.o_oU);
-    if (l.o_oD >= 0) a.oD = (cd*)(ws + l.o_oD);
-    if (l.o_psi_if >= 0) a.psi_if = (const cd*)(ws + l.o_psi_if);
-    if (l.o_hout >= 0) a.halo_out = (cd*)(ws + l.o_hout);
-    if (l.o_hin >= 0) a.halo_in = (const cd*)(ws + l.o_hin);
-    a.status = h->status;
-    void* params[] = {&a};
-    if (hipLaunchKernel(l.fn, l.grid, dim3(l.threads), params, 0, s) != hipSuccess)
-      return CN_ERR_HIP;
+  }
+  f.ok = f.red >= 0 && f.sub >= 0;
+  return f;
+}
+
+// cross-step fusion of cn_propagate (CN_FUSE=0 turns it off)
+bool fuse_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_FUSE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// Steps k0 .. k1-1 (k1 - k0 >= 2) of a Crank-Nicolson sequence over a fusable plan: the state
+// before step k is at base + (k - k0) * stride and step k writes base + (k - k0 + 1) * stride
+// (stride 0: in place).  First pass of step k0; levels above; then per step k: whole-system
+// tiles of step k, and either PH_FUSE (second pass of step k + first pass of step k+1; the
+// levels above then add the deferred joint-row terms from its edge rows) or, at the last step,
+// the second pass.  The two edge-row arrays alternate: a pass reads the state's edge rows
+// written by the pass before and writes those of its own new state.  Second passes of large
+// levels alternate their direction, so that each starts on the tiles its predecessor wrote
+// last.  In place, the state before every step k with k % K == 0 is copied to ckpt.
+cn_status run_fused(cn_handle_t h, Plan* P, const FusePlan& f, const UserArgs& u0, int64_t k0,
+                    int64_t k1, cd* base, int64_t stride, const double* E, cd* ckpt, int64_t K,
+                    hipStream_t s, void* ws_base = nullptr) {
+  char* ws = (char*)(ws_base ? ws_base : h->ws);
+  const Launch& R = P->L[f.red];
+  const Launch& S = P->L[f.sub];
+  cd* H[2] = {(cd*)(ws + R.o_hout), (cd*)(ws + R.o_hout2)};
+  auto Ek = [&](int64_t k) { return E ? E[k] : 0.0; };
+  auto with_E = [&](int64_t k) {
+    UserArgs v = u0;
+    v.E_mat = v.E_rhs = Ek(k);
+    v.psi = base + (k - k0) * stride;
+    v.x = base + (k - k0 + 1) * stride;
+    return v;
+  };
+  auto mids = [&](const cd* hal) -> cn_status {
+    for (int i : f.mids) {
+      const Launch& l = P->L[i];
+      KArgs a = plan_args(h, l, u0, ws);
+      if (hal && l.level == 2) {
+        a.ud_halo = hal;
+        a.dt = u0.dt;
+        a.dx = u0.dx;
+        a.dxs = u0.dxs;
+      }
+      cn_status st = launch_k(l.fn, l, a, s);
+      if (st != CN_OK) return st;
+    }
+    return CN_OK;
+  };
+  cn_status st;
+  if (ckpt && k0 % K == 0)
+    HIP_TRY(hipMemcpyAsync(ckpt + (k0 / K) * P->span, base, P->span * sizeof(cd),
+                           hipMemcpyDeviceToDevice, s));
+  {
+    const UserArgs v = with_E(k0);
+    KArgs a = plan_args(h, R, v, ws);
+    a.halo_out = H[0];
+    if ((st = launch_k(R.fn, R, a, s)) != CN_OK) return st;
+  }
+  if ((st = mids(nullptr)) != CN_OK) return st;
+  for (int64_t k = k0; k < k1; ++k) {
+    const UserArgs v = with_E(k);
+    for (int i : f.singles) {
+      KArgs a = plan_args(h, P->L[i], v, ws);
+      if ((st = launch_k(P->L[i].fn, P->L[i], a, s)) != CN_OK) return st;
+    }
+    KArgs a = plan_args(h, S, v, ws);
+    const int64_t i = k - k0;
+    a.halo_in = H[i & 1];
+    a.rev = S.a.rev ? (int)((i & 1) == 0) : 0;
+    if (k + 1 < k1) {
+      a.halo_out = H[(i + 1) & 1];
+      a.oU = (cd*)(ws + R.o_oU);
+      a.oD = (cd*)(ws + R.o_oD);
+      a.E_next = Ek(k + 1);
+      if ((st = launch_k(g_kern[S.cfg][nsd::SRC_CN][nsd::PH_FUSE], S, a, s)) != CN_OK) return st;
+      if (ckpt && (k + 1) % K == 0)
+        HIP_TRY(hipMemcpyAsync(ckpt + ((k + 1) / K) * P->span, v.x, P->span * sizeof(cd),
+                               hipMemcpyDeviceToDevice, s));
+      if ((st = mids(H[(i + 1) & 1])) != CN_OK) return st;
+    } else {
+      if ((st = launch_k(S.fn, S, a, s)) != CN_OK) return st;
+    }
   }
   return CN_OK;
 }
@@ -1046,6 +1186,10 @@ cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op,
   u.dx = op->dx;
   u.dt = op->dt;
   u.x = (cd*)psi;
+  if (nsteps >= 2 && fuse_enabled()) {
+    const FusePlan f = fuse_plan(P);
+    if (f.ok) return run_fused(h, P, f, u, 0, nsteps, (cd*)psi, 0, E, (cd*)ckpt, ckpt ? K : 1, s);
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
     if (ckpt && k % K == 0) {
       HIP_TRY(hipMemcpyAsync((cd*)ckpt + (k / K) * P->span, psi, P->span * sizeof(cd),
@@ -1238,7 +1382,8 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   }
   auto Ek = [&](int64_t k) { return E ? E[k] : 0.0; };
   const int64_t nseg = (nsteps + K - 1) / K;
-  // recompute segment sg forward from its checkpoint into buf (its K+1 states)
+  // recompute segment sg forward from its checkpoint into buf (its K+1 states); step by step:
+  // overlapped with the recursion, the lighter two-pass kernels measure faster than PH_FUSE
   auto recompute = [&](int64_t sg, cd* buf, void* ws, hipStream_t st) -> cn_status {
     const int64_t k0 = sg * K, k1 = std::min(nsteps, k0 + K);
     HIP_TRY(hipMemcpyAsync(buf, (const cd*)ckpt + sg * span, span * sizeof(cd),

@@ -17,7 +17,9 @@ enum Src : int {
 enum Phase : int {
   PH_SINGLE = 0,  // the tile holds the whole system: reduce, RS, SS in one pass
   PH_REDUCE = 1,  // first pass of a multi-tile system: reduce, write the tile's slots
-  PH_SUBST = 2    // second pass: re-reduce, take the tile's joint lines from above, SS
+  PH_SUBST = 2,   // second pass: re-reduce, take the tile's joint lines from above, SS
+  PH_FUSE = 3     // Crank-Nicolson sequences: PH_SUBST of step n, then PH_REDUCE of step n+1 on
+                  // the new state (the tile's joint row defers its left neighbour, see ud_halo)
 };
 
 struct KArgs {
@@ -38,9 +40,15 @@ struct KArgs {
   const double* xg;
   double vscale, E_mat, E_rhs, dx, dt;
   const double* dxs;
+  double E_next;          // PH_FUSE: field of step n+1 (matrix and explicit half-step)
   // reduced-system source (level >= 2)
   const cd* sU;           // 3 values per tile: UA, UC, UD
   const cd* sD;           // 3 values per tile: DB, DA, DD
+  // reduced system of a PH_FUSE pass: its tiles reduced the explicit half-step of their joint
+  // row without the left neighbour psi_{J-1} (the last row of the tile before, written by
+  // another workgroup of the same pass); its contribution i kap psi_{J-1} (kap from dt and
+  // dx / dxs) joins the right-hand side here, psi_{J-1} read from the pass's edge rows
+  const cd* ud_halo;
   // outputs and hand-over between passes
   cd* x;
   cd* oU;
@@ -69,22 +77,23 @@ struct Geo {
   int64_t sys, tile, n, base, es, gt, ntile;
 };
 
-// Launch position of a second-pass workgroup: the launch order reversed in rounds of 8.
-// Workgroups go to the 8 XCDs round-robin by linear id, so each tile keeps the XCD (and the L2)
-// of its first pass while the tiles that pass read last come first.
-__device__ __forceinline__ int64_t rev_linear(int64_t L, int64_t G) {
-  const int64_t Q = G >> 3;
+// Launch position of a second-pass workgroup of a one-dimensional grid: the launch order
+// reversed in rounds of 8.  Workgroups go to the 8 XCDs round-robin by linear id, so each tile
+// keeps the XCD (and the L2) of its first pass while the tiles that pass read last come first.
+__device__ __forceinline__ unsigned rev_linear(unsigned L, unsigned G) {
+  const unsigned Q = G >> 3;
   if (L >= 8 * Q) return L;
   return 8 * (Q - 1 - (L >> 3)) + (L & 7);
 }
 
+template <int PH>
 __device__ __forceinline__ Geo geometry(const KArgs& A) {
   Geo g;
-  int64_t bx = blockIdx.x, by = blockIdx.y;
-  if (A.rev) {
-    const int64_t L = rev_linear(bx + by * gridDim.x, (int64_t)gridDim.x * gridDim.y);
-    bx = L % gridDim.x;
-    by = L / gridDim.x;
+  unsigned bx = blockIdx.x;
+  const unsigned by = blockIdx.y;
+  // second passes only (PH_SUBST, PH_FUSE); the host sets rev for one-dimensional grids
+  if constexpr (PH >= 2) {
+    if (A.rev) bx = rev_linear(bx, gridDim.x);
   }
   if (A.wg_sys) {
     g.sys = A.wg_sys[bx];
@@ -227,26 +236,26 @@ __device__ __forceinline__ double cn_kappa(double dt, double dx) {
 template <int M, bool IN>
 __device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx, int64_t J,
                                         const cd (&vp)[M + 2], const double (&vv)[M + 2],
-                                        const double (&xv)[M + 2], cd (&Ar)[M], cd (&Br)[M],
-                                        cd (&Cr)[M], cd (&Dr)[M], cd& bK) {
+                                        const double (&xv)[M + 2], double Em, double Er,
+                                        bool given, cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M],
+                                        cd (&Dr)[M], cd& bK) {
   const int64_t n = G.n;
   const double tau = 0.5 * A.dt;
   const double idx2 = 1.0 / (dx * dx);
   const double kap = cn_kappa(A.dt, dx);
-  const bool given = A.rhs != nullptr;
   const cd zero = czero();
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const int64_t r = J + j;
     const bool ok = row_in<IN>(r, n);
-    const double vm = fma(xv[j + 1], A.E_mat, A.vscale * vv[j + 1]);
+    const double vm = fma(xv[j + 1], Em, A.vscale * vv[j + 1]);
     Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
     Br[j] = mk(0.0, (ok && row_pos<IN>(r)) ? -kap : 0.0);
     Cr[j] = mk(0.0, (ok && row_notlast<IN>(r, n)) ? -kap : 0.0);
     if (given) {
       Dr[j] = vp[j + 1];
     } else {
-      const double w = tau * (idx2 + fma(xv[j + 1], A.E_rhs, A.vscale * vv[j + 1]));
+      const double w = tau * (idx2 + fma(xv[j + 1], Er, A.vscale * vv[j + 1]));
       const cd p = vp[j + 1];
       const cd s = cadd(vp[j], vp[j + 2]);
       Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
@@ -283,7 +292,8 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
 #pragma unroll
     for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
   }
-  cn_rows<M, IN>(A, G, A.dxs ? A.dxs[G.sys] : A.dx, J, vp, vv, xv, Ar, Br, Cr, Dr, bK);
+  cn_rows<M, IN>(A, G, A.dxs ? A.dxs[G.sys] : A.dx, J, vp, vv, xv, A.E_mat, A.E_rhs,
+                 A.rhs != nullptr, Ar, Br, Cr, Dr, bK);
   first_state = vp[1];
   last_state = vp[M];
 }
@@ -351,6 +361,11 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
       Br[j] = csel(hasp, db, zero);
       Cr[j] = csel(ok && r < n - 1, uc, zero);
       Dr[j] = csel(ok, cadd(ud, csel(hasp, dd, zero)), zero);
+      if (A.ud_halo) {
+        const cd h = A.ud_halo[2 * gp + 1];
+        const double kap = cn_kappa(A.dt, A.dxs ? A.dxs[G.sys] : A.dx);
+        Dr[j] = cadd(Dr[j], csel(hasp, mk(-kap * h.y, kap * h.x), zero));
+      }
     }
     const int64_t K = J + M;
     const int64_t gk = G.base + (K < n ? K - 1 : 0);
@@ -390,6 +405,7 @@ struct TileSmem {
   Blk xblk[(W > 1 && !kInStage) ? 64 : 1];
   Node xnode[64];
   double wsum[W];
+  cd wedge[W];  // PH_FUSE: last new-state row of every wavefront
   __device__ __forceinline__ Blk* part(int w, int k) {
     if constexpr (kInStage)
       return reinterpret_cast<Blk*>(reinterpret_cast<char*>(lds[w]) + kOff) + k;
@@ -502,13 +518,14 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
   cd* buf = sm.lds[wave];
 
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
+  constexpr int PL = (PH == PH_FUSE) ? PH_SUBST : PH;  // the rows are those of a PH_SUBST pass
   // wavefront-uniform choice between the interior path and the general one
   if (SRC != SRC_SLOTS && w0 >= 1 && G.n >= w0 + 64 * M + 1) {
-    load_rows<M, W, SRC, PH, true>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+    load_rows<M, W, SRC, PL, true>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
     tile_finish<M, W, SRC, PH, true>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
                                      lst);
   } else {
-    load_rows<M, W, SRC, PH, false>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+    load_rows<M, W, SRC, PL, false>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
     tile_finish<M, W, SRC, PH, false>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
                                       lst);
   }
@@ -527,13 +544,15 @@ struct RdSubst {
   static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M == 8;
 };
 
-template <int M, int W, int SRC, int PH, bool IN, typename SM>
+template <int M, int W, int SRC, int PH, bool IN, bool RDR = false, typename SM>
 __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, Node* wnode,
                                           double* keep, double kap, int64_t J, int lane, int wave,
                                           cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
-                                          cd bK, cd fst, cd lst, cd (&xo)[M]) {
+                                          cd bK, cd fst, cd lst, cd (&xo)[M],
+                                          cd* pM_out = nullptr) {
   constexpr int LW = Log2<W>::v;
-  constexpr bool RD = RdSubst<M, W, SRC, PH>::on;
+  // RDR: a Crank-Nicolson first pass reduced in the RD form as well (fewer registers)
+  constexpr bool RD = RdSubst<M, W, SRC, PH>::on || RDR;
   if constexpr (PH == PH_REDUCE && SRC == SRC_CN) {
     if (A.halo_out) {
       if (wave == 0 && lane == 0) A.halo_out[2 * G.gt] = fst;
@@ -548,8 +567,10 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
     double ay[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) ay[j] = Ar[j].y;
+    if constexpr (PH != PH_REDUCE) {
 #pragma unroll
-    for (int j = 1; j < M; ++j) keep[j * 64 + lane] = ay[j];
+      for (int j = 1; j < M; ++j) keep[j * 64 + lane] = ay[j];
+    }
     reduce_block_rd<M>(ay, edges, Dr, bK.y, blk);
   } else {
     reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
@@ -611,6 +632,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
       pM = q[1];
       tree_down<LW>(pJ, pM, wnode, lane);
     }
+    if (pM_out) *pM_out = pM;
     if constexpr (RD) {
       double ay[M];
       ay[0] = 0.0;
@@ -633,6 +655,56 @@ __device__ __forceinline__ void check_rows(const KArgs& A, const Geo& G, int64_t
   if (__any(bad) && lane == 0) atomicOr(A.status, 1);
 }
 
+// PH_FUSE, after the tile's new state is stored: the rows of the next step (field E_next) from
+// that state, reduced as in PH_REDUCE.  The stores left this wavefront's new rows in its staging
+// buffer; the rows around them come from the neighbouring wavefronts (their last row through
+// wedge) and from the joint line below the lane (pM).  Wavefront 0 has no left neighbour in the
+// tile: its joint row takes the explicit half-step without psi_{J-1}, whose term the reduced
+// system adds (KArgs::ud_halo); at the start of a system that neighbour is zero anyway.
+template <int M, int W, bool IN>
+__device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+                                          cd* buf, int64_t w0, int64_t J, int lane, int wave,
+                                          const cd (&xo)[M], cd pM) {
+  using S = Stage<M>;
+  if (lane == 63) sm.wedge[wave] = xo[M - 1];
+  __syncthreads();
+  if (lane == 0) buf[S::addr(0)] = csel(wave > 0, sm.wedge[wave > 0 ? wave - 1 : 0], czero());
+  if (lane == 63) buf[S::addr(S::QN - 1)] = pM;
+  wave_sync();
+  cd vp[M + 2];
+  stage_read<M>(buf, lane, vp);
+  if constexpr (!IN) {
+    // rows past the end of the system hold no state
+#pragma unroll
+    for (int j = 0; j < M + 2; ++j) vp[j] = csel(J - 1 + j < G.n, vp[j], czero());
+  }
+  wave_sync();
+  // V and xgrid again (the loads of the first half were not kept alive across the solve: the
+  // empty asm hides that the row addresses are the same)
+  int sl = lane;
+  asm volatile("" : "+v"(sl));
+  double rv[M], rhv, vv[M + 2], xv[M + 2];
+  double* bufd = reinterpret_cast<double*>(buf);
+  stage_fetch<M, IN>(A.V + G.base, G.es, w0, G.n, sl, 0.0, rv, rhv);
+  transpose_in<M>(bufd, sl, rv, rhv, vv);
+  if (A.xg) {
+    stage_fetch<M, IN>(A.xg + G.base, G.es, w0, G.n, sl, 0.0, rv, rhv);
+    transpose_in<M>(bufd, sl, rv, rhv, xv);
+  } else {
+#pragma unroll
+    for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
+  }
+  const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
+  cd Ar[M], Br[M], Cr[M], Dr[M], bK, dummy[M];
+  cn_rows<M, IN>(A, G, dx, J, vp, vv, xv, A.E_next, A.E_next, false, Ar, Br, Cr, Dr, bK);
+  Node* wnode = reinterpret_cast<Node*>(buf);
+  double* keep = reinterpret_cast<double*>(wnode + 64);
+  // reduced in the RD form: the diagonal and the right-hand side are all it keeps per row
+  tile_core<M, W, SRC_CN, PH_REDUCE, IN, (M >= 2)>(A, G, sm, wnode, keep, cn_kappa(A.dt, dx), J,
+                                                   lane, wave, Ar, Br, Cr, Dr, bK, vp[1], vp[M],
+                                                   dummy);
+}
+
 // Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
 template <int M, int W, int SRC, int PH, bool IN>
 __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
@@ -641,20 +713,22 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
                                             cd bK, cd fst, cd lst) {
   // the staging buffer is idle between the loads and the stores: it holds the nodes and, for
   // substitution along the RD rows, the diagonals after them
+  constexpr int PS = (PH == PH_FUSE) ? PH_SUBST : PH;  // the solve that ends in this pass
   Node* wnode = reinterpret_cast<Node*>(buf);
   double* keep = reinterpret_cast<double*>(wnode + 64);
-  static_assert(!RdSubst<M, W, SRC, PH>::on ||
+  static_assert(!RdSubst<M, W, SRC, PS>::on ||
                     sizeof(Node) * 64 + sizeof(double) * 64 * M <= sizeof(cd) * Stage<M>::QS,
                 "nodes and diagonals fit the stage buffer");
   double kap = 0.0;
-  if constexpr (RdSubst<M, W, SRC, PH>::on) {
+  if constexpr (RdSubst<M, W, SRC, PS>::on) {
     const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
     kap = cn_kappa(A.dt, dx);
   }
   cd xo[M];
-  tile_core<M, W, SRC, PH, IN>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
-                               lst, xo);
-  if constexpr (PH != PH_REDUCE) {
+  cd pM = czero();
+  tile_core<M, W, SRC, PS, IN>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
+                               lst, xo, PH == PH_FUSE ? &pM : nullptr);
+  if constexpr (PS != PH_REDUCE) {
     check_rows<M, IN>(A, G, J, lane, xo);
     if constexpr (SRC == SRC_SLOTS) {
 #pragma unroll
@@ -664,13 +738,14 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
       store_tile<M, W, SRC, IN>(A, G, sm, buf, w0, lane, wave, xo);
     }
   }
+  if constexpr (PH == PH_FUSE && SRC == SRC_CN) fuse_next<M, W, IN>(A, G, sm, buf, w0, J, lane, wave, xo, pM);
 }
 
 // One workgroup = one tile of T = 64*W*M rows of one system.
 template <int M, int W, int SRC, int PH>
 __global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
   __shared__ TileSmem<M, W> sm;
-  const Geo G = geometry(A);
+  const Geo G = geometry<PH>(A);
   tile_run<M, W, SRC, PH>(A, G, sm);
 }
 
@@ -719,7 +794,10 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   // consecutive workgroups take neighbouring column groups of the same rows, so the rows that
   // run concurrently are read as long contiguous runs
   const int64_t ncg = (A.batch + 63) / 64;
-  const int64_t bid = A.rev ? rev_linear(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  int64_t bid = blockIdx.x;
+  if constexpr (PH == PH_SUBST) {
+    if (A.rev) bid = rev_linear(blockIdx.x, gridDim.x);
+  }
   const int64_t cg = bid % ncg;
   const int64_t sys = cg * 64 + lane;
   const bool live = sys < A.batch;

@@ -1,0 +1,154 @@
+"""GPU parity of cn_propagate over two-pass plans, whose steps run as one fused pass each (the
+second pass of step k with the first pass of step k+1; the reduced system adds the joint rows'
+deferred neighbour terms), against the CPU oracle stepping one step at a time.
+
+Tolerance: relative L2 <= 1e-11 (FP64 on both sides; rounding only).  Cases: one long system
+with a field and checkpoints (row tiles of 4 and 8 rows per lane, second passes alternating
+direction above 2^21 rows), a uniform batch with a dx per system, an uneven batch mixing
+whole-system tiles and two-pass systems, a reduced system that is itself two-pass, 1 and 2
+steps, and a captured graph replayed against the eager result.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_00856_amd as cn
+
+    cn.handle(0)
+    return torch, cn
+
+
+def rel(x, y):
+    x = np.asarray(x)
+    y = np.asarray(y)
+    return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
+
+
+def to_dev(torch, *arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("n", [200_003, 1_048_579, 2_100_003])
+def test_propagate_long_system_field_checkpoints(gpu, oracle_mod, n):
+    torch, cn = gpu
+    log("fused propagate", n)
+    dx, dt, steps, K = 0.05, 0.01, 7, 3
+    inp = workloads.random_cn(n, 71 + n % 97, dx, dt)
+    xg = workloads.grid_1d(n, dx)
+    E = np.random.default_rng(n % 1000).normal(0.0, 0.05, steps)
+    tV, tpsi, txg = to_dev(torch, inp["V"], inp["psi"], xg)
+    L = cn.Layout.contiguous(n, 1)
+    ckpt = torch.empty(((steps + K - 1) // K) * n, dtype=torch.complex128, device="cuda")
+    cn.propagate(tpsi, tV, dx, dt, steps, E=E, xgrid=txg, ckpt=ckpt, K=K, layout=L)
+    ref = inp["psi"]
+    states = [ref]
+    for k in range(steps):
+        ref = oracle_mod.cn_step(ref, inp["V"], dx, dt, xg, E[k])
+        states.append(ref)
+    assert rel(tpsi.cpu().numpy(), states[steps]) <= TOL
+    ck = ckpt.cpu().numpy().reshape(-1, n)
+    for j in range(ck.shape[0]):
+        assert rel(ck[j], states[j * K]) <= TOL
+    assert cn.get_status() == 0
+
+
+def test_propagate_uniform_batch_dx_per_system(gpu, oracle_mod):
+    torch, cn = gpu
+    n, batch, dt, steps = 70_001, 3, 0.02, 5
+    g = np.random.default_rng(12)
+    V = g.uniform(-2.0, 0.0, n * batch)
+    psi = workloads.complex_normal(g, n * batch)
+    dxs = np.array([0.05, 0.1, 0.17])
+    tV, tpsi, tdx = to_dev(torch, V, psi, dxs)
+    cn.propagate(tpsi, tV, 1.0, dt, steps, dx_per_system=tdx, layout=cn.Layout.contiguous(n, batch))
+    out = tpsi.cpu().numpy()
+    for s in range(batch):
+        ref = oracle_mod.cn_propagate(psi[s * n:(s + 1) * n], V[s * n:(s + 1) * n], dxs[s], dt,
+                                      steps)
+        assert rel(out[s * n:(s + 1) * n], ref) <= TOL
+
+
+def test_propagate_uneven_mixed(gpu, oracle_mod):
+    torch, cn = gpu
+    lengths = np.array([1, 5, 300, 4096, 4097, 9000, 20_000, 65_543, 2, 100_000, 2048, 33_333])
+    offs = np.zeros(lengths.size + 1, np.int64)
+    np.cumsum(lengths, out=offs[1:])
+    g = np.random.default_rng(13)
+    V = g.uniform(-2.0, 0.0, offs[-1])
+    psi = workloads.complex_normal(g, offs[-1])
+    dxs = g.uniform(0.05, 0.2, lengths.size)
+    dt, steps = 0.02, 4
+    tV, tpsi, tdx = to_dev(torch, V, psi, dxs)
+    L = cn.Layout.uneven(offs)
+    log("uneven fused plan:", cn.describe_plan(L, True))
+    cn.propagate(tpsi, tV, 1.0, dt, steps, dx_per_system=tdx, layout=L)
+    ref = psi
+    for _ in range(steps):
+        ref = oracle_mod.cn_step_batched(offs, ref, V, dxs, dt)
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+
+
+def test_propagate_two_pass_reduced_system(gpu, oracle_mod):
+    """2^24 + 5 rows: 8193 first-level tiles, whose reduced system is solved in two passes
+    as well (the deferred terms enter both of its passes)."""
+    torch, cn = gpu
+    n, dx, dt, steps = (1 << 24) + 5, 0.1, 0.02, 3
+    inp = workloads.random_cn(n, 5, dx, dt)
+    tV, tpsi = to_dev(torch, inp["V"], inp["psi"])
+    L = cn.Layout.contiguous(n, 1)
+    log("two-level plan:", cn.describe_plan(L, True))
+    cn.propagate(tpsi, tV, dx, dt, steps, layout=L)
+    ref = oracle_mod.cn_propagate(inp["psi"], inp["V"], dx, dt, steps)
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("steps", [1, 2])
+def test_propagate_few_steps(gpu, oracle_mod, steps):
+    torch, cn = gpu
+    n, dx, dt = 100_003, 0.1, 0.02
+    inp = workloads.random_cn(n, 17, dx, dt)
+    tV, tpsi = to_dev(torch, inp["V"], inp["psi"])
+    cn.propagate(tpsi, tV, dx, dt, steps)
+    ref = oracle_mod.cn_propagate(inp["psi"], inp["V"], dx, dt, steps)
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+
+
+def test_propagate_fused_graph_replays(gpu):
+    """The fused sequence captured as a graph, replayed with eager work between the replays,
+    gives the eager result bit for bit."""
+    torch, cn = gpu
+    n, dx, dt, steps = 300_001, 0.1, 0.02, 6
+    inp = workloads.random_cn(n, 23, dx, dt)
+    tV, p0 = to_dev(torch, inp["V"], inp["psi"])
+    L = cn.Layout.contiguous(n, 1)
+    cn.reserve(L)
+    eager = p0.clone()
+    cn.propagate(eager, tV, dx, dt, steps, layout=L)
+    psi = p0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        cn.propagate(psi, tV, dx, dt, steps, layout=L)
+    for _ in range(3):
+        psi.copy_(p0)
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = p0.clone()
+        cn.propagate(junk, tV, dx, dt, 2, layout=L)
+        torch.cuda.synchronize()
+        assert torch.equal(psi, eager)
