@@ -9,12 +9,14 @@ one captured hipGraph.  value = solved complex unknowns per second (2 x 4096^2 p
 
 Also reported (extra): the 2^28-unknown explicit solve with its partition sweep, the plain 1D
 workload (N = 65536, one solve + 200 steps), the uneven batch (10^4 systems, 50 steps) and the
-differentiated propagation (2^20 x 2000 steps), each with the oracle timed beside it.
+differentiated propagation (2^20 x 2000 steps) and a 2^24-row propagation with a field (20
+steps, one fused pass per step), each with the oracle timed beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--cpu-seconds S]
-                       [--copy-ref] [--only-large]
+                       [--copy-ref] [--only-large] [--only-propagate]
   --cpu-seconds 0 skips the oracle's full 100-step run of the headline grid (about 15 s on 16
-  threads; the baseline and parity then use one step); --only-large times only the 2^28 solve.
+  threads; the baseline and parity then use one step); --only-large times only the 2^28 solve,
+  --only-propagate only the 2^24-row fused propagation.
 """
 from __future__ import annotations
 
@@ -48,6 +50,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--only-large", action="store_true",
                    help="time only the 2^28 explicit solve (automatic plan), for profiling")
+    p.add_argument("--only-propagate", action="store_true",
+                   help="time only the 2^24-row fused propagation, for profiling")
     p.add_argument("--copy-ref", action="store_true",
                    help="first run a plain 256 MiB device copy three times (a reference of known "
                         "size for scaling hardware byte counters)")
@@ -133,6 +137,9 @@ def main():
 
     if args.only_large:
         print(json.dumps(large_system(torch, np, cn, dev, sweep=False)), flush=True)
+        return
+    if args.only_propagate:
+        print(json.dumps(long_propagate(torch, np, cn, dev, parity=False)), flush=True)
         return
 
     # ---------------------------------------------------------------- headline: ADI 4096^2
@@ -324,6 +331,46 @@ def large_system(torch, np, cn, dev, sweep=True):
     return out
 
 
+def long_propagate(torch, np, cn, dev, parity=True):
+    """A 2^24-row CN sequence with a field: dx = 0.05, dt = 0.01, soft-core V on the grid,
+    x E_k with E ~ N(0, 0.05^2), seeded complex-normal psi; cn_propagate of 20 steps, whose
+    two-pass plan runs one fused pass per step (48 B per unknown and step: read psi, V, x,
+    write psi)."""
+    import workloads
+
+    n, steps, dx, dt = 1 << 24, 20, 0.05, 0.01
+    g = np.random.default_rng(1005)
+    x = workloads.grid_1d(n, dx)
+    V = workloads.softcore(x)
+    E = g.normal(0.0, 0.05, steps)
+    psi0 = workloads.complex_normal(g, n)
+    tV, tx, p0 = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (V, x, psi0))
+    L = cn.Layout.contiguous(n, 1)
+    psi = p0.clone()
+    cn.propagate(psi, tV, dx, dt, steps, E=E, xgrid=tx, layout=L)
+    ts = timed_events(torch, lambda: cn.propagate(psi, tV, dx, dt, steps, E=E, xgrid=tx,
+                                                  layout=L), 5)
+    med = float(np.median(ts)) / steps
+    out = {"n": n, "steps": steps, "us_per_step": med * 1e3,
+           "unknowns_per_s": n / (med * 1e-3),
+           "GBps_48": 48 * n / (med * 1e-3) / 1e9,
+           "frac_of_peak_48B": 48 * n / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "plan": cn.describe_plan(L, True)}
+    if parity:
+        ns = 3
+        ps = p0.clone()
+        cn.propagate(ps, tV, dx, dt, ns, E=E[:ns], xgrid=tx, layout=L)
+        ref = {}
+        out["cpu_baseline"] = oracle_timed(
+            f"{ns} CN steps of the 2^24-row system with the field (serial FP64 Thomas, 1 thread)",
+            lambda o: (lambda: ref.setdefault("x", o.cn_propagate(psi0, V, dx, dt, ns, x,
+                                                                  E[:ns]))),
+            ns * n, out["unknowns_per_s"])
+        if "x" in ref:
+            out["parity_rel_l2_3_steps"] = rel_l2(ps.cpu().numpy(), ref["x"])
+    return out
+
+
 def _thomas_sample(np, o, n):
     g = np.random.default_rng(1002)
     V = g.uniform(-1.0, 0.0, n)
@@ -462,6 +509,12 @@ def extras(torch, np, cn, workloads, dev):
         out["differentiated"] = differentiated(torch, np, workloads, dev)
     except Exception as ex:  # noqa: BLE001
         out["differentiated"] = {"error": repr(ex)}
+    # ----------------------------------------------------------- 2^24-row fused propagation
+    try:
+        out["propagate_2^24"] = long_propagate(torch, np, cn, dev)
+        torch.cuda.empty_cache()
+    except Exception as ex:  # noqa: BLE001
+        out["propagate_2^24"] = {"error": repr(ex)}
     return out
 
 

@@ -268,7 +268,8 @@ template <int M, int W, int PH, bool XG, bool IN>
 __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
                                          int64_t J, int lane, int wave, CnRaw<M, XG>& raw,
                                          cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
-                                         cd& bK, cd& first_state, cd& last_state) {
+                                         cd& bK, cd& first_state, cd& last_state,
+                                         double* ayn) {
   if constexpr (PH == PH_SUBST) {
     // the neighbours' edge rows may already hold the new state: take the saved copies
     if (A.rhs == nullptr) {
@@ -292,10 +293,21 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
 #pragma unroll
     for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
   }
-  cn_rows<M, IN>(A, G, A.dxs ? A.dxs[G.sys] : A.dx, J, vp, vv, xv, A.E_mat, A.E_rhs,
-                 A.rhs != nullptr, Ar, Br, Cr, Dr, bK);
+  const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
+  cn_rows<M, IN>(A, G, dx, J, vp, vv, xv, A.E_mat, A.E_rhs, A.rhs != nullptr, Ar, Br, Cr, Dr,
+                 bK);
   first_state = vp[1];
   last_state = vp[M];
+  if (ayn) {
+    // PH_FUSE: the diagonal of the next step (field E_next), the same expression as cn_rows
+    const double tau = 0.5 * A.dt;
+    const double idx2 = 1.0 / (dx * dx);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const double t = tau * (idx2 + fma(xv[j + 1], A.E_next, A.vscale * vv[j + 1]));
+      ayn[j] = row_in<IN>(J + j, G.n) ? t : 0.0;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ row assembly per source
@@ -303,7 +315,8 @@ template <int M, int W, int SRC, int PH, bool IN>
 __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
                                           int64_t J, int lane, int wave, cd (&Ar)[M],
                                           cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M], cd& bK,
-                                          cd& first_state, cd& last_state) {
+                                          cd& first_state, cd& last_state,
+                                          double* ayn = nullptr) {
   const int64_t n = G.n;
   if constexpr (SRC == SRC_EXPL || SRC == SRC_EXPL_CT) {
     const cd one = mk(1.0, 0.0), zero = czero();
@@ -345,7 +358,7 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
     CnRaw<M, true> raw;
     cn_fetch<M, true, IN>(A, G, w0, lane, raw);
     cn_build<M, W, PH, true, IN>(A, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr, bK,
-                                 first_state, last_state);
+                                 first_state, last_state, ayn);
   } else {  // SRC_SLOTS: row k of the reduced system = U slot of tile k + D slot of tile k-1
     const cd zero = czero();
 #pragma unroll
@@ -498,7 +511,7 @@ template <int M, int W, int SRC, int PH, bool IN>
 __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                             cd* buf, int64_t w0, int64_t J, int lane, int wave,
                                             cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
-                                            cd bK, cd fst, cd lst);
+                                            cd bK, cd fst, cd lst, const double* ayn);
 
 // One tile of T = 64*W*M rows of one system, run by every thread of the workgroup.
 //   PH_SINGLE  the tile holds the whole system: RS on its two joint lines, then SS
@@ -519,15 +532,19 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
   constexpr int PL = (PH == PH_FUSE) ? PH_SUBST : PH;  // the rows are those of a PH_SUBST pass
+  double ayn[M];  // PH_FUSE: diagonal of the next step, from this pass's loads of V and xgrid
+  double* ayp = (PH == PH_FUSE) ? ayn : nullptr;
   // wavefront-uniform choice between the interior path and the general one
   if (SRC != SRC_SLOTS && w0 >= 1 && G.n >= w0 + 64 * M + 1) {
-    load_rows<M, W, SRC, PL, true>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+    load_rows<M, W, SRC, PL, true>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst,
+                                   ayp);
     tile_finish<M, W, SRC, PH, true>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
-                                     lst);
+                                     lst, ayp);
   } else {
-    load_rows<M, W, SRC, PL, false>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst);
+    load_rows<M, W, SRC, PL, false>(A, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst, lst,
+                                    ayp);
     tile_finish<M, W, SRC, PH, false>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
-                                      lst);
+                                      lst, ayp);
   }
 }
 
@@ -663,8 +680,9 @@ __device__ __forceinline__ void check_rows(const KArgs& A, const Geo& G, int64_t
 // system adds (KArgs::ud_halo); at the start of a system that neighbour is zero anyway.
 template <int M, int W, bool IN>
 __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
-                                          cd* buf, int64_t w0, int64_t J, int lane, int wave,
-                                          const cd (&xo)[M], cd pM) {
+                                          cd* buf, int64_t J, int lane, int wave,
+                                          const cd (&xo)[M], cd pM, const double* ayn) {
+  static_assert(M >= 2, "the next step is reduced in the RD form");
   using S = Stage<M>;
   if (lane == 63) sm.wedge[wave] = xo[M - 1];
   __syncthreads();
@@ -679,30 +697,28 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
     for (int j = 0; j < M + 2; ++j) vp[j] = csel(J - 1 + j < G.n, vp[j], czero());
   }
   wave_sync();
-  // V and xgrid again (the loads of the first half were not kept alive across the solve: the
-  // empty asm hides that the row addresses are the same)
-  int sl = lane;
-  asm volatile("" : "+v"(sl));
-  double rv[M], rhv, vv[M + 2], xv[M + 2];
-  double* bufd = reinterpret_cast<double*>(buf);
-  stage_fetch<M, IN>(A.V + G.base, G.es, w0, G.n, sl, 0.0, rv, rhv);
-  transpose_in<M>(bufd, sl, rv, rhv, vv);
-  if (A.xg) {
-    stage_fetch<M, IN>(A.xg + G.base, G.es, w0, G.n, sl, 0.0, rv, rhv);
-    transpose_in<M>(bufd, sl, rv, rhv, xv);
-  } else {
-#pragma unroll
-    for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
-  }
+  // the rows of the next step: its diagonal came with the first half's loads (ayn), the
+  // right-hand side is the explicit half-step of cn_rows with the same diagonal
   const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
-  cd Ar[M], Br[M], Cr[M], Dr[M], bK, dummy[M];
-  cn_rows<M, IN>(A, G, dx, J, vp, vv, xv, A.E_next, A.E_next, false, Ar, Br, Cr, Dr, bK);
+  const double kap = cn_kappa(A.dt, dx);
+  const cd zero = czero();
+  cd Ar[M], Br[M], Cr[M], Dr[M], dummy[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double w = ayn[j];
+    const cd p = vp[j + 1];
+    const cd s2 = cadd(vp[j], vp[j + 2]);
+    Ar[j] = mk(1.0, w);
+    Br[j] = Cr[j] = zero;  // the RD form takes the couplings from kap
+    Dr[j] = csel(row_in<IN>(J + j, G.n),
+                 mk(fma(w, p.y, fma(-kap, s2.y, p.x)), fma(-w, p.x, fma(kap, s2.x, p.y))), zero);
+  }
+  const cd bK = mk(0.0, row_in<IN>(J + M, G.n) ? -kap : 0.0);
   Node* wnode = reinterpret_cast<Node*>(buf);
   double* keep = reinterpret_cast<double*>(wnode + 64);
   // reduced in the RD form: the diagonal and the right-hand side are all it keeps per row
-  tile_core<M, W, SRC_CN, PH_REDUCE, IN, (M >= 2)>(A, G, sm, wnode, keep, cn_kappa(A.dt, dx), J,
-                                                   lane, wave, Ar, Br, Cr, Dr, bK, vp[1], vp[M],
-                                                   dummy);
+  tile_core<M, W, SRC_CN, PH_REDUCE, IN, (M >= 2)>(A, G, sm, wnode, keep, kap, J, lane, wave,
+                                                   Ar, Br, Cr, Dr, bK, vp[1], vp[M], dummy);
 }
 
 // Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
@@ -710,7 +726,7 @@ template <int M, int W, int SRC, int PH, bool IN>
 __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                             cd* buf, int64_t w0, int64_t J, int lane, int wave,
                                             cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
-                                            cd bK, cd fst, cd lst) {
+                                            cd bK, cd fst, cd lst, const double* ayn) {
   // the staging buffer is idle between the loads and the stores: it holds the nodes and, for
   // substitution along the RD rows, the diagonals after them
   constexpr int PS = (PH == PH_FUSE) ? PH_SUBST : PH;  // the solve that ends in this pass
@@ -738,12 +754,21 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
       store_tile<M, W, SRC, IN>(A, G, sm, buf, w0, lane, wave, xo);
     }
   }
-  if constexpr (PH == PH_FUSE && SRC == SRC_CN) fuse_next<M, W, IN>(A, G, sm, buf, w0, J, lane, wave, xo, pM);
+  if constexpr (PH == PH_FUSE && SRC == SRC_CN)
+    fuse_next<M, W, IN>(A, G, sm, buf, J, lane, wave, xo, pM, ayn);
+}
+
+// Waves per SIMD that the register allocation of a tile kernel must allow: the fused pass of
+// 8 rows per lane carries the next step's diagonal through its first half and sits one
+// register above the budget of 3 wavefronts; the others keep the compiler's choice.
+template <int M, int PH>
+constexpr int tile_min_waves() {
+  return (PH == PH_FUSE && M == 8) ? 3 : 1;
 }
 
 // One workgroup = one tile of T = 64*W*M rows of one system.
 template <int M, int W, int SRC, int PH>
-__global__ __launch_bounds__(64 * W) void k_tile(KArgs A) {
+__global__ __launch_bounds__(64 * W, (tile_min_waves<M, PH>())) void k_tile(KArgs A) {
   __shared__ TileSmem<M, W> sm;
   const Geo G = geometry<PH>(A);
   tile_run<M, W, SRC, PH>(A, G, sm);
