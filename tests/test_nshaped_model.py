@@ -107,3 +107,52 @@ def test_rd_form_slots_equal_table1_stages(oracle_mod, m, kind):
     psi = nm.rd_form_substitute(a, b, c, delta, psiJK[0], psiJK[1])
     ref = oracle_mod.thomas(a, b, c, d)
     assert rel(psi, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n,p", [(37, 8), (200, 13), (1000, 64)])
+def test_deferred_joint_row_term(oracle_mod, n, p):
+    """Cross-step fusion defers, in every tile's joint row J, the explicit half-step's term
+    i kap psi_{J-1} (the left neighbour lies in another tile) to the reduced system.  Pins that
+    deferral: RD, RU, JD and JU never touch d at a joint row, so the reduced matrix is unchanged
+    and the reduced right-hand side differs by exactly i kap psi_{J-1} at every joint line
+    w >= 1; adding it back there and substituting gives the oracle's CN step."""
+    dx, dt = 0.1, 0.02
+    inp = workloads.random_cn(n, 300 + n, dx, dt)
+    psi, V = inp["psi"], inp["V"]
+    a, b, c = oracle_mod.cn_coeffs(V, dx, dt)
+    d = oracle_mod.cn_rhs(psi, V, dx, dt)
+    kap = dt / (4.0 * dx * dx)  # the off-diagonal magnitude, |b| = |c| = kap
+    assert np.allclose(np.abs(b[1:]), kap, rtol=1e-14, atol=0)
+    J = nm.uniform_joints(n, p)
+    deferred = np.zeros(len(J), np.complex128)
+    dp = d.copy()
+    for w in range(1, len(J)):
+        deferred[w] = 1j * kap * psi[J[w] - 1]
+        dp[J[w]] -= deferred[w]
+
+    def stages(dd):
+        aa, bb, cc = np.array(a), np.array(b), np.array(c)
+        bb[0] = 0.0
+        cc[-1] = 0.0
+        ddd = np.array(dd)
+        out = nm._stages_one_level(aa, bb, cc, ddd, J)
+        return out, (aa, bb, cc, ddd)
+
+    (ra, rb, rc, rd_full, _), _ = stages(d)
+    (ra2, rb2, rc2, rd_part, _), (aa, bb, cc, ddd) = stages(dp)
+    assert np.array_equal(ra, ra2) and np.array_equal(rb, rb2) and np.array_equal(rc, rc2)
+    scale = np.max(np.abs(rd_full))
+    assert np.max(np.abs(rd_full - (rd_part + deferred))) <= 1e-14 * scale
+    # the fused reading end to end: reduced system with the deferred terms, then SS on the
+    # interior rows that the partial right-hand side produced
+    support = nm._rs(ra2, rb2, rc2, rd_part + deferred, [])
+    x = np.empty(n, np.complex128)
+    x[np.asarray(J)] = support
+    nm._ss(aa, bb, cc, ddd, J, support, x)
+    assert rel(x, oracle_mod.cn_step(psi, V, dx, dt)) <= 1e-12
+    # a deferred term with the wrong neighbour does not pass
+    wrong = deferred.copy()
+    for w in range(1, len(J)):
+        wrong[w] = 1j * kap * psi[J[w] - 2]
+    bad = nm._rs(ra2, rb2, rc2, rd_part + wrong, [])
+    assert rel(bad, support) > 1e-6
