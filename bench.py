@@ -9,8 +9,9 @@ one captured hipGraph.  value = solved complex unknowns per second (2 x 4096^2 p
 
 Also reported (extra): the 2^28-unknown explicit solve with its partition sweep, the plain 1D
 workload (N = 65536, one solve + 200 steps), the uneven batch (10^4 systems, 50 steps) and the
-differentiated propagation (2^20 x 2000 steps) and a 2^24-row propagation with a field (20
-steps, one fused pass per step), each with the oracle timed beside it.
+differentiated propagation (2^20 x 2000 steps), a 2^24-row propagation with a field (20
+steps, one fused pass per step) and one 2^22-row matrix with 16 right-hand sides, each with the
+oracle timed beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--cpu-seconds S]
                        [--copy-ref] [--only-large] [--only-propagate]
@@ -371,6 +372,58 @@ def long_propagate(torch, np, cn, dev, parity=True):
     return out
 
 
+def multi_rhs(torch, np, cn, dev):
+    """One 2^22-row matrix (the 2^28 solve's distribution) with 16 right-hand sides: the batch
+    reads the matrix of system 0 (shared_coefficients), against the same batch with the matrix
+    copied for every right-hand side.  Algorithmic bytes of the shared solve: each right-hand
+    side's d and x (32 B per unknown) plus the matrix once (48 B per row)."""
+    n, k = 1 << 22, 16
+    g = torch.Generator(device=dev)
+    g.manual_seed(1006)
+    V = torch.rand(n, dtype=torch.float64, device=dev, generator=g) - 1.0
+    a, b, c = cn.assemble(V, 0.01, 0.02)
+    d = torch.empty(k * n, dtype=torch.complex128, device=dev)
+    d.real.normal_(generator=g)
+    d.imag.normal_(generator=g)
+    x = torch.empty_like(d)
+    Ls = cn.Layout.contiguous(n, k, shared_coefficients=True)
+    cn.solve(a, b, c, d, out=x, layout=Ls)
+    ts = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=Ls), 10)
+    med = float(np.median(ts))
+    xs = x.clone()
+    A, B, C = (t.repeat(k) for t in (a, b, c))
+    Lr = cn.Layout.contiguous(n, k)
+    cn.solve(A, B, C, d, out=x, layout=Lr)
+    tr = timed_events(torch, lambda: cn.solve(A, B, C, d, out=x, layout=Lr), 10)
+    medr = float(np.median(tr))
+    same = rel_l2(xs.cpu().numpy(), x.cpu().numpy())
+    del A, B, C
+    algo = (32 * k + 48) * n
+    out = {"n": n, "rhs": k, "ms_shared": med, "ms_replicated": medr,
+           "unknowns_per_s": k * n / (med * 1e-3),
+           "GBps_algorithmic": algo / (med * 1e-3) / 1e9,
+           "frac_of_peak": algo / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "shared_vs_replicated_rel_l2": same,
+           "plan": cn.describe_plan(Ls)}
+    ref = {}
+    a0, b0, c0 = (t.cpu().numpy() for t in (a, b, c))
+    dd = d.cpu().numpy()
+    def both(o):
+        def run():
+            ref["x0"] = o.thomas(a0, b0, c0, dd[:n])
+            ref["xl"] = o.thomas(a0, b0, c0, dd[(k - 1) * n:])
+        return run
+
+    out["cpu_baseline"] = oracle_timed(
+        "serial FP64 Thomas on right-hand sides 0 and 15 (1 thread)", both, 2 * n,
+        out["unknowns_per_s"])
+    if "xl" in ref:
+        xh = xs.cpu().numpy()
+        out["parity_rel_l2_rhs_0"] = rel_l2(xh[:n], ref["x0"])
+        out["parity_rel_l2_rhs_last"] = rel_l2(xh[(k - 1) * n:], ref["xl"])
+    return out
+
+
 def _thomas_sample(np, o, n):
     g = np.random.default_rng(1002)
     V = g.uniform(-1.0, 0.0, n)
@@ -509,6 +562,12 @@ def extras(torch, np, cn, workloads, dev):
         out["differentiated"] = differentiated(torch, np, workloads, dev)
     except Exception as ex:  # noqa: BLE001
         out["differentiated"] = {"error": repr(ex)}
+    # ----------------------------------------------------------- one matrix, 16 right-hand sides
+    try:
+        out["multi_rhs_2^22x16"] = multi_rhs(torch, np, cn, dev)
+        torch.cuda.empty_cache()
+    except Exception as ex:  # noqa: BLE001
+        out["multi_rhs_2^22x16"] = {"error": repr(ex)}
     # ----------------------------------------------------------- 2^24-row fused propagation
     try:
         out["propagate_2^24"] = long_propagate(torch, np, cn, dev)

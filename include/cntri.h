@@ -73,6 +73,14 @@ typedef struct {
                               and two passes over 2048-row tiles for longer ones; > 0 = one
                               persistent launch over all systems with that tile            */
   int32_t rows_per_thread; /* rows per innermost block (2, 4, 8 or 16); 0 = automatic      */
+  int32_t shared_coefficients; /* uniform batches only: 1 = every system reads the
+                              coefficients of system 0 (a, b, c of cn_tridiag_solve; V and
+                              xgrid of cn_step / cn_propagate), so the batch is several
+                              right-hand sides of one matrix, whose coefficients are read
+                              from one system's elements; 0 = each system its own.  Entry
+                              points that accumulate per-system gradients or materialise
+                              per-system arrays (adjoints, cn_assemble, cn_rhs) return
+                              CN_ERR_UNSUPPORTED for 1                                       */
 } cn_layout;
 
 /* Crank-Nicolson operator of Sec. 2, Eqs. (2)-(4) on a uniform grid with Dirichlet walls:
@@ -93,7 +101,8 @@ typedef struct {
 /* Host-only check of a layout (no device access): CN_OK, or the negative status that every
  * entry point would return for it (null layout, batch < 1, n < 1, strides < 1, systems that
  * share elements, offsets not starting at 0 or decreasing, a partition that is not a power of two
- * in [32, 16384], rows_per_thread not in {0, 2, 4, 8, 16}). */
+ * in [32, 16384], rows_per_thread not in {0, 2, 4, 8, 16}, shared_coefficients not 0 or 1;
+ * CN_ERR_UNSUPPORTED for shared coefficients in an uneven batch). */
 cn_status cn_check_layout(const cn_layout* layout);
 
 cn_status cn_create(cn_handle_t* handle, int device);

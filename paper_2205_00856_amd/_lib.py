@@ -29,6 +29,7 @@ class CnLayout(ctypes.Structure):
         ("offsets", ctypes.POINTER(ctypes.c_int64)),
         ("partition", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32),
+        ("shared_coefficients", ctypes.c_int32),
     ]
 
 

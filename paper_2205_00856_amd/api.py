@@ -38,6 +38,7 @@ class Layout:
     offsets: Optional[Sequence[int]] = None
     partition: int = 0
     rows_per_thread: int = 0
+    shared_coefficients: bool = False  # uniform batch: all systems use system 0's a, b, c / V, x
     _offs_np: Optional[np.ndarray] = field(default=None, repr=False)
 
     @staticmethod
@@ -81,7 +82,14 @@ class Layout:
             L.offsets = None
         L.partition = int(self.partition)
         L.rows_per_thread = int(self.rows_per_thread)
+        L.shared_coefficients = 1 if self.shared_coefficients else 0
         return L
+
+    def coef_span(self) -> int:
+        """Elements the coefficient arrays (a, b, c / V, xgrid) must hold."""
+        if self.shared_coefficients and self.offsets is None:
+            return (self.n - 1) * self.elem_stride + 1
+        return self.span()
 
 
 class Handle:
@@ -155,7 +163,7 @@ def _operator(V, dx, dt, xgrid=None, v_scale=1.0, dx_per_system=None) -> CnOpera
 
 
 def _check_op(L: Layout, V, xgrid, dx_per_system):
-    span = L.span()
+    span = L.coef_span()
     _need(V, torch.float64, "V", span)
     if xgrid is not None:
         _need(xgrid, torch.float64, "xgrid", span)
@@ -182,8 +190,9 @@ def solve(a, b, c, d, out=None, layout: Optional[Layout] = None):
     """x = T^{-1} d (cn_tridiag_solve).  out may be d (in place)."""
     L = _layout_for(d, layout)
     span = L.span()
-    for t, nm in ((a, "a"), (b, "b"), (c, "c"), (d, "d")):
-        _need(t, torch.complex128, nm, span)
+    for t, nm in ((a, "a"), (b, "b"), (c, "c")):
+        _need(t, torch.complex128, nm, L.coef_span())
+    _need(d, torch.complex128, "d", span)
     if out is None:
         out = torch.empty_like(d)
     _need(out, torch.complex128, "out", span)

@@ -223,6 +223,7 @@ struct Plan {
 struct Knobs {
   int64_t partition = 0;
   int rpt = 0;
+  int shared = 0;  // level-1 systems share system 0's coefficients
 };
 
 struct Builder {
@@ -307,6 +308,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
                 int64_t o_sU, int64_t o_sD, int64_t o_x, const Knobs& kn) {
   KArgs base{};
   base.vscale = 1.0;
+  base.cshared = (level == 1) ? kn.shared : 0;
   auto set_common = [&](Launch& l) {
     l.o_sU = o_sU;
     l.o_sD = o_sD;
@@ -315,7 +317,8 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   char line[256];
   if (!bd.uneven) {
     const int64_t n = bd.n, batch = bd.batch;
-    if (bd.bs == 1 && batch >= 64 && bd.es >= batch && src != nsd::SRC_SLOTS && cols_enabled()) {
+    if (bd.bs == 1 && batch >= 64 && bd.es >= batch && src != nsd::SRC_SLOTS && cols_enabled() &&
+        !kn.shared) {
       int cc = -1;
       if (level == 1 && kn.partition > 0) cc = col_cfg(kn.partition, kn.rpt);
       if (cc < 0) cc = col_cfg(64, 16);
@@ -629,6 +632,8 @@ cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
   if (L->rows_per_thread != 0 && L->rows_per_thread != 2 && L->rows_per_thread != 4 &&
       L->rows_per_thread != 8 && L->rows_per_thread != 16)
     return CN_ERR_INVALID_ARG;
+  if (L->shared_coefficients != 0 && L->shared_coefficients != 1) return CN_ERR_INVALID_ARG;
+  if (L->offsets && L->shared_coefficients) return CN_ERR_UNSUPPORTED;
   if (L->offsets) {
     if (L->offsets[0] != 0) return CN_ERR_INVALID_ARG;
     for (int64_t s = 0; s < L->batch; ++s)
@@ -652,9 +657,9 @@ cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
 std::string plan_key(const cn_layout* L, int src) {
   std::string k;
   char buf[160];
-  snprintf(buf, sizeof(buf), "%d|%lld|%lld|%lld|%lld|%d|%d|", src, (long long)L->n,
+  snprintf(buf, sizeof(buf), "%d|%lld|%lld|%lld|%lld|%d|%d|%d|", src, (long long)L->n,
            (long long)L->batch, (long long)L->elem_stride, (long long)L->batch_stride,
-           L->partition, L->rows_per_thread);
+           L->partition, L->rows_per_thread, L->shared_coefficients);
   k = buf;
   if (L->offsets) {
     k += "U";
@@ -692,9 +697,11 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
     Knobs kn;
     kn.partition = L->partition;
     kn.rpt = L->rows_per_thread;
+    kn.shared = L->shared_coefficients;
     if (kn.partition > 0) {
       const bool columns = !L->offsets && L->batch_stride == 1 && L->batch >= 64 &&
-                           L->elem_stride >= L->batch && cols_enabled();
+                           L->elem_stride >= L->batch && cols_enabled() &&
+                           !L->shared_coefficients;
       const int M = kn.rpt > 0 ? kn.rpt : (kn.partition >= 512 ? 8 : 4);
       const bool rows_ok = find_cfg(kn.partition, M) >= 0 || find_cfg(kn.partition, 4) >= 0 ||
                            find_cfg(kn.partition, 8) >= 0 || find_cfg(kn.partition, 2) >= 0;
@@ -1071,6 +1078,7 @@ cn_status cn_tridiag_solve_adjoint(cn_handle_t h, const cn_layout* L, const void
                                    const void* b, const void* c, const void* x, const void* gx,
                                    void* gd, void* ga, void* gb, void* gc, cn_stream_t stream) {
   if (!h || !a || !b || !c || !x || !gx || !gd) return CN_ERR_INVALID_ARG;
+  if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
   if (gd == x || gd == a || gd == b || gd == c) return CN_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   Plan* P = nullptr;
@@ -1100,6 +1108,7 @@ cn_status cn_tridiag_solve_adjoint(cn_handle_t h, const cn_layout* L, const void
 cn_status cn_assemble(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E, void* a,
                       void* b, void* c, cn_stream_t stream) {
   if (!h || !a || !b || !c) return CN_ERR_INVALID_ARG;
+  if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -1124,6 +1133,7 @@ cn_status cn_assemble(cn_handle_t h, const cn_layout* L, const cn_operator* op, 
 cn_status cn_rhs(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E,
                  const void* psi, void* d, cn_stream_t stream) {
   if (!h || !psi || !d || psi == d) return CN_ERR_INVALID_ARG;
+  if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -1206,6 +1216,7 @@ cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* 
                           const void* psi_n, const void* psi_np1, const void* g_np1, void* g_n,
                           double* dV_accum, double* dE_partial, cn_stream_t stream) {
   if (!h || !psi_n || !psi_np1 || !g_np1 || !g_n) return CN_ERR_INVALID_ARG;
+  if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
   if (dE_partial && !op->xgrid) return CN_ERR_INVALID_ARG;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
@@ -1351,6 +1362,7 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
                                void* seg, void* g, double* dV_accum, double* dE,
                                cn_stream_t stream) {
   if (!h || !L || !ckpt || !seg || !g || nsteps < 1 || K < 1) return CN_ERR_INVALID_ARG;
+  if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
   if (L->offsets) return CN_ERR_UNSUPPORTED;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;

@@ -69,12 +69,15 @@ struct KArgs {
   double* acc_part;
   double acc_tau;
   int64_t batch;          // uniform batch size (column kernel)
+  int cshared;            // uniform batch: every system reads the coefficients (a, b, c or V,
+                          // xgrid) of system 0 (several right-hand sides of one matrix)
   int rev;                // workgroups take their tiles in reverse launch order, by rounds of 8
                           // (second pass: the tiles the first pass read last are still cached)
 };
 
 struct Geo {
   int64_t sys, tile, n, base, es, gt, ntile;
+  int64_t cbase;  // first element of the system's coefficients (0 when they are shared)
 };
 
 // Launch position of a second-pass workgroup of a one-dimensional grid: the launch order
@@ -126,6 +129,7 @@ __device__ __forceinline__ Geo geometry(const KArgs& A) {
     g.gt = g.sys * A.ntiles + g.tile;
     g.ntile = A.ntiles;
   }
+  g.cbase = A.cshared ? 0 : g.base;
   return g;
 }
 
@@ -218,9 +222,9 @@ __device__ __forceinline__ void cn_fetch(const KArgs& A, const Geo& G, int64_t w
                                          CnRaw<M, XG>& r) {
   const cd* src = (A.rhs ? A.rhs : A.psi) + G.base;
   stage_fetch<M, IN>(src, G.es, w0, G.n, lane, czero(), r.p, r.hp);
-  stage_fetch<M, IN>(A.V + G.base, G.es, w0, G.n, lane, 0.0, r.v, r.hv);
+  stage_fetch<M, IN>(A.V + G.cbase, G.es, w0, G.n, lane, 0.0, r.v, r.hv);
   if constexpr (XG) {
-    if (A.xg) stage_fetch<M, IN>(A.xg + G.base, G.es, w0, G.n, lane, 0.0, r.x, r.hx);
+    if (A.xg) stage_fetch<M, IN>(A.xg + G.cbase, G.es, w0, G.n, lane, 0.0, r.x, r.hx);
   }
 }
 
@@ -321,9 +325,9 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
   if constexpr (SRC == SRC_EXPL || SRC == SRC_EXPL_CT) {
     const cd one = mk(1.0, 0.0), zero = czero();
     cd ra[M], rb[M], rc[M], rd[M], ha, hb, hc, hd;
-    stage_fetch<M, IN>(A.a + G.base, G.es, w0, n, lane, one, ra, ha);
-    stage_fetch<M, IN>(A.b + G.base, G.es, w0, n, lane, zero, rb, hb);
-    stage_fetch<M, IN>(A.c + G.base, G.es, w0, n, lane, zero, rc, hc);
+    stage_fetch<M, IN>(A.a + G.cbase, G.es, w0, n, lane, one, ra, ha);
+    stage_fetch<M, IN>(A.b + G.cbase, G.es, w0, n, lane, zero, rb, hb);
+    stage_fetch<M, IN>(A.c + G.cbase, G.es, w0, n, lane, zero, rc, hc);
     stage_fetch<M, IN>(A.d + G.base, G.es, w0, n, lane, zero, rd, hd);
     cd va[M + 2], vb[M + 2], vc[M + 2], vd[M + 2];
     transpose_in<M>(buf, lane, ra, ha, va);
@@ -836,6 +840,7 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
   G.n = A.n;
   G.es = A.es;
   G.base = G.sys * A.bs;
+  G.cbase = G.base;
   G.tile = bid / ncg;
   G.ntile = A.ntiles;
   G.gt = G.sys * A.ntiles + G.tile;
@@ -1077,6 +1082,7 @@ __global__ __launch_bounds__(64 * W) void k_system(KArgs A) {
     Geo G;
     G.sys = A.wg_sys[item];
     G.base = A.offs[G.sys];
+    G.cbase = G.base;
     G.n = A.offs[G.sys + 1] - G.base;
     G.es = 1;
     const int64_t K = (G.n + T - 1) / T;
