@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -767,6 +768,7 @@ struct UserArgs {
   double* acc_dV = nullptr;
   double* acc_part = nullptr;
   double acc_tau = 0.0;
+  int acc_half = 0;
 };
 
 // Kernel arguments of one launch of a plan for the caller's arrays u and workspace ws.
@@ -792,6 +794,7 @@ KArgs plan_args(cn_handle_t h, const Launch& l, const UserArgs& u, char* ws) {
     a.acc_dV = u.acc_dV;
     a.acc_part = u.acc_part;
     a.acc_tau = u.acc_tau;
+    a.acc_half = u.acc_half;
   }
   a.x = (l.o_x >= 0) ? (cd*)(ws + l.o_x) : u.x;
   if (l.o_sU >= 0) a.sU = (const cd*)(ws + l.o_sU);
@@ -867,39 +870,34 @@ bool fuse_enabled() {
   return on;
 }
 
-// Steps k0 .. k1-1 (k1 - k0 >= 2) of a Crank-Nicolson sequence over a fusable plan: the state
-// before step k is at base + (k - k0) * stride and step k writes base + (k - k0 + 1) * stride
-// (stride 0: in place).  First pass of step k0; levels above; then per step k: whole-system
-// tiles of step k, and either PH_FUSE (second pass of step k + first pass of step k+1; the
-// levels above then add the deferred joint-row terms from its edge rows) or, at the last step,
-// the second pass.  The two edge-row arrays alternate: a pass reads the state's edge rows
-// written by the pass before and writes those of its own new state.  Second passes of large
-// levels alternate their direction, so that each starts on the tiles its predecessor wrote
-// last.  In place, the state before every step k with k % K == 0 is copied to ckpt.
-cn_status run_fused(cn_handle_t h, Plan* P, const FusePlan& f, const UserArgs& u0, int64_t k0,
-                    int64_t k1, cd* base, int64_t stride, const double* E, cd* ckpt, int64_t K,
-                    hipStream_t s, void* ws_base = nullptr) {
+// A chain of nst >= 1 Crank-Nicolson steps over a plan with one fusable two-pass group.
+// args(i) gives step i's arrays, field (E_mat = E_rhs) and accumulation; before(i) runs before
+// step i writes its new state, after(i) once it has.  Launches: first pass of step 0; the
+// levels above; then per step i: whole-system tiles, and either PH_FUSE (second pass of step i
+// + first pass of step i+1; the levels above then add the deferred joint-row terms from its
+// edge rows) or, at the last step, the second pass.  The two edge-row arrays alternate: a pass
+// reads the state's edge rows written by the pass before and writes those of its own new
+// state.  Second passes of large levels alternate their direction, so that each starts on the
+// tiles its predecessor wrote last.
+using StepArgs = std::function<UserArgs(int64_t)>;
+using StepHook = std::function<cn_status(int64_t)>;
+
+cn_status run_chain(cn_handle_t h, Plan* P, const FusePlan& f, int64_t nst, const StepArgs& args,
+                    const StepHook& before, const StepHook& after, hipStream_t s,
+                    void* ws_base = nullptr) {
   char* ws = (char*)(ws_base ? ws_base : h->ws);
   const Launch& R = P->L[f.red];
   const Launch& S = P->L[f.sub];
   cd* H[2] = {(cd*)(ws + R.o_hout), (cd*)(ws + R.o_hout2)};
-  auto Ek = [&](int64_t k) { return E ? E[k] : 0.0; };
-  auto with_E = [&](int64_t k) {
-    UserArgs v = u0;
-    v.E_mat = v.E_rhs = Ek(k);
-    v.psi = base + (k - k0) * stride;
-    v.x = base + (k - k0 + 1) * stride;
-    return v;
-  };
-  auto mids = [&](const cd* hal) -> cn_status {
+  auto mids = [&](const cd* hal, const UserArgs& u) -> cn_status {
     for (int i : f.mids) {
       const Launch& l = P->L[i];
-      KArgs a = plan_args(h, l, u0, ws);
+      KArgs a = plan_args(h, l, u, ws);
       if (hal && l.level == 2) {
         a.ud_halo = hal;
-        a.dt = u0.dt;
-        a.dx = u0.dx;
-        a.dxs = u0.dxs;
+        a.dt = u.dt;
+        a.dx = u.dx;
+        a.dxs = u.dxs;
       }
       cn_status st = launch_k(l.fn, l, a, s);
       if (st != CN_OK) return st;
@@ -907,38 +905,35 @@ cn_status run_fused(cn_handle_t h, Plan* P, const FusePlan& f, const UserArgs& u
     return CN_OK;
   };
   cn_status st;
-  if (ckpt && k0 % K == 0)
-    HIP_TRY(hipMemcpyAsync(ckpt + (k0 / K) * P->span, base, P->span * sizeof(cd),
-                           hipMemcpyDeviceToDevice, s));
+  UserArgs v = args(0);
   {
-    const UserArgs v = with_E(k0);
     KArgs a = plan_args(h, R, v, ws);
     a.halo_out = H[0];
     if ((st = launch_k(R.fn, R, a, s)) != CN_OK) return st;
   }
-  if ((st = mids(nullptr)) != CN_OK) return st;
-  for (int64_t k = k0; k < k1; ++k) {
-    const UserArgs v = with_E(k);
-    for (int i : f.singles) {
-      KArgs a = plan_args(h, P->L[i], v, ws);
-      if ((st = launch_k(P->L[i].fn, P->L[i], a, s)) != CN_OK) return st;
+  if ((st = mids(nullptr, v)) != CN_OK) return st;
+  for (int64_t i = 0; i < nst; ++i) {
+    if (before && (st = before(i)) != CN_OK) return st;
+    for (int l : f.singles) {
+      KArgs a = plan_args(h, P->L[l], v, ws);
+      if ((st = launch_k(P->L[l].fn, P->L[l], a, s)) != CN_OK) return st;
     }
     KArgs a = plan_args(h, S, v, ws);
-    const int64_t i = k - k0;
     a.halo_in = H[i & 1];
     a.rev = S.a.rev ? (int)((i & 1) == 0) : 0;
-    if (k + 1 < k1) {
+    if (i + 1 < nst) {
+      const UserArgs vn = args(i + 1);
       a.halo_out = H[(i + 1) & 1];
       a.oU = (cd*)(ws + R.o_oU);
       a.oD = (cd*)(ws + R.o_oD);
-      a.E_next = Ek(k + 1);
+      a.E_next = vn.E_mat;
       if ((st = launch_k(g_kern[S.cfg][nsd::SRC_CN][nsd::PH_FUSE], S, a, s)) != CN_OK) return st;
-      if (ckpt && (k + 1) % K == 0)
-        HIP_TRY(hipMemcpyAsync(ckpt + ((k + 1) / K) * P->span, v.x, P->span * sizeof(cd),
-                               hipMemcpyDeviceToDevice, s));
-      if ((st = mids(H[(i + 1) & 1])) != CN_OK) return st;
+      if (after && (st = after(i)) != CN_OK) return st;
+      if ((st = mids(H[(i + 1) & 1], vn)) != CN_OK) return st;
+      v = vn;
     } else {
       if ((st = launch_k(S.fn, S, a, s)) != CN_OK) return st;
+      if (after && (st = after(i)) != CN_OK) return st;
     }
   }
   return CN_OK;
@@ -1198,7 +1193,20 @@ cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op,
   u.x = (cd*)psi;
   if (nsteps >= 2 && fuse_enabled()) {
     const FusePlan f = fuse_plan(P);
-    if (f.ok) return run_fused(h, P, f, u, 0, nsteps, (cd*)psi, 0, E, (cd*)ckpt, ckpt ? K : 1, s);
+    if (f.ok) {
+      auto args = [&](int64_t k) {
+        UserArgs v = u;
+        v.E_mat = v.E_rhs = E ? E[k] : 0.0;
+        return v;
+      };
+      auto before = [&](int64_t k) -> cn_status {
+        if (ckpt && k % K == 0)
+          HIP_TRY(hipMemcpyAsync((cd*)ckpt + (k / K) * P->span, psi, P->span * sizeof(cd),
+                                 hipMemcpyDeviceToDevice, s));
+        return CN_OK;
+      };
+      return run_chain(h, P, f, nsteps, args, before, nullptr, s);
+    }
   }
   for (int64_t k = 0; k < nsteps; ++k) {
     if (ckpt && k % K == 0) {
@@ -1371,7 +1379,6 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   Plan* P = nullptr;
   st = get_plan(h, L, nsd::SRC_CN, s, &P);
   if (st != CN_OK) return st;
-  cd* lam = (cd*)((char*)h->ws + P->o_aux);
   cd* segs = (cd*)seg;
   const int64_t span = P->span;
   // dE: every step of a segment writes its row of per-tile partials; one launch per segment
@@ -1394,10 +1401,12 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   }
   auto Ek = [&](int64_t k) { return E ? E[k] : 0.0; };
   const int64_t nseg = (nsteps + K - 1) / K;
-  // recompute segment sg forward from its checkpoint into buf (its K+1 states); step by step:
+  auto k0_of = [&](int64_t sg) { return sg * K; };
+  auto k1_of = [&](int64_t sg) { return std::min(nsteps, sg * K + K); };
+  // recompute segment sg forward from its checkpoint into buf (its K+1 states), step by step:
   // overlapped with the recursion, the lighter two-pass kernels measure faster than PH_FUSE
   auto recompute = [&](int64_t sg, cd* buf, void* ws, hipStream_t st) -> cn_status {
-    const int64_t k0 = sg * K, k1 = std::min(nsteps, k0 + K);
+    const int64_t k0 = k0_of(sg), k1 = k1_of(sg);
     HIP_TRY(hipMemcpyAsync(buf, (const cd*)ckpt + sg * span, span * sizeof(cd),
                            hipMemcpyDeviceToDevice, st));
     for (int64_t k = k0; k < k1; ++k) {
@@ -1416,52 +1425,13 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
     }
     return CN_OK;
   };
-  // adjoint recursion backwards through segment sg, whose states are in buf:
-  //   lambda_k = T_k^{-H} T_{k+1} lambda_{k+1}: a CN step with dt -> -dt whose explicit
-  //   half-step uses E_{k+1} and whose matrix uses E_k (T_{N-1}^{-H} g at the last step)
-  auto adjoint = [&](int64_t sg, const cd* buf, hipStream_t st) -> cn_status {
-    const int64_t k0 = sg * K, k1 = std::min(nsteps, k0 + K);
-    for (int64_t k = k1 - 1; k >= k0; --k) {
-      UserArgs u;
-      if (k == nsteps - 1) {
-        u.rhs = (const cd*)g;
-        u.psi = (const cd*)g;
-      } else {
-        u.psi = lam;
-      }
-      u.x = lam;
-      u.V = op->V;
-      u.xg = op->xgrid;
-      u.dxs = op->dx_per_system;
-      u.vscale = op->v_scale;
-      u.dx = op->dx;
-      u.dt = -op->dt;
-      u.E_mat = Ek(k);
-      u.E_rhs = (k + 1 < nsteps) ? Ek(k + 1) : Ek(k);
-      u.acc_pa = buf + (k - k0) * span;
-      u.acc_pb = buf + (k - k0 + 1) * span;
-      u.acc_dV = dV_accum;
-      u.acc_part = dE ? part + (k - k0) * P->ntiles1 : nullptr;
-      u.acc_tau = 0.5 * op->dt;
-      cn_status r = run_plan(h, P, u, st);
-      if (r != CN_OK) return r;
-    }
-    if (dE) {
-      hipLaunchKernelGGL(nsd::k_sum_partials, dim3((unsigned)(k1 - k0)), dim3(256), 0, st,
-                         (const double*)part, P->ntiles1, dE + k0);
-      if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
-    }
-    return CN_OK;
-  };
-  if (nseg >= 2 && !capturing(s) && bwd_overlap_enabled()) {
-    // The recompute of segment sg-1 depends only on its checkpoint: it runs on the second
-    // stream, into the other of two segment buffers and with its own workspace, while the
-    // adjoint recursion of segment sg runs on the caller's stream.
-    if (!h->aux) {
-      HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-      for (hipEvent_t& e : h->ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
-    const size_t sb = (size_t)(std::min(K, nsteps) + 1) * (size_t)span * sizeof(cd);
+  // The second workspace keeps the recompute off the recursion's workspace (the fused chain
+  // holds its next step's slots and edge rows there across steps); overlapped, the second
+  // segment buffer holds the next segment.  Both are allocated outside graph capture only.
+  const bool cap = capturing(s);
+  const bool overlap = nseg >= 2 && !cap && bwd_overlap_enabled();
+  if (!cap) {
+    const size_t sb = overlap ? (size_t)(std::min(K, nsteps) + 1) * (size_t)span * sizeof(cd) : 0;
     if (h->ws2_size < P->ws_bytes || h->seg2_bytes < sb) {
       HIP_TRY(hipDeviceSynchronize());
       if (h->ws2_size < P->ws_bytes) {
@@ -1479,48 +1449,92 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
         h->seg2_bytes = sb;
       }
     }
-    cd* bufs[2] = {segs, (cd*)h->seg2};
-    hipEvent_t start = h->ev[0], rec_done[2] = {h->ev[1], h->ev[2]},
-               adj_done[2] = {h->ev[3], h->ev[4]};
+    if (overlap && !h->aux) {
+      HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+      for (hipEvent_t& e : h->ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+  }
+  const FusePlan fz = fuse_enabled() ? fuse_plan(P) : FusePlan();
+  const bool chain = fz.ok && h->ws2 && h->ws2_size >= P->ws_bytes;
+  cd* bufs[2] = {segs, overlap ? (cd*)h->seg2 : segs};
+  auto buf_of = [&](int64_t sg) { return overlap ? bufs[(nseg - 1 - sg) & 1] : segs; };
+  hipEvent_t start = h->ev[0], rec_done[2] = {h->ev[1], h->ev[2]},
+             adj_done[2] = {h->ev[3], h->ev[4]};
+  // The recursion runs on g in place, step k = nsteps-1 .. 0 (chain step i = nsteps-1-k):
+  //   g_k = T_k lambda_k with lambda_k = T_k^{-H} g_{k+1}, i.e.
+  //   g_k = (1 - i tau H_k)^{-1} (1 + i tau H_k) g_{k+1},
+  // a CN step with dt -> -dt and E_k on both sides (the two factors commute), and
+  //   lambda_k = (g_k + g_{k+1}) / 2   (sum of (1 - i tau H_k) lambda_k = g_{k+1} and
+  //                                      (1 + i tau H_k) lambda_k = g_k),
+  // which the store of step k forms for the accumulation.  g_N is the gradient at the final
+  // state; g_0, the result, is the gradient at the initial one.
+  auto args = [&](int64_t i) {
+    const int64_t k = nsteps - 1 - i, sg = k / K, k0 = k0_of(sg);
+    const cd* buf = buf_of(sg);
+    UserArgs u;
+    u.psi = (const cd*)g;
+    u.x = (cd*)g;
+    u.V = op->V;
+    u.xg = op->xgrid;
+    u.dxs = op->dx_per_system;
+    u.vscale = op->v_scale;
+    u.dx = op->dx;
+    u.dt = -op->dt;
+    u.E_mat = u.E_rhs = Ek(k);
+    u.acc_pa = buf + (k - k0) * span;
+    u.acc_pb = buf + (k - k0 + 1) * span;
+    u.acc_dV = dV_accum;
+    u.acc_part = dE ? part + (k - k0) * P->ntiles1 : nullptr;
+    u.acc_tau = 0.5 * op->dt;
+    u.acc_half = 1;
+    return u;
+  };
+  // entering segment sg (at its last step): its states must be there.  Overlapped, the
+  // recompute of segment sg-1 starts on the second stream once segment sg+1 has released the
+  // buffer it will use; serially the segment is recomputed here.
+  auto before = [&](int64_t i) -> cn_status {
+    const int64_t k = nsteps - 1 - i, sg = k / K;
+    if (k != k1_of(sg) - 1) return CN_OK;
+    if (overlap) {
+      const int b = (int)((nseg - 1 - sg) & 1);
+      if (sg >= 1) {
+        if (sg + 1 <= nseg - 1) HIP_TRY(hipStreamWaitEvent(h->aux, adj_done[1 - b], 0));
+        cn_status r = recompute(sg - 1, bufs[1 - b], h->ws2, h->aux);
+        if (r != CN_OK) return r;
+        HIP_TRY(hipEventRecord(rec_done[1 - b], h->aux));
+      }
+      HIP_TRY(hipStreamWaitEvent(s, rec_done[b], 0));
+      return CN_OK;
+    }
+    return recompute(sg, segs, chain ? h->ws2 : nullptr, s);
+  };
+  // leaving segment sg (after its first step): its dE rows are summed (one launch, the fixed
+  // order of one sum per step) and its buffer is released
+  auto after = [&](int64_t i) -> cn_status {
+    const int64_t k = nsteps - 1 - i, sg = k / K, k0 = k0_of(sg);
+    if (k != k0) return CN_OK;
+    if (dE) {
+      hipLaunchKernelGGL(nsd::k_sum_partials, dim3((unsigned)(k1_of(sg) - k0)), dim3(256), 0, s,
+                         (const double*)part, P->ntiles1, dE + k0);
+      if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
+    }
+    if (overlap) HIP_TRY(hipEventRecord(adj_done[(nseg - 1 - sg) & 1], s));
+    return CN_OK;
+  };
+  if (overlap) {
     HIP_TRY(hipEventRecord(start, s));
     HIP_TRY(hipStreamWaitEvent(h->aux, start, 0));
     st = recompute(nseg - 1, bufs[0], h->ws2, h->aux);
     if (st != CN_OK) return st;
     HIP_TRY(hipEventRecord(rec_done[0], h->aux));
-    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
-      const int b = (int)((nseg - 1 - sg) & 1);
-      if (sg >= 1) {
-        // bufs[1-b] last held segment sg+1, whose adjoint must be done with it
-        if (sg + 1 <= nseg - 1) HIP_TRY(hipStreamWaitEvent(h->aux, adj_done[1 - b], 0));
-        st = recompute(sg - 1, bufs[1 - b], h->ws2, h->aux);
-        if (st != CN_OK) return st;
-        HIP_TRY(hipEventRecord(rec_done[1 - b], h->aux));
-      }
-      HIP_TRY(hipStreamWaitEvent(s, rec_done[b], 0));
-      st = adjoint(sg, bufs[b], s);
-      if (st != CN_OK) return st;
-      HIP_TRY(hipEventRecord(adj_done[b], s));
-    }
-  } else {
-    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
-      st = recompute(sg, segs, nullptr, s);
-      if (st != CN_OK) return st;
-      st = adjoint(sg, segs, s);
-      if (st != CN_OK) return st;
-    }
   }
-  // gradient at psi_0: G_0 = T_0 lambda_0 = (1 + i tau H_0) lambda_0
-  nsd::AuxArgs X = aux_from(L, P);
-  X.V = op->V;
-  X.xg = op->xgrid;
-  X.vscale = op->v_scale;
-  X.E = Ek(0);
-  X.dx = op->dx;
-  X.dxs = op->dx_per_system;
-  X.dt = -op->dt;
-  X.psi = lam;
-  X.d = (cd*)g;
-  return launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
+  if (chain) return run_chain(h, P, fz, nsteps, args, before, after, s);
+  for (int64_t i = 0; i < nsteps; ++i) {
+    if ((st = before(i)) != CN_OK) return st;
+    if ((st = run_plan(h, P, args(i), s)) != CN_OK) return st;
+    if ((st = after(i)) != CN_OK) return st;
+  }
+  return CN_OK;
 }
 
 cn_status cn_get_status(cn_handle_t h, cn_stream_t stream) {

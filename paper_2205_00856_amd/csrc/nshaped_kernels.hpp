@@ -68,6 +68,8 @@ struct KArgs {
   double* acc_dV;
   double* acc_part;
   double acc_tau;
+  int acc_half;           // lambda = (x + the value x overwrites) / 2 instead of x (reverse
+                          // recursion on g, where lambda_k = (g_k + g_{k+1}) / 2)
   int64_t batch;          // uniform batch size (column kernel)
   int cshared;            // uniform batch: every system reads the coefficients (a, b, c or V,
                           // xgrid) of system 0 (several right-hand sides of one matrix)
@@ -468,33 +470,43 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
   } else {
     // all loads of the tile's rows first: the stores below may alias them as far as the
     // compiler knows, which would otherwise cost one memory round trip per row
-    cd s[M];
-    double dv[M], xv[M];
+    // in two halves of the lane's rows, which keeps the gathered operands within the
+    // registers the solve needed
+    constexpr int CH = M >= 8 ? M / 2 : M;
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const int64_t r = w0 + 64 * k + sl;
-      const int64_t e = G.base + r * G.es;
-      cd sk = czero();
-      double d0 = 0.0, x0 = 0.0;
-      if (row_in<IN>(r, G.n)) {
-        sk = cadd(A.acc_pa[e], A.acc_pb[e]);
-        if (A.acc_dV) d0 = A.acc_dV[e];
-        if (A.xg) x0 = A.xg[e];
-      }
-      s[k] = sk;
-      dv[k] = d0;
-      xv[k] = x0;
-    }
+    for (int c = 0; c < M; c += CH) {
+      cd s[CH], ov[CH];
+      double dv[CH], xv[CH];
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const int64_t r = w0 + 64 * k + sl;
-      if (row_in<IN>(r, G.n)) {
-        const cd v = buf[S::addr(1 + 64 * k + sl)];
+      for (int k = 0; k < CH; ++k) {
+        const int64_t r = w0 + 64 * (c + k) + sl;
         const int64_t e = G.base + r * G.es;
-        g[r * G.es] = v;
-        const double q = A.acc_tau * (v.x * s[k].y - v.y * s[k].x);
-        if (A.acc_dV) A.acc_dV[e] = dv[k] + A.vscale * q;
-        if (A.xg) part = fma(xv[k], q, part);
+        cd sk = czero(), o = czero();
+        double d0 = 0.0, x0 = 0.0;
+        if (row_in<IN>(r, G.n)) {
+          sk = cadd(A.acc_pa[e], A.acc_pb[e]);
+          if (A.acc_dV) d0 = A.acc_dV[e];
+          if (A.xg) x0 = A.xg[e];
+          if (A.acc_half) o = g[r * G.es];
+        }
+        s[k] = sk;
+        ov[k] = o;
+        dv[k] = d0;
+        xv[k] = x0;
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int64_t r = w0 + 64 * (c + k) + sl;
+        if (row_in<IN>(r, G.n)) {
+          const cd v = buf[S::addr(1 + 64 * (c + k) + sl)];
+          const int64_t e = G.base + r * G.es;
+          g[r * G.es] = v;
+          const cd lam =
+              csel(A.acc_half != 0, mk(0.5 * (v.x + ov[k].x), 0.5 * (v.y + ov[k].y)), v);
+          const double q = A.acc_tau * (lam.x * s[k].y - lam.y * s[k].x);
+          if (A.acc_dV) A.acc_dV[e] = dv[k] + A.vscale * q;
+          if (A.xg) part = fma(xv[k], q, part);
+        }
       }
     }
   }
@@ -992,11 +1004,15 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
     for (int j = 0; j < M; ++j) {
       const int64_t r = r0 + j;
       if (live && r < n) {
+        cd old = czero();
+        if (acc && A.acc_half) old = col_at(A.x + c0, ob16, r, G.es);
         col_at(A.x + c0, ob16, r, G.es) = xo[j];
         bad |= !cfinite(xo[j]);
         if (acc) {
           const cd s = cadd(col_at(A.acc_pa + c0, ob16, r, G.es), col_at(A.acc_pb + c0, ob16, r, G.es));
-          const double q = A.acc_tau * (xo[j].x * s.y - xo[j].y * s.x);
+          const cd lam =
+              csel(A.acc_half != 0, mk(0.5 * (xo[j].x + old.x), 0.5 * (xo[j].y + old.y)), xo[j]);
+          const double q = A.acc_tau * (lam.x * s.y - lam.y * s.x);
           if (A.acc_dV) col_at(A.acc_dV + c0, ob8, r, G.es) += A.vscale * q;
           if (A.xg) part = fma(col_at(A.xg + c0, ob8, r, G.es), q, part);
         }
