@@ -1403,12 +1403,29 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   const int64_t nseg = (nsteps + K - 1) / K;
   auto k0_of = [&](int64_t sg) { return sg * K; };
   auto k1_of = [&](int64_t sg) { return std::min(nsteps, sg * K + K); };
-  // recompute segment sg forward from its checkpoint into buf (its K+1 states), step by step:
-  // overlapped with the recursion, the lighter two-pass kernels measure faster than PH_FUSE
+  // recompute segment sg forward from its checkpoint into buf (its K+1 states): a fused chain
+  // on the second workspace when there is one, else step by step
+  const FusePlan fzr = fuse_enabled() ? fuse_plan(P) : FusePlan();
   auto recompute = [&](int64_t sg, cd* buf, void* ws, hipStream_t st) -> cn_status {
     const int64_t k0 = k0_of(sg), k1 = k1_of(sg);
     HIP_TRY(hipMemcpyAsync(buf, (const cd*)ckpt + sg * span, span * sizeof(cd),
                            hipMemcpyDeviceToDevice, st));
+    if (fzr.ok && ws && k1 - k0 >= 2) {
+      auto rargs = [&](int64_t i) {
+        UserArgs u;
+        u.psi = buf + i * span;
+        u.x = buf + (i + 1) * span;
+        u.V = op->V;
+        u.xg = op->xgrid;
+        u.dxs = op->dx_per_system;
+        u.vscale = op->v_scale;
+        u.dx = op->dx;
+        u.dt = op->dt;
+        u.E_mat = u.E_rhs = Ek(k0 + i);
+        return u;
+      };
+      return run_chain(h, P, fzr, k1 - k0, rargs, nullptr, nullptr, st, ws);
+    }
     for (int64_t k = k0; k < k1; ++k) {
       UserArgs u;
       u.psi = buf + (k - k0) * span;
