@@ -152,3 +152,64 @@ def test_propagate_fused_graph_replays(gpu):
         cn.propagate(junk, tV, dx, dt, 2, layout=L)
         torch.cuda.synchronize()
         assert torch.equal(psi, eager)
+
+
+# ------------------------------------------------------------------ reverse mode on g
+def _reverse_case(torch, cn, oracle_mod, n, batch, steps, K, interleaved=False, seed=0):
+    """cn_propagate with checkpoints, then cn_propagate_adjoint, against the oracle's reverse
+    mode per system (dE summed over the systems, as the library sums over all rows)."""
+    dx, dt = 0.05, 0.01
+    g = np.random.default_rng(seed)
+    x1 = workloads.grid_1d(n, dx)
+    V = g.uniform(-1.0, 0.0, (batch, n))
+    P0 = workloads.complex_normal(g, (batch, n))
+    GT = workloads.complex_normal(g, (batch, n))
+    E = g.normal(0.0, 0.05, steps)
+    X = np.tile(x1, (batch, 1))
+    if interleaved:
+        L = cn.Layout.interleaved(n, batch)
+        lay = lambda a: np.ascontiguousarray(a.T).ravel()  # noqa: E731
+    else:
+        L = cn.Layout.contiguous(n, batch)
+        lay = lambda a: np.ascontiguousarray(a).ravel()  # noqa: E731
+    tV, tx, tp, tg = to_dev(torch, lay(V), lay(X), lay(P0), lay(GT))
+    nseg = (steps + K - 1) // K
+    ckpt = torch.empty(nseg * n * batch, dtype=torch.complex128, device="cuda")
+    cn.propagate(tp, tV, dx, dt, steps, E=E, xgrid=tx, ckpt=ckpt, K=K, layout=L)
+    dV = torch.zeros(n * batch, dtype=torch.float64, device="cuda")
+    dE = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    cn.propagate_adjoint(ckpt, tg, tV, dx, dt, steps, K, E=E, xgrid=tx, dV=dV, dE=dE, layout=L)
+    unlay = (lambda t: t.cpu().numpy().reshape(n, batch).T) if interleaved else \
+        (lambda t: t.cpu().numpy().reshape(batch, n))
+    g0, gV = unlay(tg), unlay(dV)
+    dE_ref = np.zeros(steps)
+    for s in range(batch):
+        r0, rV, rE = oracle_mod.cn_propagate_grad(P0[s], V[s], dx, dt, steps, GT[s], x1, E)
+        assert rel(g0[s], r0) <= 1e-10, s
+        assert rel(gV[s], rV) <= 1e-10, s
+        dE_ref += rE
+    assert rel(dE.cpu().numpy(), dE_ref) <= 1e-10
+    assert cn.get_status() == 0
+
+
+@pytest.mark.parametrize("n,steps,K", [(5000, 3, 10), (5000, 4, 1), (5000, 1, 3), (3000, 5, 2)])
+def test_reverse_mode_segments(gpu, oracle_mod, n, steps, K):
+    """One segment (serial chain, recompute on the second workspace), one step per segment
+    (the chain crosses a segment at every step), a single step, and single-tile systems
+    (no fusable group: steps one at a time)."""
+    torch, cn = gpu
+    log("reverse", n, steps, K)
+    _reverse_case(torch, cn, oracle_mod, n, 1, steps, K, seed=n + steps + K)
+
+
+def test_reverse_mode_interleaved_batch(gpu, oracle_mod):
+    """64 interleaved systems: the column kernels form lambda = (g_k + g_{k+1}) / 2 at their
+    store; segments overlapped on the second stream."""
+    torch, cn = gpu
+    _reverse_case(torch, cn, oracle_mod, 300, 64, 5, 2, interleaved=True, seed=3)
+
+
+def test_reverse_mode_uniform_batch_two_pass(gpu, oracle_mod):
+    """3 contiguous systems of 20 000 rows: the fused chain over a batch, 7 steps, K = 3."""
+    torch, cn = gpu
+    _reverse_case(torch, cn, oracle_mod, 20_000, 3, 7, 3, seed=11)
