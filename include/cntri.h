@@ -171,12 +171,15 @@ cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_
  * that cn_propagate stored before every step k with k % K == 0 (same layout, one span each);
  * seg is scratch for K+1 states.  On entry g is the gradient of a real loss at the final state
  * ((d/dRe + i d/dIm) convention); on return it is the gradient at the initial state.  Each
- * segment of K steps is recomputed forward from its checkpoint, then the adjoint recursion
- *   lambda_k = T_k^{-H} T_{k+1} lambda_{k+1}   (lambda_{N-1} = T_{N-1}^{-H} g)
- * runs backwards through it as Crank-Nicolson steps with dt -> -dt, accumulating
+ * segment of K steps is recomputed forward from its checkpoint; the recursion then runs
+ * backwards through it on g itself, g_N = g and
+ *   g_k = T_k lambda_k,  lambda_k = T_k^{-H} g_{k+1},  i.e.  g_k = (1 - i tau H_k)^{-1}
+ *   (1 + i tau H_k) g_{k+1}: a Crank-Nicolson step with dt -> -dt and E_k on both sides,
+ * with lambda_k = (g_k + g_{k+1}) / 2, accumulating
  *   dV_accum_j += v_scale tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (may be NULL)
  *   dE[k] = sum_j xgrid_j tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (needs xgrid; may be NULL)
- * in fixed order; finally g = T_0 lambda_0.  With two or more segments and a stream that is
+ * in fixed order; g_0 is the result.  Two-pass plans run the recompute and the recursion as
+ * fused passes (see cn_propagate).  With two or more segments and a stream that is
  * not being captured, the recompute of segment s-1 runs on a second stream of the handle while
  * the recursion runs through segment s; the handle then keeps a second segment buffer and a
  * second workspace (allocated on first use).  The results are the same in either form; the
