@@ -109,8 +109,10 @@ cn_status cn_create(cn_handle_t* handle, int device);
 cn_status cn_destroy(cn_handle_t handle);
 const char* cn_status_string(cn_status status);
 
-/* Builds the plan for this layout and grows the workspace so that later calls with the same
- * layout allocate nothing (required before HIP graph capture). */
+/* Builds the plans for this layout and grows the workspaces so that later calls with the same
+ * layout allocate nothing (required before HIP graph capture).  For cn_propagate_adjoint under
+ * capture this covers the fused recursion; its dE rows need one call outside capture first
+ * (they are sized by the segment length K). */
 cn_status cn_reserve(cn_handle_t handle, const cn_layout* layout);
 
 /* x = T^{-1} d for every system of the batch: the N-shaped partition method (Sec. 4,
@@ -184,7 +186,8 @@ cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_
  * the recursion runs through segment s; the handle then keeps a second segment buffer and a
  * second workspace (allocated on first use).  The results are the same in either form; the
  * call is ordered on the caller's stream as usual.  Under graph capture the segments run one
- * after the other on the caller's stream. */
+ * after the other on the caller's stream, as the same fused chain when the second workspace
+ * exists (cn_reserve, or an earlier call), else one step at a time (equal up to rounding). */
 cn_status cn_propagate_adjoint(cn_handle_t handle, const cn_layout* layout,
                                const cn_operator* op, int64_t nsteps, const double* E,
                                const void* ckpt, int64_t K, void* seg, void* g,

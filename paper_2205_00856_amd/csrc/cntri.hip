@@ -1040,6 +1040,15 @@ cn_status cn_reserve(cn_handle_t h, const cn_layout* L) {
     cn_status st = get_plan(h, L, src, nullptr, &P);
     if (st != CN_OK) return st;
   }
+  // the second workspace of the reverse mode's fused chain (P is the Crank-Nicolson plan)
+  if (h->ws2_size < P->ws_bytes) {
+    HIP_TRY(hipDeviceSynchronize());
+    if (h->ws2) (void)hipFree(h->ws2);
+    h->ws2 = nullptr;
+    h->ws2_size = 0;
+    if (hipMalloc(&h->ws2, P->ws_bytes) != hipSuccess) return CN_ERR_NO_MEMORY;
+    h->ws2_size = P->ws_bytes;
+  }
   return CN_OK;
 }
 

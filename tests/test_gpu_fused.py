@@ -213,3 +213,40 @@ def test_reverse_mode_uniform_batch_two_pass(gpu, oracle_mod):
     """3 contiguous systems of 20 000 rows: the fused chain over a batch, 7 steps, K = 3."""
     torch, cn = gpu
     _reverse_case(torch, cn, oracle_mod, 20_000, 3, 7, 3, seed=11)
+
+
+def test_reverse_mode_captured_after_reserve_only(gpu):
+    """A layout no call has used yet: after cn_reserve alone, the reverse mode (dV, no dE) is
+    captured and replayed; every replay equals an eager call bit for bit (both run the fused
+    chain, the capture with its segments one after the other)."""
+    torch, cn = gpu
+    n, dx, dt, steps, K = 40_003, 0.05, 0.01, 9, 4
+    g = np.random.default_rng(31)
+    V = g.uniform(-1.0, 0.0, n)
+    tV, tp, tg = to_dev(torch, V, workloads.complex_normal(g, n), workloads.complex_normal(g, n))
+    L = cn.Layout.contiguous(n, 1)
+    cn.reserve(L)
+    ckpt = torch.empty(((steps + K - 1) // K) * n, dtype=torch.complex128, device="cuda")
+    seg = torch.empty((K + 1) * n, dtype=torch.complex128, device="cuda")
+    gc = torch.empty_like(tg)
+    dVc = torch.zeros(n, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        cn.propagate(tp, tV, dx, dt, steps, ckpt=ckpt, K=K, layout=L)
+        cn.propagate_adjoint(ckpt, gc, tV, dx, dt, steps, K, dV=dVc, seg=seg, layout=L)
+    p0 = tp.clone()
+    for _ in range(3):
+        tp.copy_(p0)
+        gc.copy_(tg)
+        dVc.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        pe = p0.clone()
+        cn.propagate(pe, tV, dx, dt, steps, ckpt=ckpt, K=K, layout=L)
+        ge = tg.clone()
+        dVe = torch.zeros(n, dtype=torch.float64, device="cuda")
+        cn.propagate_adjoint(ckpt, ge, tV, dx, dt, steps, K, dV=dVe, seg=seg, layout=L)
+        torch.cuda.synchronize()
+        assert torch.equal(gc, ge) and torch.equal(dVc, dVe)
