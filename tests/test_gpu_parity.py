@@ -559,6 +559,22 @@ def test_autotune_keeps_results(gpu, oracle_mod):
     assert "chosen" in rep and "automatic" in rep
     out2 = cn.step(tpsi, tV, 0.0, wl["dt"], dx_per_system=tdx, layout=L)
     assert rel(out2.cpu().numpy(), ref) <= TOL
+    # a sequence over the tuned plan (fused when it has a two-pass group)
+    ref3 = wl["psi0"]
+    for _ in range(3):
+        ref3 = oracle_mod.cn_step_batched(wl["offsets"], ref3, wl["V"], wl["dx"], wl["dt"], 8)
+    p3 = tpsi.clone()
+    cn.propagate(p3, tV, 0.0, wl["dt"], 3, dx_per_system=tdx, layout=L)
+    assert rel(p3.cpu().numpy(), ref3) <= TOL
+    # a long CN line tuned in cn_step mode, then propagated
+    m, dxm, dtm = 300_001, 0.1, 0.02
+    inp = workloads.random_cn(m, 44, dxm, dtm)
+    mV, mp = to_dev(torch, inp["V"], inp["psi"])
+    Lm = cn.Layout.contiguous(m, 1)
+    rep = cn.autotune(Lm, mp, torch.empty_like(mp), V=mV, dx=dxm, dt=dtm)
+    log(rep)
+    cn.propagate(mp, mV, dxm, dtm, 4, layout=Lm)
+    assert rel(mp.cpu().numpy(), oracle_mod.cn_propagate(inp["psi"], inp["V"], dxm, dtm, 4)) <= TOL
     n = 200_000
     a, b, c, d = workloads.random_system(n, 3, "dd")
     xref = oracle_mod.thomas(a, b, c, d)
