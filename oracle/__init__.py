@@ -9,7 +9,9 @@ What it computes (arXiv 2205.00856):
 * ``thomas``            -- x = T^{-1} d by serial elimination without pivoting: the RS stage of
                            Table 1 applied to the whole system (Sec. 2 last paragraph, Sec. 4.1.5).
 * ``cn_coeffs``/``cn_rhs``/``cn_step``/``cn_propagate`` -- the CN step of Sec. 2, Eqs. (2)-(4),
-                           with the three-point Laplacian and Dirichlet walls.
+                           with the three-point Laplacian and Dirichlet walls.  ``W`` adds an
+                           absorbing potential (V - iW); the step is then the Cayley form
+                           (1 + i tau H)^{-1} (1 - i tau H), whose right side is not T^dagger.
 * ``adi_step``          -- one Lie-split ADI step (operator splitting, Sec. 3) on a 2D grid.
 * ``thomas_adjoint``    -- reverse mode of the solve (plain definition, lambda = T^{-H} G).
 * ``cn_propagate_grad`` -- reverse mode of many CN steps with every state stored.
@@ -61,6 +63,12 @@ def _load():
     lib.oracle_cn_rhs.restype = None
     lib.oracle_cn_step.argtypes = [i64, P, d, d, P, d, P, P]
     lib.oracle_cn_propagate.argtypes = [i64, P, d, d, i64, P, P, P]
+    lib.oracle_cn_coeffs_w.argtypes = [i64, P, d, d, P, d, P, P, P, P]
+    lib.oracle_cn_coeffs_w.restype = None
+    lib.oracle_cn_rhs_w.argtypes = [i64, P, P, d, d, P, d, P, P]
+    lib.oracle_cn_rhs_w.restype = None
+    lib.oracle_cn_step_w.argtypes = [i64, P, d, d, P, d, P, P, P]
+    lib.oracle_cn_propagate_w.argtypes = [i64, P, d, d, i64, P, P, P, P]
     lib.oracle_cn_step_batched.argtypes = [i64, P, P, P, d, P, P, ci]
     lib.oracle_adi_step.argtypes = [i64, i64, P, d, d, d, P, ci]
     lib.oracle_thomas_adjoint.argtypes = [i64, P, P, P, P, P, P, P, P, P]
@@ -113,44 +121,51 @@ def thomas_batched(offsets, a, b, c, d, nthreads: int = 0):
     return x
 
 
-def cn_coeffs(V, dx, dt, xgrid=None, E=0.0):
+def cn_coeffs(V, dx, dt, xgrid=None, E=0.0, W=None):
+    """T = 1 + i tau H; with W the potential is V - iW (absorbing, non-Hermitian H)."""
     lib = _load()
     V = _c(V, np.float64)
     xg = None if xgrid is None else _c(xgrid, np.float64)
+    Wa = None if W is None else _c(W, np.float64)
     n = V.shape[0]
     a, b, c = (np.empty(n, np.complex128) for _ in range(3))
-    lib.oracle_cn_coeffs(n, _p(V), dx, dt, _p(xg), E, _p(a), _p(b), _p(c))
+    lib.oracle_cn_coeffs_w(n, _p(V), dx, dt, _p(xg), E, _p(Wa), _p(a), _p(b), _p(c))
     return a, b, c
 
 
-def cn_rhs(psi, V, dx, dt, xgrid=None, E=0.0):
+def cn_rhs(psi, V, dx, dt, xgrid=None, E=0.0, W=None):
+    """d = (1 - i tau H) psi (Sec. 2, Eq. (3)); with W the potential is V - iW."""
     lib = _load()
     psi = _c(psi, np.complex128)
     V = _c(V, np.float64)
     xg = None if xgrid is None else _c(xgrid, np.float64)
+    Wa = None if W is None else _c(W, np.float64)
     d = np.empty_like(psi)
-    lib.oracle_cn_rhs(psi.shape[0], _p(psi), _p(V), dx, dt, _p(xg), E, _p(d))
+    lib.oracle_cn_rhs_w(psi.shape[0], _p(psi), _p(V), dx, dt, _p(xg), E, _p(Wa), _p(d))
     return d
 
 
-def cn_step(psi, V, dx, dt, xgrid=None, E=0.0):
+def cn_step(psi, V, dx, dt, xgrid=None, E=0.0, W=None):
     lib = _load()
     psi = _c(psi, np.complex128)
     V = _c(V, np.float64)
     xg = None if xgrid is None else _c(xgrid, np.float64)
+    Wa = None if W is None else _c(W, np.float64)
     out = np.empty_like(psi)
-    _check(lib.oracle_cn_step(psi.shape[0], _p(V), dx, dt, _p(xg), E, _p(psi), _p(out)))
+    _check(lib.oracle_cn_step_w(psi.shape[0], _p(V), dx, dt, _p(xg), E, _p(Wa), _p(psi),
+                                _p(out)))
     return out
 
 
-def cn_propagate(psi, V, dx, dt, nsteps, xgrid=None, E=None):
+def cn_propagate(psi, V, dx, dt, nsteps, xgrid=None, E=None, W=None):
     lib = _load()
     psi = _c(psi, np.complex128).copy()
     V = _c(V, np.float64)
     xg = None if xgrid is None else _c(xgrid, np.float64)
     Ea = None if E is None else _c(E, np.float64)
-    _check(lib.oracle_cn_propagate(psi.shape[0], _p(V), dx, dt, int(nsteps), _p(xg), _p(Ea),
-                                   _p(psi)))
+    Wa = None if W is None else _c(W, np.float64)
+    _check(lib.oracle_cn_propagate_w(psi.shape[0], _p(V), dx, dt, int(nsteps), _p(xg), _p(Ea),
+                                     _p(Wa), _p(psi)))
     return psi
 
 

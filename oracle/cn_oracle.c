@@ -83,53 +83,78 @@ int oracle_thomas_batched(int64_t batch, const int64_t* offsets, const cplx* a, 
 }
 
 /* Coefficients of T = 1 + i tau H (Sec. 2, Eq. (4) with the Laplacian above).
- * xgrid may be NULL (no field term). */
-void oracle_cn_coeffs(int64_t n, const double* V, double dx, double dt, const double* xgrid,
-                      double E, cplx* a, cplx* b, cplx* c) {
+ * xgrid may be NULL (no field term).  W may be NULL; else the potential is v - i W
+ * (an absorbing, non-Hermitian H), so that T's diagonal gains + tau W_j. */
+void oracle_cn_coeffs_w(int64_t n, const double* V, double dx, double dt, const double* xgrid,
+                        double E, const double* W, cplx* a, cplx* b, cplx* c) {
   double tau = 0.5 * dt;
   double kappa = tau / (2.0 * dx * dx);
   for (int64_t j = 0; j < n; ++j) {
     double v = V[j] + (xgrid ? xgrid[j] * E : 0.0);
-    a[j] = 1.0 + I * (tau * (1.0 / (dx * dx) + v));
+    cplx h = (1.0 / (dx * dx) + v) - I * (W ? W[j] : 0.0); /* diagonal of H */
+    a[j] = 1.0 + I * tau * h;
     b[j] = (j == 0) ? 0.0 : -I * kappa;
     c[j] = (j == n - 1) ? 0.0 : -I * kappa;
   }
 }
 
-/* Explicit forward half-step d = (1 - i tau H) psi (Sec. 2, Eq. (3)). */
-void oracle_cn_rhs(int64_t n, const cplx* psi, const double* V, double dx, double dt,
-                   const double* xgrid, double E, cplx* d) {
+void oracle_cn_coeffs(int64_t n, const double* V, double dx, double dt, const double* xgrid,
+                      double E, cplx* a, cplx* b, cplx* c) {
+  oracle_cn_coeffs_w(n, V, dx, dt, xgrid, E, NULL, a, b, c);
+}
+
+/* Explicit forward half-step d = (1 - i tau H) psi (Sec. 2, Eq. (3)).  For a Hermitian H this
+ * operator is T^dagger; with the absorbing term (W non-NULL) it is 1 - i tau H, not T^dagger:
+ * the step stays the Cayley form (1 + i tau H)^{-1} (1 - i tau H) of exp(-i dt H). */
+void oracle_cn_rhs_w(int64_t n, const cplx* psi, const double* V, double dx, double dt,
+                     const double* xgrid, double E, const double* W, cplx* d) {
   double tau = 0.5 * dt;
   double kappa = tau / (2.0 * dx * dx);
   for (int64_t j = 0; j < n; ++j) {
     double v = V[j] + (xgrid ? xgrid[j] * E : 0.0);
+    cplx h = (1.0 / (dx * dx) + v) - I * (W ? W[j] : 0.0);
     cplx left = (j > 0) ? psi[j - 1] : 0.0;
     cplx right = (j < n - 1) ? psi[j + 1] : 0.0;
-    d[j] = (1.0 - I * (tau * (1.0 / (dx * dx) + v))) * psi[j] + I * kappa * (left + right);
+    d[j] = (1.0 - I * tau * h) * psi[j] + I * kappa * (left + right);
   }
 }
 
+void oracle_cn_rhs(int64_t n, const cplx* psi, const double* V, double dx, double dt,
+                   const double* xgrid, double E, cplx* d) {
+  oracle_cn_rhs_w(n, psi, V, dx, dt, xgrid, E, NULL, d);
+}
+
 /* One CN step: d = (1 - i tau H) psi_in, then T psi_out = d (Sec. 2, Eqs. (3)-(4)).
- * psi_out may alias psi_in.  Returns the Thomas status. */
-int oracle_cn_step(int64_t n, const double* V, double dx, double dt, const double* xgrid,
-                   double E, const cplx* psi_in, cplx* psi_out) {
+ * psi_out may alias psi_in.  W may be NULL.  Returns the Thomas status. */
+int oracle_cn_step_w(int64_t n, const double* V, double dx, double dt, const double* xgrid,
+                     double E, const double* W, const cplx* psi_in, cplx* psi_out) {
   cplx* buf = (cplx*)malloc(sizeof(cplx) * (size_t)(6 * n));
   cplx *a = buf, *b = buf + n, *c = buf + 2 * n, *d = buf + 3 * n, *w = buf + 4 * n;
-  oracle_cn_coeffs(n, V, dx, dt, xgrid, E, a, b, c);
-  oracle_cn_rhs(n, psi_in, V, dx, dt, xgrid, E, d);
+  oracle_cn_coeffs_w(n, V, dx, dt, xgrid, E, W, a, b, c);
+  oracle_cn_rhs_w(n, psi_in, V, dx, dt, xgrid, E, W, d);
   int st = oracle_thomas(n, a, b, c, d, psi_out, w);
   free(buf);
   return st;
 }
 
+int oracle_cn_step(int64_t n, const double* V, double dx, double dt, const double* xgrid,
+                   double E, const cplx* psi_in, cplx* psi_out) {
+  return oracle_cn_step_w(n, V, dx, dt, xgrid, E, NULL, psi_in, psi_out);
+}
+
 /* nsteps CN steps in place.  E may be NULL (no field); else E[k] is the field of step k,
- * used on both sides of step k (midpoint sample). */
-int oracle_cn_propagate(int64_t n, const double* V, double dx, double dt, int64_t nsteps,
-                        const double* xgrid, const double* E, cplx* psi) {
+ * used on both sides of step k (midpoint sample).  W may be NULL. */
+int oracle_cn_propagate_w(int64_t n, const double* V, double dx, double dt, int64_t nsteps,
+                          const double* xgrid, const double* E, const double* W, cplx* psi) {
   int st = 0;
   for (int64_t k = 0; k < nsteps; ++k)
-    st |= oracle_cn_step(n, V, dx, dt, xgrid, E ? E[k] : 0.0, psi, psi);
+    st |= oracle_cn_step_w(n, V, dx, dt, xgrid, E ? E[k] : 0.0, W, psi, psi);
   return st;
+}
+
+int oracle_cn_propagate(int64_t n, const double* V, double dx, double dt, int64_t nsteps,
+                        const double* xgrid, const double* E, cplx* psi) {
+  return oracle_cn_propagate_w(n, V, dx, dt, nsteps, xgrid, E, NULL, psi);
 }
 
 /* One CN step for each of many packed systems (own dx each), one system per thread. */

@@ -325,3 +325,69 @@ def test_propagate_grad_matches_finite_differences(oracle_mod):
         Em[k] -= h
         fd = (loss(V, Ep) - loss(V, Em)) / (2 * h)
         assert abs(fd - dE[k]) <= 1e-7 * max(abs(fd), 1e-3)
+
+
+# ------------------------------------------- absorbing (non-Hermitian) potential V - iW
+def test_absorbing_coeffs_and_rhs_match_dense_hamiltonian(oracle_mod):
+    """With H = -1/2 D2 + diag(V - iW), the step is (1 + i tau H)^{-1} (1 - i tau H) psi; the
+    right side is 1 - i tau H, which differs from T^dagger once W is nonzero."""
+    n, dx, dt = 12, 0.3, 0.05
+    inp = workloads.random_cn(n, 23, dx, dt)
+    W = np.random.default_rng(5).uniform(0.0, 3.0, n)
+    H = hamiltonian_dense(inp["V"], dx) - 1j * np.diag(W)
+    A = np.eye(n) + 0.5j * dt * H
+    B = np.eye(n) - 0.5j * dt * H
+    a, b, c = oracle_mod.cn_coeffs(inp["V"], dx, dt, W=W)
+    np.testing.assert_allclose(dense(a, b, c), A, rtol=0, atol=1e-14)
+    d = oracle_mod.cn_rhs(inp["psi"], inp["V"], dx, dt, W=W)
+    np.testing.assert_allclose(d, B @ inp["psi"], rtol=0, atol=1e-13)
+    assert np.max(np.abs(B - A.conj().T)) > 0.01  # T^dagger would be a different operator
+    step = oracle_mod.cn_step(inp["psi"], inp["V"], dx, dt, W=W)
+    assert rel(step, np.linalg.solve(A, B @ inp["psi"])) <= 1e-13
+
+
+@pytest.mark.parametrize("W0", [0.05, 1.5])
+def test_absorbing_amplification_on_sine_modes(oracle_mod, W0):
+    """With constant V0 and W0 the sine modes stay eigenvectors of H, with eigenvalue
+    lam - i W0; one step multiplies each by (1 - tau W0 - i tau lam)/(1 + tau W0 + i tau lam),
+    whose modulus is below one."""
+    N, dx, dt, steps, V0 = 257, 0.1, 0.02, 40, -0.4
+    j = np.arange(1, N + 1)
+    tau = dt / 2
+    ks = [1, 3, 50, 256]
+    coef = np.array([1.0, 0.4j, -0.3 + 0.2j, 0.1])
+    psi0 = sum(ck * np.sin(k * np.pi * j / (N + 1)) for k, ck in zip(ks, coef))
+    out = oracle_mod.cn_propagate(psi0, np.full(N, V0), dx, dt, steps, W=np.full(N, W0))
+    ref = np.zeros(N, np.complex128)
+    for k, ck in zip(ks, coef):
+        lam = (1 - np.cos(k * np.pi / (N + 1))) / dx**2 + V0
+        g = (1 - tau * W0 - 1j * tau * lam) / (1 + tau * W0 + 1j * tau * lam)
+        assert abs(g) < 1
+        ref += ck * g**steps * np.sin(k * np.pi * j / (N + 1))
+    assert rel(out, ref) <= 1e-12
+
+
+def test_absorbing_norm_decays_and_zero_W_is_hermitian_step(oracle_mod):
+    """W >= 0 makes every step contract the norm; W = 0 gives the Hermitian step exactly."""
+    w = workloads.absorbing_1d(n=2048)
+    psi = workloads.gaussian(w["x"], w["x"][1880], 5.0, 2.0, w["dx"])  # on the ramp
+    norms = [np.sum(np.abs(psi) ** 2)]
+    for _ in range(30):
+        psi = oracle_mod.cn_step(psi, w["V"], w["dx"], w["dt"], W=w["W"])
+        norms.append(np.sum(np.abs(psi) ** 2))
+    assert all(b < a for a, b in zip(norms, norms[1:]))
+    z = oracle_mod.cn_step(psi, w["V"], w["dx"], w["dt"], W=np.zeros(2048))
+    h = oracle_mod.cn_step(psi, w["V"], w["dx"], w["dt"])
+    assert np.array_equal(z, h)
+
+
+def test_absorbing_loss_rate(oracle_mod):
+    """For small dt the norm falls at the rate d|psi|^2/dt = -2 sum W |psi|^2."""
+    w = workloads.absorbing_1d(n=2048)
+    psi0 = w["psi0"]
+    W = np.full(2048, 0.3)
+    for dt in (1e-3, 5e-4):
+        p1 = oracle_mod.cn_step(psi0, w["V"], w["dx"], dt, W=W)
+        rate = (np.sum(np.abs(p1) ** 2) - np.sum(np.abs(psi0) ** 2)) / dt
+        expect = -2 * np.sum(W * np.abs(psi0) ** 2)
+        assert abs(rate - expect) <= 2 * dt * abs(expect)

@@ -65,6 +65,23 @@ def plain_1d(n: int = 65536, dx: float = 0.1, dt: float = 0.02, steps: int = 200
                 psi0=gaussian(x, 0.0, 5.0, 1.0, dx))
 
 
+def absorber(n: int, frac: float = 0.1, strength: float = 2.0) -> np.ndarray:
+    """A quadratic absorbing ramp W >= 0 over the outer `frac` of the box at both walls, zero
+    inside: the usual shape of a complex absorbing potential (the potential is V - iW)."""
+    j = np.arange(n, dtype=np.float64)
+    width = max(1.0, frac * n)
+    depth = np.maximum(0.0, np.maximum(width - j, j - (n - 1 - width)) / width)
+    return strength * depth * depth
+
+
+def absorbing_1d(n: int = 65536, dx: float = 0.1, dt: float = 0.02, steps: int = 200):
+    """The plain 1D workload with an absorbing ramp over the outer tenth of the box, and the
+    wave packet started off centre and moving toward the right wall."""
+    x = grid_1d(n, dx)
+    return dict(name="absorbing_1d", n=n, dx=dx, dt=dt, steps=steps, x=x, V=softcore(x),
+                W=absorber(n), psi0=gaussian(x, x[int(0.7 * n)], 5.0, 2.0, dx))
+
+
 def adi_2d(n: int = 4096, dx: float = 0.1, dt: float = 0.01, steps: int = 100,
            seed: int = SEED_BASE + 1):
     g = rng(seed)
