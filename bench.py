@@ -504,6 +504,12 @@ def extras(torch, np, cn, workloads, dev):
             out["plain_1d"]["parity_rel_l2_200"] = rel_l2(psi200, ref["x"])
     except Exception as ex:  # noqa: BLE001
         out["plain_1d"] = {"error": repr(ex)}
+    # ----------------------------------------------------------- absorbing potential V - iW
+    try:
+        out["absorbing"] = absorbing(torch, np, cn, workloads, dev)
+        torch.cuda.empty_cache()
+    except Exception as ex:  # noqa: BLE001
+        out["absorbing"] = {"error": repr(ex)}
     # ----------------------------------------------------------- uneven batch
     try:
         wl = workloads.uneven_batch()
@@ -575,6 +581,59 @@ def extras(torch, np, cn, workloads, dev):
     except Exception as ex:  # noqa: BLE001
         out["propagate_2^24"] = {"error": repr(ex)}
     return out
+
+
+def absorbing(torch, np, cn, workloads, dev):
+    """Steps with an absorbing potential (non-Hermitian H), which run materialised: d into a
+    buffer, then the general two-pass solve (T assembled once without a field).  The plain 1D
+    workload with a ramp at both walls, 200 steps in a graph, with the oracle's 200 steps for
+    parity; and 2^24 rows, 10 steps, priced at 48 B (explicit side: psi, V, W in, d out) plus
+    144 B (two-pass solve of a, b, c, d) per unknown and step."""
+    res = {}
+    w = workloads.absorbing_1d()
+    psi0 = torch.from_numpy(w["psi0"]).to(dev)
+    V = torch.from_numpy(w["V"]).to(dev)
+    W = torch.from_numpy(w["W"]).to(dev)
+    L = cn.Layout.contiguous(w["n"], 1)
+    cn.reserve(L)
+    psi = psi0.clone()
+    cn.propagate(psi, V, w["dx"], w["dt"], 1, W=W, layout=L)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        cn.propagate(psi, V, w["dx"], w["dt"], w["steps"], W=W, layout=L)
+    psi.copy_(psi0)
+    gr.replay()
+    torch.cuda.synchronize()
+    psi200 = psi.cpu().numpy()
+    med = float(np.median(timed_events(torch, gr.replay, 5)))
+    n0 = float(np.sum(np.abs(w["psi0"]) ** 2))
+    res["1d_65536"] = {"steps": w["steps"], "us_per_step_graph": med * 1e3 / w["steps"],
+                       "unknowns_per_s": w["n"] * w["steps"] / (med * 1e-3),
+                       "norm_left_after_200": float(np.sum(np.abs(psi200) ** 2)) / n0}
+    ref = {}
+    res["1d_65536"]["cpu_baseline"] = oracle_timed(
+        "200 absorbing CN steps of the 65536-row system (serial FP64 Thomas, 1 thread)",
+        lambda o: (lambda: ref.setdefault("x", o.cn_propagate(w["psi0"], w["V"], w["dx"],
+                                                              w["dt"], w["steps"], W=w["W"]))),
+        w["n"] * w["steps"], res["1d_65536"]["unknowns_per_s"])
+    if "x" in ref:
+        res["1d_65536"]["parity_rel_l2_200"] = rel_l2(psi200, ref["x"])
+    del psi, psi0, V, W
+    n, steps = 1 << 24, 10
+    g = np.random.default_rng(1010)
+    Vb = torch.from_numpy(g.uniform(-1.0, 0.0, n)).to(dev)
+    Wb = torch.from_numpy(workloads.absorber(n)).to(dev)
+    pb = torch.from_numpy(workloads.complex_normal(g, n)).to(dev)
+    Lb = cn.Layout.contiguous(n, 1)
+    cn.reserve(Lb)
+    cn.propagate(pb, Vb, 0.01, 0.02, 1, W=Wb, layout=Lb)
+    ts = timed_events(torch, lambda: cn.propagate(pb, Vb, 0.01, 0.02, steps, W=Wb, layout=Lb), 3)
+    us = float(np.median(ts)) * 1e3 / steps
+    res["2^24"] = {"steps": steps, "us_per_step": us, "unknowns_per_s": n / (us * 1e-6),
+                   "GBps_192": 192.0 * n / (us * 1e-6) / 1e9,
+                   "frac_of_8TBps": 192.0 * n / (us * 1e-6) / 8e12}
+    return res
 
 
 def differentiated(torch, np, workloads, dev):

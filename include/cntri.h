@@ -88,7 +88,17 @@ typedef struct {
  *   three-point Laplacian, tau = dt/2, kappa = tau / (2 dx^2):
  *   T = 1 + i tau H: diagonal 1 + i tau (1/dx^2 + v_j), off-diagonals -i kappa.
  * V and xgrid are DEVICE arrays with the layout of psi.  dx_per_system (DEVICE, batch values)
- * overrides dx when non-NULL. */
+ * overrides dx when non-NULL.
+ * absorb (DEVICE, layout of psi, values W_j >= 0 expected) or NULL: an absorbing potential,
+ * v_j - i W_j, which makes H non-Hermitian.  T's diagonal becomes 1 + tau W_j + i tau (...) and
+ * the explicit side is 1 - i tau H (diagonal 1 - tau W_j - i tau (...)), which is no longer
+ * T^dagger: the step stays the Cayley form (1 + i tau H)^{-1} (1 - i tau H).  cn_assemble,
+ * cn_rhs, cn_step and cn_propagate take it; cn_step and cn_propagate then run materialised
+ * (cn_assemble, cn_rhs and cn_tridiag_solve's kernels through a handle buffer of 4 * span
+ * complex values, allocated on the first such call for a layout, so a captured call needs one
+ * call outside capture first, else CN_ERR_NOT_RESERVED) with no cross-step fusion.  The
+ * adjoint entry points and cn_autotune return CN_ERR_UNSUPPORTED for it, as do shared
+ * coefficients.  Zero-initialise the struct so that absorb is NULL by default. */
 typedef struct {
   const double* V;
   double v_scale;
@@ -96,6 +106,7 @@ typedef struct {
   const double* dx_per_system;
   double dt;
   const double* xgrid;
+  const double* absorb;
 } cn_operator;
 
 /* Host-only check of a layout (no device access): CN_OK, or the negative status that every

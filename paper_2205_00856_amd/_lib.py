@@ -41,6 +41,7 @@ class CnOperator(ctypes.Structure):
         ("dx_per_system", ctypes.c_void_p),
         ("dt", ctypes.c_double),
         ("xgrid", ctypes.c_void_p),
+        ("absorb", ctypes.c_void_p),
     ]
 
 

@@ -151,8 +151,9 @@ def _layout_for(t: torch.Tensor, layout: Optional[Layout]) -> Layout:
     raise ValueError("give a Layout for tensors of more than two dimensions")
 
 
-def _operator(V, dx, dt, xgrid=None, v_scale=1.0, dx_per_system=None) -> CnOperator:
+def _operator(V, dx, dt, xgrid=None, v_scale=1.0, dx_per_system=None, W=None) -> CnOperator:
     op = CnOperator()
+    op.absorb = None if W is None else W.data_ptr()
     op.V = V.data_ptr()
     op.v_scale = float(v_scale)
     op.dx = float(dx)
@@ -162,9 +163,11 @@ def _operator(V, dx, dt, xgrid=None, v_scale=1.0, dx_per_system=None) -> CnOpera
     return op
 
 
-def _check_op(L: Layout, V, xgrid, dx_per_system):
+def _check_op(L: Layout, V, xgrid, dx_per_system, W=None):
     span = L.coef_span()
     _need(V, torch.float64, "V", span)
+    if W is not None:
+        _need(W, torch.float64, "W", span)
     if xgrid is not None:
         _need(xgrid, torch.float64, "xgrid", span)
     if dx_per_system is not None:
@@ -222,15 +225,15 @@ def solve_adjoint(a, b, c, x, gx, need_abc=True, layout: Optional[Layout] = None
 
 
 def assemble(V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
-             layout: Optional[Layout] = None):
+             layout: Optional[Layout] = None, W=None):
     """Materialised coefficients (a, b, c) of T = 1 + i dt/2 H (cn_assemble)."""
     L = _layout_for(V, layout)
-    _check_op(L, V, xgrid, dx_per_system)
+    _check_op(L, V, xgrid, dx_per_system, W)
     shape = V.shape
     a = torch.empty(shape, dtype=torch.complex128, device=V.device)
     b = torch.empty_like(a)
     c = torch.empty_like(a)
-    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system, W)
     h = handle(V.device.index)
     Lc = L.c()
     check(_lib.lib().cn_assemble(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E), _ptr(a),
@@ -239,13 +242,13 @@ def assemble(V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
 
 
 def rhs(psi, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
-        layout: Optional[Layout] = None):
+        layout: Optional[Layout] = None, W=None):
     """Materialised explicit half-step d = (1 - i dt/2 H) psi (cn_rhs)."""
     L = _layout_for(psi, layout)
     _need(psi, torch.complex128, "psi", L.span())
-    _check_op(L, V, xgrid, dx_per_system)
+    _check_op(L, V, xgrid, dx_per_system, W)
     d = torch.empty_like(psi)
-    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system, W)
     h = handle(psi.device.index)
     Lc = L.c()
     check(_lib.lib().cn_rhs(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E), _ptr(psi),
@@ -254,15 +257,16 @@ def rhs(psi, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
 
 
 def step(psi, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None, out=None,
-         layout: Optional[Layout] = None):
-    """One Crank-Nicolson step (cn_step).  out may be psi (in place)."""
+         layout: Optional[Layout] = None, W=None):
+    """One Crank-Nicolson step (cn_step).  out may be psi (in place).  W: absorbing potential
+    (the potential is V - iW), taken in materialised form."""
     L = _layout_for(psi, layout)
     _need(psi, torch.complex128, "psi", L.span())
-    _check_op(L, V, xgrid, dx_per_system)
+    _check_op(L, V, xgrid, dx_per_system, W)
     if out is None:
         out = torch.empty_like(psi)
     _need(out, torch.complex128, "out", L.span())
-    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system, W)
     h = handle(psi.device.index)
     Lc = L.c()
     check(_lib.lib().cn_step(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E), _ptr(psi),
@@ -271,11 +275,11 @@ def step(psi, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None, out
 
 
 def propagate(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0, dx_per_system=None,
-              ckpt=None, K=1, layout: Optional[Layout] = None):
+              ckpt=None, K=1, layout: Optional[Layout] = None, W=None):
     """nsteps CN steps in place on psi (cn_propagate); E: host sequence of nsteps values."""
     L = _layout_for(psi, layout)
     _need(psi, torch.complex128, "psi", L.span())
-    _check_op(L, V, xgrid, dx_per_system)
+    _check_op(L, V, xgrid, dx_per_system, W)
     Earr = None
     if E is not None:
         Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
@@ -283,7 +287,7 @@ def propagate(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0, dx_per_sy
             raise ValueError("E needs one value per step")
     if ckpt is not None:
         _need(ckpt, torch.complex128, "ckpt", ((nsteps + K - 1) // K) * L.span())
-    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system)
+    op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system, W)
     h = handle(psi.device.index)
     Lc = L.c()
     Ep = None if Earr is None else Earr.ctypes.data_as(ctypes.c_void_p)

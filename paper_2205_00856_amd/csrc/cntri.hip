@@ -608,6 +608,9 @@ struct cn_handle_s {
   size_t ws2_size = 0;
   void* seg2 = nullptr;
   size_t seg2_bytes = 0;
+  // materialised a, b, c, d of steps with an absorbing potential
+  void* mat = nullptr;
+  size_t mat_size = 0;
 };
 
 namespace {
@@ -971,6 +974,68 @@ cn_status check_op(const cn_operator* op) {
   return CN_OK;
 }
 
+nsd::AuxArgs aux_op(const cn_layout* L, const Plan* P, const cn_operator* op, double E) {
+  nsd::AuxArgs X = aux_from(L, P);
+  X.offs = dev_offsets(P);
+  X.V = op->V;
+  X.xg = op->xgrid;
+  X.vscale = op->v_scale;
+  X.E = E;
+  X.dx = op->dx;
+  X.dxs = op->dx_per_system;
+  X.dt = op->dt;
+  X.W = op->absorb;
+  return X;
+}
+
+// A Crank-Nicolson step whose potential has an absorbing part (V - iW): T and the explicit
+// side 1 - i tau H are no longer each other's adjoints and T's diagonal has a real part other
+// than 1, so the step is taken in materialised form -- a, b, c and d = (1 - i tau H) psi_in in
+// the handle's buffer, then the general solve of the same layout.  coeffs = false reuses a, b, c
+// from the previous call (same operator and field).
+cn_status absorbing_step(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E,
+                         bool coeffs, const cd* psi_in, cd* psi_out, hipStream_t s) {
+  if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
+  Plan* P = nullptr;
+  cn_status st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  if (st != CN_OK) return st;
+  Plan* Pe = nullptr;
+  st = get_plan(h, L, nsd::SRC_EXPL, s, &Pe);
+  if (st != CN_OK) return st;
+  const int64_t sp = P->span;
+  const size_t need = 4 * (size_t)sp * sizeof(cd);
+  if (h->mat_size < need) {
+    if (capturing(s)) return CN_ERR_NOT_RESERVED;
+    HIP_TRY(hipDeviceSynchronize());
+    if (h->mat) (void)hipFree(h->mat);
+    h->mat = nullptr;
+    h->mat_size = 0;
+    if (hipMalloc(&h->mat, need) != hipSuccess) return CN_ERR_NO_MEMORY;
+    h->mat_size = need;
+    coeffs = true;
+  }
+  cd* m = (cd*)h->mat;
+  nsd::AuxArgs X = aux_op(L, P, op, E);
+  if (coeffs) {
+    X.a = m;
+    X.b = m + sp;
+    X.c = m + 2 * sp;
+    st = launch_aux((const void*)&nsd::k_assemble, P->rows, X, s);
+    if (st != CN_OK) return st;
+  }
+  X.psi = psi_in;
+  X.d = m + 3 * sp;
+  st = launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
+  if (st != CN_OK) return st;
+  UserArgs u;
+  u.a = m;
+  u.b = m + sp;
+  u.c = m + 2 * sp;
+  u.d = m + 3 * sp;
+  u.x = psi_out;
+  return run_plan(h, Pe, u, s);
+}
+
 }  // namespace
 
 // =============================================================================== C ABI
@@ -1025,6 +1090,7 @@ cn_status cn_destroy(cn_handle_t h) {
   if (h->rows_buf) (void)hipFree(h->rows_buf);
   if (h->ws2) (void)hipFree(h->ws2);
   if (h->seg2) (void)hipFree(h->seg2);
+  if (h->mat) (void)hipFree(h->mat);
   for (hipEvent_t e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -1119,15 +1185,7 @@ cn_status cn_assemble(cn_handle_t h, const cn_layout* L, const cn_operator* op, 
   Plan* P = nullptr;
   st = get_plan(h, L, nsd::SRC_CN, s, &P);
   if (st != CN_OK) return st;
-  nsd::AuxArgs X = aux_from(L, P);
-  X.offs = dev_offsets(P);
-  X.V = op->V;
-  X.xg = op->xgrid;
-  X.vscale = op->v_scale;
-  X.E = E;
-  X.dx = op->dx;
-  X.dxs = op->dx_per_system;
-  X.dt = op->dt;
+  nsd::AuxArgs X = aux_op(L, P, op, E);
   X.a = (cd*)a;
   X.b = (cd*)b;
   X.c = (cd*)c;
@@ -1144,15 +1202,7 @@ cn_status cn_rhs(cn_handle_t h, const cn_layout* L, const cn_operator* op, doubl
   Plan* P = nullptr;
   st = get_plan(h, L, nsd::SRC_CN, s, &P);
   if (st != CN_OK) return st;
-  nsd::AuxArgs X = aux_from(L, P);
-  X.offs = dev_offsets(P);
-  X.V = op->V;
-  X.xg = op->xgrid;
-  X.vscale = op->v_scale;
-  X.E = E;
-  X.dx = op->dx;
-  X.dxs = op->dx_per_system;
-  X.dt = op->dt;
+  nsd::AuxArgs X = aux_op(L, P, op, E);
   X.psi = (const cd*)psi;
   X.d = (cd*)d;
   return launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
@@ -1164,6 +1214,8 @@ cn_status cn_step(cn_handle_t h, const cn_layout* L, const cn_operator* op, doub
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (op->absorb)
+    return absorbing_step(h, L, op, E, true, (const cd*)psi_in, (cd*)psi_out, s);
   Plan* P = nullptr;
   st = get_plan(h, L, nsd::SRC_CN, s, &P);
   if (st != CN_OK) return st;
@@ -1191,6 +1243,18 @@ cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op,
   Plan* P = nullptr;
   st = get_plan(h, L, nsd::SRC_CN, s, &P);
   if (st != CN_OK) return st;
+  if (op->absorb) {
+    for (int64_t k = 0; k < nsteps; ++k) {
+      if (ckpt && k % K == 0)
+        HIP_TRY(hipMemcpyAsync((cd*)ckpt + (k / K) * P->span, psi, P->span * sizeof(cd),
+                               hipMemcpyDeviceToDevice, s));
+      // without a field T is the same every step: assemble it once
+      st = absorbing_step(h, L, op, E ? E[k] : 0.0, k == 0 || E != nullptr, (const cd*)psi,
+                          (cd*)psi, s);
+      if (st != CN_OK) return st;
+    }
+    return CN_OK;
+  }
   UserArgs u;
   u.psi = (const cd*)psi;
   u.V = op->V;
@@ -1234,9 +1298,10 @@ cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* 
                           double* dV_accum, double* dE_partial, cn_stream_t stream) {
   if (!h || !psi_n || !psi_np1 || !g_np1 || !g_n) return CN_ERR_INVALID_ARG;
   if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
-  if (dE_partial && !op->xgrid) return CN_ERR_INVALID_ARG;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
+  if (dE_partial && !op->xgrid) return CN_ERR_INVALID_ARG;
+  if (op->absorb) return CN_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   Plan* P = nullptr;
   st = get_plan(h, L, nsd::SRC_CN, s, &P);
@@ -1297,6 +1362,7 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
                       void* x, char* report, int64_t report_len, cn_stream_t stream) {
   if (!h || !L || !d || !x || d == x) return CN_ERR_INVALID_ARG;
   if (cn_mode && check_op(op) != CN_OK) return CN_ERR_INVALID_ARG;
+  if (cn_mode && op->absorb) return CN_ERR_UNSUPPORTED;
   if (!cn_mode && (!a || !b || !c)) return CN_ERR_INVALID_ARG;
   if (L->partition != 0 || L->rows_per_thread != 0) return CN_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -1383,6 +1449,7 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   if (L->offsets) return CN_ERR_UNSUPPORTED;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
+  if (op->absorb) return CN_ERR_UNSUPPORTED;
   if (dE && !op->xgrid) return CN_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   Plan* P = nullptr;

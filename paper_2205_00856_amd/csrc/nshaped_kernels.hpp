@@ -1143,6 +1143,7 @@ struct AuxArgs {
   const double* xg;
   double vscale, E, dx, dt;
   const double* dxs;
+  const double* W;  // absorbing potential (the potential is V - iW), or null
   const cd* psi;
   cd *a, *b, *c, *d;
   // adjoint accumulation
@@ -1190,7 +1191,8 @@ __global__ void k_assemble(AuxArgs A) {
   const double dx = A.dxs ? A.dxs[sys] : A.dx;
   const double tau = 0.5 * A.dt, idx2 = 1.0 / (dx * dx), kap = tau * 0.5 * idx2;
   const double v = A.vscale * A.V[e] + (A.xg ? A.xg[e] * A.E : 0.0);
-  A.a[e] = mk(1.0, tau * (idx2 + v));
+  // with the absorbing term -iW in H the diagonal of 1 + i tau H gains + tau W
+  A.a[e] = mk(A.W ? fma(tau, A.W[e], 1.0) : 1.0, tau * (idx2 + v));
   A.b[e] = mk(0.0, (r > 0) ? -kap : 0.0);
   A.c[e] = mk(0.0, (r < n - 1) ? -kap : 0.0);
 }
@@ -1207,7 +1209,10 @@ __global__ void k_rhs(AuxArgs A) {
   const cd l = csel(r > 0, A.psi[(r > 0) ? e - st : e], czero());
   const cd h = csel(r < n - 1, A.psi[(r < n - 1) ? e + st : e], czero());
   const cd s = cadd(l, h);
-  A.d[e] = mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y)));
+  // the diagonal of 1 - i tau H is 1 - tau W - i w (with the absorbing term, not T^dagger's)
+  const double f = A.W ? fma(-tau, A.W[e], 1.0) : 1.0;
+  const cd q = A.W ? mk(f * p.x, f * p.y) : p;
+  A.d[e] = mk(fma(w, p.y, fma(-kap, s.y, q.x)), fma(-w, p.x, fma(kap, s.x, q.y)));
 }
 
 // gradients of the solve: ga_i = -lam_i conj(x_i), gb_i = -lam_i conj(x_{i-1}), gc_i = ...

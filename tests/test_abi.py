@@ -100,3 +100,34 @@ def test_layout_errors_are_reported_on_the_host():
     assert check(L(n=10, batch=3, es=1, bs=10, shared=1)) == OK   # one matrix, 3 right-hand sides
     assert check(L(shared=2)) == BAD
     assert check(L(offsets=[0, 5, 9], batch=2, shared=1)) == UNSUP
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of cn_layout and cn_operator have the C structs' size and field
+    offsets (the header compiled by the host C compiler)."""
+    import shutil
+    import subprocess
+
+    from paper_2205_00856_amd._lib import CnLayout, CnOperator
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"cn_layout": CnLayout, "cn_operator": CnOperator}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cntri.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, field, value = line.split()
+        py = structs[cname]
+        want = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(value) == want, (cname, field)

@@ -76,10 +76,10 @@ def absorber(n: int, frac: float = 0.1, strength: float = 2.0) -> np.ndarray:
 
 def absorbing_1d(n: int = 65536, dx: float = 0.1, dt: float = 0.02, steps: int = 200):
     """The plain 1D workload with an absorbing ramp over the outer tenth of the box, and the
-    wave packet started off centre and moving toward the right wall."""
+    wave packet started inside the right ramp (at 93 % of the box), moving toward the wall."""
     x = grid_1d(n, dx)
     return dict(name="absorbing_1d", n=n, dx=dx, dt=dt, steps=steps, x=x, V=softcore(x),
-                W=absorber(n), psi0=gaussian(x, x[int(0.7 * n)], 5.0, 2.0, dx))
+                W=absorber(n), psi0=gaussian(x, x[int(0.93 * n)], 5.0, 2.0, dx))
 
 
 def adi_2d(n: int = 4096, dx: float = 0.1, dt: float = 0.01, steps: int = 100,
