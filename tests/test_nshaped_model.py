@@ -156,3 +156,18 @@ def test_deferred_joint_row_term(oracle_mod, n, p):
         wrong[w] = 1j * kap * psi[J[w] - 2]
     bad = nm._rs(ra2, rb2, rc2, rd_part + wrong, [])
     assert rel(bad, support) > 1e-6
+
+
+def test_absorbing_pivots_and_nested_solve(oracle_mod):
+    """With an absorbing potential T = I + tau W + iK (W >= 0 diagonal, K real symmetric) the
+    Hermitian part of T is at least I, and so is that of every Schur complement: every pivot of
+    the partitioned elimination keeps Re >= 1 (no pivoting needed, as for the Hermitian case),
+    and the nested N-shaped solve equals the oracle's Thomas solve."""
+    w = workloads.absorbing_1d(n=3000)
+    a, b, c = oracle_mod.cn_coeffs(w["V"], w["dx"], w["dt"], W=w["W"])
+    d = oracle_mod.cn_rhs(w["psi0"], w["V"], w["dx"], w["dt"], W=w["W"])
+    assert max(np.real(a)) > 1.0 + 1e-3  # the absorber really changes the diagonal
+    J = nm.uniform_joints(3000, 37)
+    x, piv = nm.solve(a, b, c, d, J, [nm.uniform_joints(len(J), 4)], return_pivots=True)
+    assert min(np.real(piv)) >= 1.0 - 1e-12
+    assert rel(x, oracle_mod.thomas(a, b, c, d)) <= 1e-13
