@@ -14,10 +14,11 @@ steps, one fused pass per step) and one 2^22-row matrix with 16 right-hand sides
 oracle timed beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--cpu-seconds S]
-                       [--copy-ref] [--only-large] [--only-propagate]
+                       [--copy-ref] [--only-large] [--only-propagate] [--only-absorbing]
   --cpu-seconds 0 skips the oracle's full 100-step run of the headline grid (about 15 s on 16
   threads; the baseline and parity then use one step); --only-large times only the 2^28 solve,
-  --only-propagate only the 2^24-row fused propagation.
+  --only-propagate only the 2^24-row fused propagation, --only-absorbing only the 2^24-row
+  steps with an absorbing potential.
 """
 from __future__ import annotations
 
@@ -53,6 +54,8 @@ def parse():
                    help="time only the 2^28 explicit solve (automatic plan), for profiling")
     p.add_argument("--only-propagate", action="store_true",
                    help="time only the 2^24-row fused propagation, for profiling")
+    p.add_argument("--only-absorbing", action="store_true",
+                   help="time only the 2^24-row steps with an absorbing potential, for profiling")
     p.add_argument("--copy-ref", action="store_true",
                    help="first run a plain 256 MiB device copy three times (a reference of known "
                         "size for scaling hardware byte counters)")
@@ -141,6 +144,9 @@ def main():
         return
     if args.only_propagate:
         print(json.dumps(long_propagate(torch, np, cn, dev, parity=False)), flush=True)
+        return
+    if args.only_absorbing:
+        print(json.dumps(absorbing_large(torch, np, cn, workloads, dev)), flush=True)
         return
 
     # ---------------------------------------------------------------- headline: ADI 4096^2
@@ -620,6 +626,12 @@ def absorbing(torch, np, cn, workloads, dev):
     if "x" in ref:
         res["1d_65536"]["parity_rel_l2_200"] = rel_l2(psi200, ref["x"])
     del psi, psi0, V, W
+    res["2^24"] = absorbing_large(torch, np, cn, workloads, dev)
+    return res
+
+
+def absorbing_large(torch, np, cn, workloads, dev):
+    """2^24 rows with an absorbing ramp, 10 materialised steps per timed call."""
     n, steps = 1 << 24, 10
     g = np.random.default_rng(1010)
     Vb = torch.from_numpy(g.uniform(-1.0, 0.0, n)).to(dev)
@@ -630,10 +642,10 @@ def absorbing(torch, np, cn, workloads, dev):
     cn.propagate(pb, Vb, 0.01, 0.02, 1, W=Wb, layout=Lb)
     ts = timed_events(torch, lambda: cn.propagate(pb, Vb, 0.01, 0.02, steps, W=Wb, layout=Lb), 3)
     us = float(np.median(ts)) * 1e3 / steps
-    res["2^24"] = {"steps": steps, "us_per_step": us, "unknowns_per_s": n / (us * 1e-6),
-                   "GBps_192": 192.0 * n / (us * 1e-6) / 1e9,
-                   "frac_of_8TBps": 192.0 * n / (us * 1e-6) / 8e12}
-    return res
+    return {"steps": steps, "us_per_step": us, "unknowns_per_s": n / (us * 1e-6),
+            "GBps_192": 192.0 * n / (us * 1e-6) / 1e9,
+            "frac_of_8TBps": 192.0 * n / (us * 1e-6) / 8e12,
+            "plan": cn.describe_plan(Lb, False)}
 
 
 def differentiated(torch, np, workloads, dev):
