@@ -25,7 +25,8 @@
  *   CN_NUMERICAL_BREAKDOWN.  The library never aborts the process.
  * - Workspace: the handle owns a device workspace that grows on demand.  Inside HIP graph
  *   capture nothing may be allocated: call cn_reserve with the same layout first, else the
- *   call returns CN_ERR_NOT_RESERVED.
+ *   call returns CN_ERR_NOT_RESERVED.  Growing a workspace frees the old one, so a graph
+ *   captured earlier must not be replayed after a call on a larger layout.
  * - Threading: a handle is used by one host thread at a time.  Calls that overlap on
  *   different streams of one handle share its workspace and must not run concurrently.
  * - All arithmetic is FP64.  Results are deterministic: no floating-point atomics.
