@@ -391,3 +391,22 @@ def test_absorbing_loss_rate(oracle_mod):
         rate = (np.sum(np.abs(p1) ** 2) - np.sum(np.abs(psi0) ** 2)) / dt
         expect = -2 * np.sum(W * np.abs(psi0) ** 2)
         assert abs(rate - expect) <= 2 * dt * abs(expect)
+
+
+def test_absorbing_pin_rejects_t_dagger_right_side(oracle_mod):
+    """The plausible mistake of keeping T^dagger as the right side (1 + tau W - i tau H0) gives
+    a norm-preserving step; the amplification pin above tells it apart by far."""
+    N, dx, dt, V0, W0 = 257, 0.1, 0.02, -0.4, 1.5
+    j = np.arange(1, N + 1)
+    tau = dt / 2
+    k = 3
+    mode = np.sin(k * np.pi * j / (N + 1)).astype(np.complex128)
+    V, W = np.full(N, V0), np.full(N, W0)
+    a, b, c = oracle_mod.cn_coeffs(V, dx, dt, W=W)
+    wrong = oracle_mod.thomas(a, b, c, oracle_mod.cn_rhs(mode, V, dx, dt, W=-W))
+    right = oracle_mod.cn_step(mode, V, dx, dt, W=W)
+    lam = (1 - np.cos(k * np.pi / (N + 1))) / dx**2 + V0
+    g = (1 - tau * W0 - 1j * tau * lam) / (1 + tau * W0 + 1j * tau * lam)
+    assert rel(right, g * mode) <= 1e-13
+    assert rel(wrong, g * mode) > 1e-3
+    assert abs(np.linalg.norm(wrong) - np.linalg.norm(mode)) <= 1e-12 * np.linalg.norm(mode)
