@@ -25,8 +25,10 @@
  *   CN_NUMERICAL_BREAKDOWN.  The library never aborts the process.
  * - Workspace: the handle owns a device workspace that grows on demand.  Inside HIP graph
  *   capture nothing may be allocated: call cn_reserve with the same layout first, else the
- *   call returns CN_ERR_NOT_RESERVED.  Growing a workspace frees the old one, so a graph
- *   captured earlier must not be replayed after a call on a larger layout.
+ *   call returns CN_ERR_NOT_RESERVED.  Growing a workspace frees the old one only while no
+ *   call of the handle has been captured; after the first captured call, replaced buffers are
+ *   kept until cn_destroy, so every graph captured on the handle stays valid until then
+ *   (cn_handle_info reports how many are kept).
  * - Threading: a handle is used by one host thread at a time.  Calls that overlap on
  *   different streams of one handle share its workspace and must not run concurrently.
  * - All arithmetic is FP64.  Results are deterministic: no floating-point atomics.
@@ -216,6 +218,12 @@ cn_status cn_autotune(cn_handle_t handle, const cn_layout* layout, int cn_mode,
                       const cn_operator* op, double E, const void* a, const void* b,
                       const void* c, const void* d, void* x, char* report, int64_t report_len,
                       cn_stream_t stream);
+
+/* Device memory held by the handle (workspaces and plan tables, excluding retired buffers),
+ * the number of buffers retired after graph capture (freed by cn_destroy), and whether a call
+ * of the handle has been captured.  Each output pointer may be NULL.  Host only. */
+cn_status cn_handle_info(cn_handle_t handle, int64_t* device_bytes, int64_t* retired_buffers,
+                         int32_t* captured);
 
 /* Synchronises the stream, returns CN_NUMERICAL_BREAKDOWN if any kernel of this handle met a
  * non-finite result since the last call (and clears the flag), else CN_OK. */

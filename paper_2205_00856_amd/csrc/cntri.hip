@@ -15,104 +15,42 @@
 #include <vector>
 
 #include "../../include/cntri.h"
+#include "kern_table.hpp"
 #include "nshaped_kernels.hpp"
 
 using nsd::cd;
 using nsd::KArgs;
 
+// The kernel entry addresses, filled once (on first use) by the kern_*.hip units.
+nsk::Tables& nsk::tables() {
+  static Tables t = [] {
+    Tables x{};
+    reg_tile_expl(x);
+    reg_tile_ct(x);
+    reg_tile_cn_lo(x);
+    reg_tile_cn_hi(x);
+    reg_tile_slots(x);
+    reg_cols(x);
+    reg_pers(x);
+    reg_aux(x);
+    return x;
+  }();
+  return t;
+}
+
 namespace {
 
 // ----------------------------------------------------------------------- kernel table
-struct Cfg {
-  int M, W;
-  int64_t T() const { return 64LL * W * M; }
-};
-// (rows per lane, wavefronts per workgroup); tile T = 64 W M rows
-constexpr Cfg kCfgs[] = {{2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 1},
-                         {8, 2}, {8, 4}, {8, 8}, {2, 2}, {2, 4}, {16, 4}, {16, 2}};
-constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
+using nsk::Cfg;
+using nsk::kCfgs;
+using nsk::kColCfgs;
+using nsk::kNumCfg;
+using nsk::kNumColCfg;
 
-typedef void (*KFn)(KArgs);
-const void* g_kern[kNumCfg][4][4];
-
-template <int M, int W, int SRC>
-void reg_src(int ci) {
-  g_kern[ci][SRC][nsd::PH_SINGLE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_SINGLE>;
-  g_kern[ci][SRC][nsd::PH_REDUCE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_REDUCE>;
-  g_kern[ci][SRC][nsd::PH_SUBST] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_SUBST>;
-  if constexpr (SRC == nsd::SRC_CN)
-    g_kern[ci][SRC][nsd::PH_FUSE] = (const void*)&nsd::k_tile<M, W, SRC, nsd::PH_FUSE>;
-}
-template <int M, int W>
-void reg_cfg(int ci) {
-  reg_src<M, W, nsd::SRC_EXPL>(ci);
-  reg_src<M, W, nsd::SRC_EXPL_CT>(ci);
-  reg_src<M, W, nsd::SRC_CN>(ci);
-  reg_src<M, W, nsd::SRC_SLOTS>(ci);
-}
-struct KernTableInit {
-  KernTableInit() {
-    reg_cfg<2, 1>(0);
-    reg_cfg<4, 1>(1);
-    reg_cfg<4, 2>(2);
-    reg_cfg<4, 4>(3);
-    reg_cfg<4, 8>(4);
-    reg_cfg<4, 16>(5);
-    reg_cfg<8, 1>(6);
-    reg_cfg<8, 2>(7);
-    reg_cfg<8, 4>(8);
-    reg_cfg<8, 8>(9);
-    reg_cfg<2, 2>(10);
-    reg_cfg<2, 4>(11);
-    reg_cfg<16, 4>(12);
-    reg_cfg<16, 2>(13);
-  }
-} g_kern_init;
-
-// persistent whole-system kernels (uneven batches)
-const void* g_pers[kNumCfg][3];
-template <int M, int W>
-void reg_pers(int ci) {
-  g_pers[ci][nsd::SRC_EXPL] = (const void*)&nsd::k_system<M, W, nsd::SRC_EXPL>;
-  g_pers[ci][nsd::SRC_EXPL_CT] = (const void*)&nsd::k_system<M, W, nsd::SRC_EXPL_CT>;
-  g_pers[ci][nsd::SRC_CN] = (const void*)&nsd::k_system<M, W, nsd::SRC_CN>;
-}
-struct PersTableInit {
-  PersTableInit() {
-    reg_pers<4, 2>(2);
-    reg_pers<4, 4>(3);
-    reg_pers<4, 8>(4);
-    reg_pers<8, 2>(7);
-    reg_pers<8, 4>(8);
-  }
-} g_pers_init;
-
-// column kernels for interleaved batches (lanes across neighbouring systems); tile T = W*M
-constexpr Cfg kColCfgs[] = {{4, 8}, {8, 4}, {8, 8}, {4, 16}, {16, 4}, {8, 16}};
-constexpr int kNumColCfg = sizeof(kColCfgs) / sizeof(kColCfgs[0]);
-const void* g_cols[kNumColCfg][4][3];
-template <int M, int W, int SRC>
-void reg_col_src(int ci) {
-  g_cols[ci][SRC][nsd::PH_SINGLE] = (const void*)&nsd::k_cols<M, W, SRC, nsd::PH_SINGLE>;
-  g_cols[ci][SRC][nsd::PH_REDUCE] = (const void*)&nsd::k_cols<M, W, SRC, nsd::PH_REDUCE>;
-  g_cols[ci][SRC][nsd::PH_SUBST] = (const void*)&nsd::k_cols<M, W, SRC, nsd::PH_SUBST>;
-}
-template <int M, int W>
-void reg_col(int ci) {
-  reg_col_src<M, W, nsd::SRC_EXPL>(ci);
-  reg_col_src<M, W, nsd::SRC_EXPL_CT>(ci);
-  reg_col_src<M, W, nsd::SRC_CN>(ci);
-}
-struct ColTableInit {
-  ColTableInit() {
-    reg_col<4, 8>(0);
-    reg_col<8, 4>(1);
-    reg_col<8, 8>(2);
-    reg_col<4, 16>(3);
-    reg_col<16, 4>(4);
-    reg_col<8, 16>(5);
-  }
-} g_col_init;
+const void* const (&g_kern)[kNumCfg][nsk::kNumSrc][nsk::kNumPh] = nsk::tables().tile;
+const void* const (&g_pers)[kNumCfg][nsk::kNumSrc] = nsk::tables().pers;
+const void* const (&g_cols)[kNumColCfg][nsk::kNumSrc][3] = nsk::tables().cols;
+const void* aux_fn(int k) { return nsk::tables().aux[k]; }
 
 int col_cfg(int64_t T, int M) {
   for (int i = 0; i < kNumColCfg; ++i)
@@ -611,6 +549,11 @@ struct cn_handle_s {
   // materialised a, b, c, d of steps with an absorbing potential
   void* mat = nullptr;
   size_t mat_size = 0;
+  // Once a call of this handle has been captured into a HIP graph, the graph holds the device
+  // addresses of the handle's buffers: a buffer replaced by a larger one is then kept here
+  // until cn_destroy instead of being freed.
+  bool captured = false;
+  std::vector<void*> retired;
 };
 
 namespace {
@@ -624,6 +567,28 @@ bool capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
   return st != hipStreamCaptureStatusNone;
+}
+
+// Replaces handle buffer *p (size *bytes) by a new allocation of `need` bytes.  The old buffer
+// is freed (after the device is idle) unless a graph captured on this handle may still use it;
+// then it is retired until cn_destroy.  Never called during capture.
+cn_status regrow(cn_handle_t h, void** p, size_t* bytes, size_t need) {
+  if (*p) {
+    if (h->captured) {
+      h->retired.push_back(*p);
+    } else {
+      if (hipDeviceSynchronize() != hipSuccess) return CN_ERR_HIP;
+      (void)hipFree(*p);
+    }
+  }
+  *p = nullptr;
+  *bytes = 0;
+  if (hipMalloc(p, need) != hipSuccess) {
+    *p = nullptr;
+    return CN_ERR_NO_MEMORY;
+  }
+  *bytes = need;
+  return CN_OK;
 }
 
 cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
@@ -672,6 +637,68 @@ std::string plan_key(const cn_layout* L, int src) {
   return k;
 }
 
+// Builds the launches of a plan for this layout on the host (no device access).  tab receives
+// the plan's device tables (offsets, launch lists, queue counters); adjoint_ws adds the
+// workspace of cn_step_adjoint (Crank-Nicolson plans).
+cn_status build_plan(const cn_layout* L, int src, bool adjoint_ws, Plan& P,
+                     std::vector<char>& tab) {
+  int64_t rows = 0, span = 0;
+  cn_status st = validate(L, rows, span);
+  if (st != CN_OK) return st;
+  Builder B;
+  BatchDesc bd;
+  if (L->offsets) {
+    bd.uneven = true;
+    bd.batch = L->batch;
+    bd.offs.assign(L->offsets, L->offsets + L->batch + 1);
+  } else {
+    bd.n = L->n;
+    bd.batch = L->batch;
+    bd.es = L->elem_stride;
+    bd.bs = L->batch_stride;
+  }
+  Knobs kn;
+  kn.partition = L->partition;
+  kn.rpt = L->rows_per_thread;
+  kn.shared = L->shared_coefficients;
+  if (kn.partition > 0) {
+    const bool columns = !L->offsets && L->batch_stride == 1 && L->batch >= 64 &&
+                         L->elem_stride >= L->batch && cols_enabled() &&
+                         !L->shared_coefficients;
+    const int M = kn.rpt > 0 ? kn.rpt : (kn.partition >= 512 ? 8 : 4);
+    const bool rows_ok = find_cfg(kn.partition, M) >= 0 || find_cfg(kn.partition, 4) >= 0 ||
+                         find_cfg(kn.partition, 8) >= 0 || find_cfg(kn.partition, 2) >= 0;
+    const bool cols_ok = col_cfg(kn.partition, kn.rpt) >= 0;
+    if (columns ? !cols_ok : !rows_ok) return CN_ERR_UNSUPPORTED;
+  }
+  plan_level(B, P.L, bd, src, 1, -1, -1, -1, kn);
+  P.span = span;
+  P.rows = rows;
+  if (src == nsd::SRC_CN && adjoint_ws) {
+    P.o_aux = B.add_ws(rows * sizeof(cd) + 16);
+    P.nparts = (rows + 255) / 256;
+    P.o_part = B.add_ws((rows / 64 + 64) * sizeof(double));
+    for (const Launch& l : P.L)
+      if (l.level == 1 && (l.ph == nsd::PH_SINGLE || l.ph == nsd::PH_SUBST))
+        P.ntiles1 = l.a.nitems > 0 ? (int64_t)l.a.nitems : (int64_t)l.grid.x * l.grid.y;
+  }
+  P.ws_bytes = B.ws;
+  P.desc = B.desc;
+  tab.swap(B.tab);
+  return CN_OK;
+}
+
+// Points the launches of a plan at its tables, stored at device address tb.
+void bind_tables(Plan& P, char* tb) {
+  for (Launch& l : P.L) {
+    if (l.t_offs >= 0) l.a.offs = (const int64_t*)(tb + l.t_offs);
+    if (l.t_tbase >= 0) l.a.tbase = (const int64_t*)(tb + l.t_tbase);
+    if (l.t_wgs >= 0) l.a.wg_sys = (const int*)(tb + l.t_wgs);
+    if (l.t_wgt >= 0) l.a.wg_tile = (const int*)(tb + l.t_wgt);
+    if (l.t_queue >= 0) l.a.queue = (int*)(tb + l.t_queue);
+  }
+}
+
 cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Plan** out) {
   int64_t rows = 0, span = 0;
   cn_status st = validate(L, rows, span);
@@ -683,75 +710,27 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
   }
   auto it = h->plans.find(key);
   const bool cap = s != nullptr ? capturing(s) : false;
+  if (cap) h->captured = true;
   if (it == h->plans.end()) {
     if (cap) return CN_ERR_NOT_RESERVED;
     std::unique_ptr<Plan> P(new Plan());
-    Builder B;
-    BatchDesc bd;
-    if (L->offsets) {
-      bd.uneven = true;
-      bd.batch = L->batch;
-      bd.offs.assign(L->offsets, L->offsets + L->batch + 1);
-    } else {
-      bd.n = L->n;
-      bd.batch = L->batch;
-      bd.es = L->elem_stride;
-      bd.bs = L->batch_stride;
-    }
-    Knobs kn;
-    kn.partition = L->partition;
-    kn.rpt = L->rows_per_thread;
-    kn.shared = L->shared_coefficients;
-    if (kn.partition > 0) {
-      const bool columns = !L->offsets && L->batch_stride == 1 && L->batch >= 64 &&
-                           L->elem_stride >= L->batch && cols_enabled() &&
-                           !L->shared_coefficients;
-      const int M = kn.rpt > 0 ? kn.rpt : (kn.partition >= 512 ? 8 : 4);
-      const bool rows_ok = find_cfg(kn.partition, M) >= 0 || find_cfg(kn.partition, 4) >= 0 ||
-                           find_cfg(kn.partition, 8) >= 0 || find_cfg(kn.partition, 2) >= 0;
-      const bool cols_ok = col_cfg(kn.partition, kn.rpt) >= 0;
-      if (columns ? !cols_ok : !rows_ok) return CN_ERR_UNSUPPORTED;
-    }
-    plan_level(B, P->L, bd, src, 1, -1, -1, -1, kn);
-    P->span = span;
-    P->rows = rows;
-    if (src == nsd::SRC_CN) {
-      P->o_aux = B.add_ws(rows * sizeof(cd) + 16);
-      P->nparts = (rows + 255) / 256;
-      P->o_part = B.add_ws((rows / 64 + 64) * sizeof(double));
-      for (const Launch& l : P->L)
-        if (l.level == 1 && (l.ph == nsd::PH_SINGLE || l.ph == nsd::PH_SUBST))
-          P->ntiles1 = l.a.nitems > 0 ? (int64_t)l.a.nitems : (int64_t)l.grid.x * l.grid.y;
-    }
-    P->ws_bytes = B.ws;
-    P->desc = B.desc;
-    if (!B.tab.empty()) {
-      if (hipMalloc(&P->tables, B.tab.size()) != hipSuccess) return CN_ERR_NO_MEMORY;
-      if (hipMemcpy(P->tables, B.tab.data(), B.tab.size(), hipMemcpyHostToDevice) != hipSuccess)
+    std::vector<char> tab;
+    st = build_plan(L, src, true, *P, tab);
+    if (st != CN_OK) return st;
+    if (!tab.empty()) {
+      if (hipMalloc(&P->tables, tab.size()) != hipSuccess) return CN_ERR_NO_MEMORY;
+      if (hipMemcpy(P->tables, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess)
         return CN_ERR_HIP;
-      P->tables_bytes = B.tab.size();
+      P->tables_bytes = tab.size();
     }
-    char* tb = (char*)P->tables;
-    for (Launch& l : P->L) {
-      if (l.t_offs >= 0) l.a.offs = (const int64_t*)(tb + l.t_offs);
-      if (l.t_tbase >= 0) l.a.tbase = (const int64_t*)(tb + l.t_tbase);
-      if (l.t_wgs >= 0) l.a.wg_sys = (const int*)(tb + l.t_wgs);
-      if (l.t_wgt >= 0) l.a.wg_tile = (const int*)(tb + l.t_wgt);
-      if (l.t_queue >= 0) l.a.queue = (int*)(tb + l.t_queue);
-    }
+    bind_tables(*P, (char*)P->tables);
     it = h->plans.emplace(key, std::move(P)).first;
   }
   Plan* P = it->second.get();
   if (P->ws_bytes > h->ws_size) {
     if (cap) return CN_ERR_NOT_RESERVED;
-    if (h->ws) {
-      if (hipDeviceSynchronize() != hipSuccess) return CN_ERR_HIP;
-      (void)hipFree(h->ws);
-      h->ws = nullptr;
-      h->ws_size = 0;
-    }
-    if (hipMalloc(&h->ws, P->ws_bytes) != hipSuccess) return CN_ERR_NO_MEMORY;
-    h->ws_size = P->ws_bytes;
+    const cn_status st2 = regrow(h, &h->ws, &h->ws_size, P->ws_bytes);
+    if (st2 != CN_OK) return st2;
   }
   *out = P;
   return CN_OK;
@@ -967,6 +946,16 @@ cn_status launch_aux(const void* fn, int64_t rows, nsd::AuxArgs& x, hipStream_t 
   return CN_OK;
 }
 
+// out[r] = sum of row r of part (rows of nparts values), r < rows, in a fixed order
+cn_status launch_sum_partials(const double* part, int64_t nparts, double* out, int64_t rows,
+                              hipStream_t s) {
+  void* params[] = {&part, &nparts, &out};
+  if (hipLaunchKernel(aux_fn(nsk::AUX_SUM_PARTIALS), dim3((unsigned)rows), dim3(256), params, 0,
+                      s) != hipSuccess)
+    return CN_ERR_HIP;
+  return CN_OK;
+}
+
 cn_status check_op(const cn_operator* op) {
   if (!op || !op->V) return CN_ERR_INVALID_ARG;
   if (!op->dx_per_system && !(op->dx > 0.0)) return CN_ERR_INVALID_ARG;
@@ -1006,12 +995,8 @@ cn_status absorbing_step(cn_handle_t h, const cn_layout* L, const cn_operator* o
   const size_t need = 4 * (size_t)sp * sizeof(cd);
   if (h->mat_size < need) {
     if (capturing(s)) return CN_ERR_NOT_RESERVED;
-    HIP_TRY(hipDeviceSynchronize());
-    if (h->mat) (void)hipFree(h->mat);
-    h->mat = nullptr;
-    h->mat_size = 0;
-    if (hipMalloc(&h->mat, need) != hipSuccess) return CN_ERR_NO_MEMORY;
-    h->mat_size = need;
+    st = regrow(h, &h->mat, &h->mat_size, need);
+    if (st != CN_OK) return st;
     coeffs = true;
   }
   cd* m = (cd*)h->mat;
@@ -1020,12 +1005,12 @@ cn_status absorbing_step(cn_handle_t h, const cn_layout* L, const cn_operator* o
     X.a = m;
     X.b = m + sp;
     X.c = m + 2 * sp;
-    st = launch_aux((const void*)&nsd::k_assemble, P->rows, X, s);
+    st = launch_aux(aux_fn(nsk::AUX_ASSEMBLE), P->rows, X, s);
     if (st != CN_OK) return st;
   }
   X.psi = psi_in;
   X.d = m + 3 * sp;
-  st = launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
+  st = launch_aux(aux_fn(nsk::AUX_RHS), P->rows, X, s);
   if (st != CN_OK) return st;
   UserArgs u;
   u.a = m;
@@ -1091,6 +1076,7 @@ cn_status cn_destroy(cn_handle_t h) {
   if (h->ws2) (void)hipFree(h->ws2);
   if (h->seg2) (void)hipFree(h->seg2);
   if (h->mat) (void)hipFree(h->mat);
+  for (void* p : h->retired) (void)hipFree(p);
   for (hipEvent_t e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -1107,14 +1093,7 @@ cn_status cn_reserve(cn_handle_t h, const cn_layout* L) {
     if (st != CN_OK) return st;
   }
   // the second workspace of the reverse mode's fused chain (P is the Crank-Nicolson plan)
-  if (h->ws2_size < P->ws_bytes) {
-    HIP_TRY(hipDeviceSynchronize());
-    if (h->ws2) (void)hipFree(h->ws2);
-    h->ws2 = nullptr;
-    h->ws2_size = 0;
-    if (hipMalloc(&h->ws2, P->ws_bytes) != hipSuccess) return CN_ERR_NO_MEMORY;
-    h->ws2_size = P->ws_bytes;
-  }
+  if (h->ws2_size < P->ws_bytes) return regrow(h, &h->ws2, &h->ws2_size, P->ws_bytes);
   return CN_OK;
 }
 
@@ -1170,7 +1149,7 @@ cn_status cn_tridiag_solve_adjoint(cn_handle_t h, const cn_layout* L, const void
     X.ga = (cd*)ga;
     X.gb = (cd*)gb;
     X.gc = (cd*)gc;
-    st = launch_aux((const void*)&nsd::k_solve_grads, P->rows, X, s);
+    st = launch_aux(aux_fn(nsk::AUX_SOLVE_GRADS), P->rows, X, s);
   }
   return st;
 }
@@ -1189,7 +1168,7 @@ cn_status cn_assemble(cn_handle_t h, const cn_layout* L, const cn_operator* op, 
   X.a = (cd*)a;
   X.b = (cd*)b;
   X.c = (cd*)c;
-  return launch_aux((const void*)&nsd::k_assemble, P->rows, X, s);
+  return launch_aux(aux_fn(nsk::AUX_ASSEMBLE), P->rows, X, s);
 }
 
 cn_status cn_rhs(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E,
@@ -1205,7 +1184,7 @@ cn_status cn_rhs(cn_handle_t h, const cn_layout* L, const cn_operator* op, doubl
   nsd::AuxArgs X = aux_op(L, P, op, E);
   X.psi = (const cd*)psi;
   X.d = (cd*)d;
-  return launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
+  return launch_aux(aux_fn(nsk::AUX_RHS), P->rows, X, s);
 }
 
 cn_status cn_step(cn_handle_t h, const cn_layout* L, const cn_operator* op, double E,
@@ -1333,7 +1312,7 @@ cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* 
   X.dt = -op->dt;
   X.psi = lam;
   X.d = (cd*)g_n;
-  st = launch_aux((const void*)&nsd::k_rhs, P->rows, X, s);
+  st = launch_aux(aux_fn(nsk::AUX_RHS), P->rows, X, s);
   if (st != CN_OK) return st;
   // gradient terms
   nsd::AuxArgs Y = aux_from(L, P);
@@ -1347,12 +1326,11 @@ cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* 
   Y.dV = dV_accum;
   double* part = (double*)((char*)h->ws + P->o_part);
   Y.dE_part = dE_partial ? part : nullptr;
-  st = launch_aux((const void*)&nsd::k_adj_accum, P->rows, Y, s);
+  st = launch_aux(aux_fn(nsk::AUX_ADJ_ACCUM), P->rows, Y, s);
   if (st != CN_OK) return st;
   if (dE_partial) {
-    hipLaunchKernelGGL(nsd::k_sum_partials, dim3(1), dim3(256), 0, s, (const double*)part,
-                       (int64_t)((P->rows + 255) / 256), dE_partial);
-    if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
+    st = launch_sum_partials(part, (int64_t)((P->rows + 255) / 256), dE_partial, 1, s);
+    if (st != CN_OK) return st;
   }
   return CN_OK;
 }
@@ -1464,14 +1442,12 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
     const size_t need = (size_t)std::min<int64_t>(K, nsteps) * (size_t)P->ntiles1;
     if (h->rows_cap < need) {
       if (capturing(s)) return CN_ERR_NOT_RESERVED;
-      if (h->rows_buf) {
-        if (hipDeviceSynchronize() != hipSuccess) return CN_ERR_HIP;
-        (void)hipFree(h->rows_buf);
-        h->rows_buf = nullptr;
-        h->rows_cap = 0;
-      }
-      if (hipMalloc(&h->rows_buf, need * sizeof(double)) != hipSuccess) return CN_ERR_NO_MEMORY;
-      h->rows_cap = need;
+      size_t bytes = h->rows_cap * sizeof(double);
+      void* p = h->rows_buf;
+      st = regrow(h, &p, &bytes, need * sizeof(double));
+      h->rows_buf = (double*)p;
+      h->rows_cap = bytes / sizeof(double);
+      if (st != CN_OK) return st;
     }
     part = h->rows_buf;
   }
@@ -1525,22 +1501,13 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   const bool overlap = nseg >= 2 && !cap && bwd_overlap_enabled();
   if (!cap) {
     const size_t sb = overlap ? (size_t)(std::min(K, nsteps) + 1) * (size_t)span * sizeof(cd) : 0;
-    if (h->ws2_size < P->ws_bytes || h->seg2_bytes < sb) {
-      HIP_TRY(hipDeviceSynchronize());
-      if (h->ws2_size < P->ws_bytes) {
-        if (h->ws2) (void)hipFree(h->ws2);
-        h->ws2 = nullptr;
-        h->ws2_size = 0;
-        if (hipMalloc(&h->ws2, P->ws_bytes) != hipSuccess) return CN_ERR_NO_MEMORY;
-        h->ws2_size = P->ws_bytes;
-      }
-      if (h->seg2_bytes < sb) {
-        if (h->seg2) (void)hipFree(h->seg2);
-        h->seg2 = nullptr;
-        h->seg2_bytes = 0;
-        if (hipMalloc(&h->seg2, sb) != hipSuccess) return CN_ERR_NO_MEMORY;
-        h->seg2_bytes = sb;
-      }
+    if (h->ws2_size < P->ws_bytes) {
+      st = regrow(h, &h->ws2, &h->ws2_size, P->ws_bytes);
+      if (st != CN_OK) return st;
+    }
+    if (h->seg2_bytes < sb) {
+      st = regrow(h, &h->seg2, &h->seg2_bytes, sb);
+      if (st != CN_OK) return st;
     }
     if (overlap && !h->aux) {
       HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
@@ -1607,9 +1574,8 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
     const int64_t k = nsteps - 1 - i, sg = k / K, k0 = k0_of(sg);
     if (k != k0) return CN_OK;
     if (dE) {
-      hipLaunchKernelGGL(nsd::k_sum_partials, dim3((unsigned)(k1_of(sg) - k0)), dim3(256), 0, s,
-                         (const double*)part, P->ntiles1, dE + k0);
-      if (hipGetLastError() != hipSuccess) return CN_ERR_HIP;
+      const cn_status r = launch_sum_partials(part, P->ntiles1, dE + k0, k1_of(sg) - k0, s);
+      if (r != CN_OK) return r;
     }
     if (overlap) HIP_TRY(hipEventRecord(adj_done[(nseg - 1 - sg) & 1], s));
     return CN_OK;
@@ -1627,6 +1593,20 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
     if ((st = run_plan(h, P, args(i), s)) != CN_OK) return st;
     if ((st = after(i)) != CN_OK) return st;
   }
+  return CN_OK;
+}
+
+cn_status cn_handle_info(cn_handle_t h, int64_t* device_bytes, int64_t* retired_buffers,
+                         int32_t* captured) {
+  if (!h) return CN_ERR_INVALID_ARG;
+  if (device_bytes) {
+    size_t b = h->ws_size + h->ws2_size + h->seg2_bytes + h->mat_size +
+               h->rows_cap * sizeof(double);
+    for (const auto& kv : h->plans) b += kv.second->tables_bytes;
+    *device_bytes = (int64_t)b;
+  }
+  if (retired_buffers) *retired_buffers = (int64_t)h->retired.size();
+  if (captured) *captured = h->captured ? 1 : 0;
   return CN_OK;
 }
 

@@ -1,0 +1,129 @@
+// Auxiliary kernels: materialised coefficient assembly and explicit half-step, the gradients
+// of a solve, the adjoint accumulation of a Crank-Nicolson step and fixed-order partial sums.
+#include "kern_table.hpp"
+#include "nshaped_kernels.hpp"
+
+namespace nsd {
+
+// Locate (system, row, element) of flat index t.
+__device__ __forceinline__ bool locate(const AuxArgs& A, int64_t t, int64_t& sys, int64_t& r,
+                                       int64_t& n, int64_t& e) {
+  if (A.offs) {
+    if (t >= A.total) return false;
+    int64_t lo = 0, hi = A.batch;  // find sys with offs[sys] <= t < offs[sys+1]
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (A.offs[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    sys = lo;
+    r = t - A.offs[sys];
+    n = A.offs[sys + 1] - A.offs[sys];
+    e = t;
+  } else {
+    if (t >= A.n * A.batch) return false;
+    sys = t / A.n;
+    r = t - sys * A.n;
+    n = A.n;
+    e = sys * A.bs + r * A.es;
+  }
+  return true;
+}
+
+// a1: coefficients of T = 1 + i tau H
+__global__ void k_assemble(AuxArgs A) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  if (!locate(A, t, sys, r, n, e)) return;
+  const double dx = A.dxs ? A.dxs[sys] : A.dx;
+  const double tau = 0.5 * A.dt, idx2 = 1.0 / (dx * dx), kap = tau * 0.5 * idx2;
+  const double v = A.vscale * A.V[e] + (A.xg ? A.xg[e] * A.E : 0.0);
+  // with the absorbing term -iW in H the diagonal of 1 + i tau H gains + tau W
+  A.a[e] = mk(A.W ? fma(tau, A.W[e], 1.0) : 1.0, tau * (idx2 + v));
+  A.b[e] = mk(0.0, (r > 0) ? -kap : 0.0);
+  A.c[e] = mk(0.0, (r < n - 1) ? -kap : 0.0);
+}
+
+// a2: d = (1 - i tau H) psi
+__global__ void k_rhs(AuxArgs A) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  if (!locate(A, t, sys, r, n, e)) return;
+  const int64_t st = A.offs ? 1 : A.es;
+  const double dx = A.dxs ? A.dxs[sys] : A.dx;
+  const double tau = 0.5 * A.dt, idx2 = 1.0 / (dx * dx), kap = tau * 0.5 * idx2;
+  const double w = tau * (idx2 + A.vscale * A.V[e] + (A.xg ? A.xg[e] * A.E : 0.0));
+  const cd p = A.psi[e];
+  const cd l = csel(r > 0, A.psi[(r > 0) ? e - st : e], czero());
+  const cd h = csel(r < n - 1, A.psi[(r < n - 1) ? e + st : e], czero());
+  const cd s = cadd(l, h);
+  // the diagonal of 1 - i tau H is 1 - tau W - i w (with the absorbing term, not T^dagger's)
+  const double f = A.W ? fma(-tau, A.W[e], 1.0) : 1.0;
+  const cd q = A.W ? mk(f * p.x, f * p.y) : p;
+  A.d[e] = mk(fma(w, p.y, fma(-kap, s.y, q.x)), fma(-w, p.x, fma(kap, s.x, q.y)));
+}
+
+// gradients of the solve: ga_i = -lam_i conj(x_i), gb_i = -lam_i conj(x_{i-1}), gc_i = ...
+__global__ void k_solve_grads(AuxArgs A) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  if (!locate(A, t, sys, r, n, e)) return;
+  const int64_t st = A.offs ? 1 : A.es;
+  const cd l = A.lam[e];
+  if (A.ga) A.ga[e] = cneg(cmul(l, cconj(A.xsol[e])));
+  if (A.gb) A.gb[e] = csel(r > 0, cneg(cmul(l, cconj(A.xsol[(r > 0) ? e - st : e]))), czero());
+  if (A.gc) A.gc[e] = csel(r < n - 1, cneg(cmul(l, cconj(A.xsol[(r < n - 1) ? e + st : e]))), czero());
+}
+
+// adjoint accumulation: q_j = tau Im(conj(lam_j)(psi_n,j + psi_np1,j));
+// dV_j += vscale q_j; per-block partial sums of x_j q_j (summed in a fixed order).
+__global__ __launch_bounds__(256) void k_adj_accum(AuxArgs A) {
+  __shared__ double red[256];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sys, r, n, e;
+  double part = 0.0;
+  if (locate(A, t, sys, r, n, e)) {
+    const double tau = 0.5 * A.dt;
+    const cd l = A.lam[e];
+    const cd s = cadd(A.psi_n[e], A.psi_np1[e]);
+    const double q = tau * (l.x * s.y - l.y * s.x);
+    if (A.dV) A.dV[e] += A.vscale * q;
+    if (A.xg) part = A.xg[e] * q;
+  }
+  if (!A.dE_part) return;
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A.dE_part[blockIdx.x] = red[0];
+}
+
+// deterministic second stage: workgroup r sets out[r] = sum of the nparts partials in row r of
+// part (rows of nparts values), in a fixed order
+__global__ __launch_bounds__(256) void k_sum_partials(const double* part, int64_t nparts,
+                                                      double* out) {
+  __shared__ double red[256];
+  part += (int64_t)blockIdx.x * nparts;
+  out += blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace nsd
+
+namespace nsk {
+void reg_aux(Tables& t) {
+  t.aux[AUX_ASSEMBLE] = (const void*)&nsd::k_assemble;
+  t.aux[AUX_RHS] = (const void*)&nsd::k_rhs;
+  t.aux[AUX_SOLVE_GRADS] = (const void*)&nsd::k_solve_grads;
+  t.aux[AUX_ADJ_ACCUM] = (const void*)&nsd::k_adj_accum;
+  t.aux[AUX_SUM_PARTIALS] = (const void*)&nsd::k_sum_partials;
+}
+}  // namespace nsk

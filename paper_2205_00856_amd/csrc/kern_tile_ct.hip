@@ -1,0 +1,23 @@
+// Row-tile kernels (k_tile) of the adjoint solve (conjugate-transposed matrix): every tile configuration.
+#include "kern_table.hpp"
+#include "nshaped_kernels.hpp"
+
+namespace nsk {
+namespace {
+template <int I>
+void reg_one(Tables& t) {
+  constexpr int M = kCfgs[I].M, W = kCfgs[I].W;
+  constexpr int S = nsd::SRC_EXPL_CT;
+  t.tile[I][S][nsd::PH_SINGLE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_SINGLE>;
+  t.tile[I][S][nsd::PH_REDUCE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_REDUCE>;
+  t.tile[I][S][nsd::PH_SUBST] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_SUBST>;
+}
+template <int... I>
+void reg_range(Tables& t, std::integer_sequence<int, I...>) {
+  (reg_one<I + 0>(t), ...);
+}
+}  // namespace
+
+void reg_tile_ct(Tables& t) { reg_range(t, std::make_integer_sequence<int, kNumCfg - 0>{}); }
+
+}  // namespace nsk
