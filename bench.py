@@ -140,7 +140,8 @@ def main():
         del src, dst
 
     if args.only_large:
-        print(json.dumps(large_system(torch, np, cn, dev, sweep=False)), flush=True)
+        print(json.dumps(large_system(torch, np, cn, dev, sweep=False, oracle_parity=False)),
+              flush=True)
         return
     if args.only_propagate:
         print(json.dumps(long_propagate(torch, np, cn, dev, parity=False)), flush=True)
@@ -224,10 +225,16 @@ def main():
     value = unknowns_per_step * args.steps / (total_ms * 1e-3)
     norm = float(torch.sum(torch.abs(psi) ** 2).item() * w["dx"] * w["dy"])
     # dominant kernel: the x-sweep (one launch of the fused CN-step tile kernel), timed with
-    # events around each of its launches on the stream it runs on, over the same number of ADI
-    # steps run eagerly right after the timed replays (each x-sweep followed by its y-sweep, as
-    # in the graph: back to back the x-sweeps alone run into the power limit)
+    # events around each of its launches on the stream it runs on, over --steps ADI steps run
+    # eagerly behind a backlog of graph replays: the host enqueues the events and launches while
+    # the replays run, so no host launch gap falls inside a bracket, and each x-sweep sits
+    # between two y-sweeps as in the graph (back to back the x-sweeps alone run into the power
+    # limit).  The rocprofv3 kernel trace of the same command gives the same mean within a few
+    # per cent.
+    launch_src = "events around each eager x-sweep launch, behind a backlog of graph replays"
     stream = torch.cuda.current_stream()
+    for _ in range(10):
+        graph.replay()  # backlog: the host enqueues the eager launches while these run
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     for e0, e1 in ev:
@@ -274,6 +281,8 @@ def main():
                       "+ N-shaped solve of 4096 lines of 4096)",
             "algorithmic_bytes_per_launch": algo_bytes,
             "launch_ms": launch_ms,
+            "launch_ms_source": launch_src,
+            "launch_ms_median": float(np.median(x_ms)),
         },
         "cpu_baseline": cpu_baseline,
         "parity_rel_l2_first_step": parity,
@@ -284,57 +293,94 @@ def main():
     }
 
     if not args.no_extra:
-        result["extra"] = extras(torch, np, cn, workloads, dev)
+        ex = extras(torch, np, cn, workloads, dev)
+        result["extra"] = ex
+
+        def get(leg, key):
+            v = ex.get(leg, {})
+            return v.get(key) if isinstance(v, dict) else None
+
+        # relative L2 against the oracle of each workload's whole run, at its full size
+        result["parity_full_size"] = {
+            "plain_1d_solve": get("plain_1d", "parity_rel_l2_solve"),
+            "plain_1d_psi_200": get("plain_1d", "parity_rel_l2_200"),
+            "adi_2d_psi_100": parity_full,
+            "large_system_2^28_x": get("large_system_2^28", "parity_rel_l2"),
+            "uneven_batch_psi_50": get("uneven_batch", "parity_rel_l2_50_steps"),
+            "differentiated_psi_2000": get("differentiated", "parity_rel_l2_psi_T"),
+            "differentiated_loss": get("differentiated", "parity_rel_loss"),
+            "differentiated_fd_64": get("differentiated", "fd_rel_l2_64"),
+        }
     print(json.dumps(result), flush=True)
 
 
-def large_system(torch, np, cn, dev, sweep=True):
-    """The 2^28-unknown explicit solve (a, b, c from the config-0 stencil with dx = 0.01,
-    dt = 0.02, V ~ U(-1, 0); d complex normal, drawn with torch's seeded device generator),
-    timed with the automatic plan and over the partition sweep."""
-    N = 1 << 28
-    g = torch.Generator(device=dev)
-    g.manual_seed(1002)
-    V = torch.rand(N, dtype=torch.float64, device=dev, generator=g) - 1.0
-    a, b, c = cn.assemble(V, 0.01, 0.02)
+def large_system(torch, np, cn, dev, sweep=True, oracle_parity=True):
+    """The 2^28-unknown explicit solve on the seeded workload (workloads.large_system: V_j ~
+    U(-1, 0) on dx = 0.01, dt = 0.02, then d complex normal; a, b, c assembled on the GPU),
+    timed with the automatic plan and over the partition sweep; the oracle's serial Thomas solve
+    of the same arrays gives the parity of the automatic plan's x and is the CPU baseline."""
+    import workloads
+
+    w = workloads.large_system()
+    N = w["n"]
+    sha = workloads.digest(w["V"], w["d"])
+    V = torch.from_numpy(w["V"]).to(dev)
+    a, b, c = cn.assemble(V, w["dx"], w["dt"])
     del V
-    d = torch.empty(N, dtype=torch.complex128, device=dev)
-    d.real.normal_(generator=g)
-    d.imag.normal_(generator=g)
+    d = torch.from_numpy(w["d"]).to(dev)
     x = torch.empty_like(d)
     rows = []
     parts = (0, 128, 256, 512, 1024, 2048, 4096) if sweep else (0,)
+    x_auto = None
     for T in parts:
         M = 2 if T == 128 else (0 if T == 0 else 4)
         L = cn.Layout.contiguous(N, 1, partition=T, rows_per_thread=M)
         cn.solve(a, b, c, d, out=x, layout=L)
+        if T == 0:
+            x_auto = x.cpu().numpy()
         ts = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), 10)
         med = float(np.median(ts))
         rows.append({"partition": T, "rows_per_thread": M, "ms_median": med,
                      "ms_min": float(np.min(ts)),
                      "GBps_144": BYTES_PER_UNKNOWN_SOLVE_2PASS * N / (med * 1e-3) / 1e9,
                      "plan": cn.describe_plan(L)})
+    # T's Hermitian part is I, so |x - x*| <= |T x - d|: the residual over |x| bounds the
+    # relative forward error of the last solve
     r = a * x
     r[1:] += b[1:] * x[:-1]
     r[:-1] += c[:-1] * x[1:]
-    resid = float(torch.linalg.norm(r - d) / torch.linalg.norm(d))
+    r -= d
+    rn = float(torch.linalg.vector_norm(r))
+    resid = rn / float(torch.linalg.vector_norm(d))
+    fwd_bound = rn / float(torch.linalg.vector_norm(x))
     del r, a, b, c, d, x
+    torch.cuda.empty_cache()
     auto = rows[0]
     out = {
         "unknowns_per_solve": N,
+        "inputs_sha256_16": sha,
         "auto_ms": auto["ms_median"],
         "auto_unknowns_per_s": N / (auto["ms_median"] * 1e-3),
-        "auto_frac_of_peak_144B": auto["GBps_144"] / HBM_PEAK_GBS,
-        "auto_frac_of_peak_80B": BYTES_PER_UNKNOWN_SOLVE_MIN * N / (auto["ms_median"] * 1e-3)
-                                 / 1e9 / HBM_PEAK_GBS,
+        "auto_frac_of_peak_80B_compulsory": BYTES_PER_UNKNOWN_SOLVE_MIN * N
+                                            / (auto["ms_median"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "auto_frac_of_peak_144B_two_pass": auto["GBps_144"] / HBM_PEAK_GBS,
         "residual_rel": resid,
+        "forward_error_bound_rel": fwd_bound,
         "paper_optimum_single_level_partition": math.sqrt(N),
         "sweep": rows,
     }
-    if sweep:
+    if oracle_parity:
+        ref = {}
+
+        def make(o):
+            oa, ob, oc = o.cn_coeffs(w["V"], w["dx"], w["dt"])
+            return lambda: ref.setdefault("x", o.thomas(oa, ob, oc, w["d"]))
+
         out["cpu_baseline"] = oracle_timed(
-            "serial FP64 Thomas on a 2^24-row system of the same distribution (1 thread)",
-            lambda o: _thomas_sample(np, o, 1 << 24), 1 << 24, out["auto_unknowns_per_s"])
+            "serial FP64 Thomas on the whole 2^28-row system (same arrays, 1 thread)", make, N,
+            out["auto_unknowns_per_s"])
+        if "x" in ref:
+            out["parity_rel_l2"] = rel_l2(x_auto, ref["x"])
     return out
 
 
@@ -430,14 +476,6 @@ def multi_rhs(torch, np, cn, dev):
     return out
 
 
-def _thomas_sample(np, o, n):
-    g = np.random.default_rng(1002)
-    V = g.uniform(-1.0, 0.0, n)
-    a, b, c = o.cn_coeffs(V, 0.01, 0.02)
-    d = g.standard_normal(n) + 1j * g.standard_normal(n)
-    return lambda: o.thomas(a, b, c, d)
-
-
 def oracle_timed(sample, make, units, gpu_units_per_s, threads=1):
     """The oracle timed on a bounded sample of a workload (make(oracle) returns the call)."""
     try:
@@ -474,6 +512,7 @@ def extras(torch, np, cn, workloads, dev):
         d = cn.rhs(psi0, V, w["dx"], w["dt"])
         x = torch.empty_like(d)
         ts_solve = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), 20)
+        x_solve = x.cpu().numpy()
         # 200 chained steps: eager, then captured as one graph
         psi = psi0.clone()
         ts_eager = timed_events(torch, lambda: cn.propagate(psi, V, w["dx"], w["dt"], w["steps"]), 3)
@@ -508,6 +547,12 @@ def extras(torch, np, cn, workloads, dev):
             w["n"] * w["steps"], out["plain_1d"]["unknowns_per_s"])
         if "x" in ref:
             out["plain_1d"]["parity_rel_l2_200"] = rel_l2(psi200, ref["x"])
+        # the one materialised solve against the oracle's assembly, half-step and Thomas solve
+        import oracle
+
+        oa, ob, oc = oracle.cn_coeffs(w["V"], w["dx"], w["dt"])
+        od = oracle.cn_rhs(w["psi0"], w["V"], w["dx"], w["dt"])
+        out["plain_1d"]["parity_rel_l2_solve"] = rel_l2(x_solve, oracle.thomas(oa, ob, oc, od))
     except Exception as ex:  # noqa: BLE001
         out["plain_1d"] = {"error": repr(ex)}
     # ----------------------------------------------------------- absorbing potential V - iW
@@ -525,7 +570,6 @@ def extras(torch, np, cn, workloads, dev):
         dxs = torch.from_numpy(wl["dx"]).to(dev)
         rows = int(wl["offsets"][-1])
         cn.reserve(L)
-        first = cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, layout=L).cpu().numpy()
         cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi, layout=L)
         ts = timed_events(torch, lambda: cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi,
                                                  layout=L), wl["steps"])
@@ -557,16 +601,35 @@ def extras(torch, np, cn, workloads, dev):
                                "propagate_vs_single_steps_rel_l2": prop_vs_steps,
                                "persistent_plan_ms_per_step": float(np.median(tsp)),
                                "persistent_plan": cn.describe_plan(Lp, True)[:200]}
+        # the workload's whole run: 50 steps of cn_propagate from psi0, against the oracle's
+        # 50 batched steps (its timed run is the CPU baseline)
+        p50 = torch.from_numpy(wl["psi0"]).to(dev)
+        cn.propagate(p50, V, 0.0, wl["dt"], wl["steps"], dx_per_system=dxs, layout=L)
+        p50 = p50.cpu().numpy()
         nthr = cpu_threads()
         ref = {}
+
+        def run50(o):
+            def run():
+                st = wl["psi0"]
+                for _ in range(wl["steps"]):
+                    st = o.cn_step_batched(wl["offsets"], st, wl["V"], wl["dx"], wl["dt"], nthr)
+                ref["x"] = st
+            return run
+
         out["uneven_batch"]["cpu_baseline"] = oracle_timed(
-            f"one CN step of all 10^4 systems (serial FP64 Thomas per system, {nthr} threads)",
-            lambda o: (lambda: ref.setdefault("x", o.cn_step_batched(
-                wl["offsets"], wl["psi0"], wl["V"], wl["dx"], wl["dt"], nthr))),
-            rows, out["uneven_batch"]["unknowns_per_s"], nthr)
+            f"the {wl['steps']} CN steps of all 10^4 systems (serial FP64 Thomas per system, "
+            f"{nthr} threads)", run50, rows * wl["steps"],
+            out["uneven_batch"]["unknowns_per_s"], nthr)
         if "x" in ref:
-            out["uneven_batch"]["parity_rel_l2_first_step"] = rel_l2(first, ref["x"])
-        del first, ref
+            offs = wl["offsets"]
+            num_s = np.add.reduceat(np.abs(p50 - ref["x"]) ** 2, offs[:-1])
+            den_s = np.add.reduceat(np.abs(ref["x"]) ** 2, offs[:-1])
+            out["uneven_batch"]["parity_rel_l2_50_steps"] = float(np.sqrt(num_s.sum()
+                                                                          / den_s.sum()))
+            out["uneven_batch"]["parity_worst_system_50_steps"] = float(np.sqrt(
+                (num_s / den_s).max()))
+        del p50, ref
     except Exception as ex:  # noqa: BLE001
         out["uneven_batch"] = {"error": repr(ex)}
     # ----------------------------------------------------------- differentiated propagation
@@ -716,24 +779,26 @@ def differentiated(torch, np, workloads, dev):
     ana = np.asarray(ana)
     fwd_s = float(np.median(tf))
     bwd_s = float(np.median(tb))
-    # the oracle beside it on a bounded sample: the first 50 steps of the same propagation,
-    # and the GPU's 50-step state against it
-    import paper_2205_00856_amd as cn
-
-    ns = 50
-    p50 = p0.clone()
-    cn.propagate(p50, tV.detach(), dx, dt, ns, E=np.ascontiguousarray(w["E"][:ns]), xgrid=tx)
-    p50 = p50.cpu().numpy()
+    # the oracle beside it: the whole 2000-step propagation (1 thread), against which the
+    # GPU's psi_T and loss are compared
+    psiT = out.detach().cpu().numpy()
     ref = {}
     cpu = oracle_timed(
-        f"the first {ns} of the {w['steps']} steps (serial FP64 Thomas with the field term, "
-        f"1 thread)",
-        lambda o: (lambda: ref.setdefault("x", o.cn_propagate(w["psi0"], w["V"], dx, dt, ns,
-                                                              xgrid=w["x"], E=w["E"][:ns]))),
-        w["n"] * ns, w["n"] * w["steps"] / fwd_s)
+        f"all {w['steps']} steps of the 2^20-row propagation with the field term (serial FP64 "
+        f"Thomas, 1 thread)",
+        lambda o: (lambda: ref.setdefault("x", o.cn_propagate(w["psi0"], w["V"], dx, dt,
+                                                              w["steps"], xgrid=w["x"],
+                                                              E=w["E"]))),
+        w["n"] * w["steps"], w["n"] * w["steps"] / fwd_s)
+    par = par_loss = None
+    if "x" in ref:
+        par = rel_l2(psiT, ref["x"])
+        ref_loss = abs(np.sum(np.conj(w["phi"]) * ref["x"]) * dx) ** 2
+        par_loss = abs(float(L.item()) - ref_loss) / ref_loss
     return {
         "cpu_baseline": cpu,
-        "parity_rel_l2_50_steps": rel_l2(p50, ref["x"]) if "x" in ref else None,
+        "parity_rel_l2_psi_T": par,
+        "parity_rel_loss": par_loss,
         "n": w["n"], "steps": w["steps"], "checkpoint_every": K,
         "forward_ms": fwd_s * 1e3, "backward_ms": bwd_s * 1e3,
         "forward_us_per_step": fwd_s * 1e6 / w["steps"],
