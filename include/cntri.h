@@ -52,7 +52,9 @@ typedef enum {
   CN_ERR_UNSUPPORTED = -2,    /* valid request the library does not implement               */
   CN_ERR_NO_MEMORY = -3,      /* device allocation failed                                   */
   CN_ERR_HIP = -4,            /* a HIP runtime call failed                                  */
-  CN_ERR_NOT_RESERVED = -5    /* workspace would have to grow during graph capture          */
+  CN_ERR_NOT_RESERVED = -5,   /* workspace would have to grow during graph capture          */
+  CN_ERR_SCRATCH_TOO_SMALL = -6 /* cn_tridiag_solve_noalloc: the layout needs more device
+                                  memory than the library's fixed scratch array holds          */
 } cn_status;
 
 /* Shape of the batch of independent systems handled by one call.
@@ -136,6 +138,24 @@ cn_status cn_reserve(cn_handle_t handle, const cn_layout* layout);
 cn_status cn_tridiag_solve(cn_handle_t handle, const cn_layout* layout, const void* a,
                            const void* b, const void* c, const void* d, void* x,
                            cn_stream_t stream);
+
+/* cn_tridiag_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same plan and kernels,
+ * with the plan's tables and workspace in a fixed device array of the library instead of the
+ * handle's workspace.  The array holds 32 MiB (33554432 bytes) per GPU, is set up by cn_create
+ * and kept until the process ends; the call allocates no device memory (the plan of a new
+ * layout is built in host memory on its first call) and copies the plan's tables into the
+ * array on the caller's stream before the kernels.  Arguments, layouts and results are those of
+ * cn_tridiag_solve (x may alias d; the automatic or explicit partition of the layout, never an
+ * autotuned one).  A layout whose tables and workspace exceed the array returns
+ * CN_ERR_SCRATCH_TOO_SMALL with nothing enqueued (a single contiguous system of up to about
+ * 2^28 rows fits; cn_tridiag_solve takes any size).  Every call on one GPU, from any handle or
+ * stream, uses that GPU's one array: calls that overlap in time on a GPU race and must be
+ * ordered by the caller (for example, issued on one stream).  Nothing in the array needs to
+ * start at zero; each call rewrites what it reads. */
+cn_status cn_tridiag_solve_noalloc(cn_handle_t handle, const cn_layout* layout, const void* a,
+                                   const void* b, const void* c, const void* d, void* x,
+                                   cn_stream_t stream);
 
 /* Reverse mode of cn_tridiag_solve.  Given x = T^{-1} d and gx, the gradient of a real loss
  * with respect to x in the (d/dRe + i d/dIm) convention, writes

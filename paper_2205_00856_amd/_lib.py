@@ -18,6 +18,7 @@ CN_ERR_UNSUPPORTED = -2
 CN_ERR_NO_MEMORY = -3
 CN_ERR_HIP = -4
 CN_ERR_NOT_RESERVED = -5
+CN_ERR_SCRATCH_TOO_SMALL = -6
 
 
 class CnLayout(ctypes.Structure):
@@ -76,6 +77,7 @@ def lib():
         "cn_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "cn_reserve": ([H, LP], ctypes.c_int),
         "cn_tridiag_solve": ([H, LP, P, P, P, P, P, P], ctypes.c_int),
+        "cn_tridiag_solve_noalloc": ([H, LP, P, P, P, P, P, P], ctypes.c_int),
         "cn_tridiag_solve_adjoint": ([H, LP, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "cn_assemble": ([H, LP, OP, d, P, P, P, P], ctypes.c_int),
         "cn_rhs": ([H, LP, OP, d, P, P, P], ctypes.c_int),
@@ -102,7 +104,7 @@ def lib():
 EXPORTED = ["cn_check_layout", "cn_create", "cn_destroy", "cn_status_string", "cn_reserve", "cn_tridiag_solve",
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
             "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
-            "cn_propagate_adjoint", "cn_handle_info"]
+            "cn_propagate_adjoint", "cn_handle_info", "cn_tridiag_solve_noalloc"]
 
 
 def status_string(st: int) -> str:

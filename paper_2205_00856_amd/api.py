@@ -18,7 +18,7 @@ import torch
 from . import _lib
 from ._lib import CnLayout, CnOperator, check
 
-__all__ = ["Layout", "Handle", "handle", "solve", "solve_adjoint", "assemble", "rhs", "step",
+__all__ = ["Layout", "Handle", "handle", "solve", "solve_noalloc", "solve_adjoint", "assemble", "rhs", "step",
            "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune",
            "propagate_adjoint"]
 
@@ -203,6 +203,23 @@ def solve(a, b, c, d, out=None, layout: Optional[Layout] = None):
     Lc = L.c()
     check(_lib.lib().cn_tridiag_solve(h.ptr, ctypes.byref(Lc), _ptr(a), _ptr(b), _ptr(c), _ptr(d),
                                       _ptr(out), _stream(d)), "cn_tridiag_solve")
+    return out
+
+
+def solve_noalloc(a, b, c, d, out, layout: Optional[Layout] = None):
+    """x = T^{-1} d through cn_tridiag_solve_noalloc: the library allocates no device memory
+    (its fixed scratch array holds the plan's tables and workspace); out is required."""
+    L = _layout_for(d, layout)
+    span = L.span()
+    for t, nm in ((a, "a"), (b, "b"), (c, "c")):
+        _need(t, torch.complex128, nm, L.coef_span())
+    _need(d, torch.complex128, "d", span)
+    _need(out, torch.complex128, "out", span)
+    h = handle(d.device.index)
+    Lc = L.c()
+    check(_lib.lib().cn_tridiag_solve_noalloc(h.ptr, ctypes.byref(Lc), _ptr(a), _ptr(b), _ptr(c),
+                                              _ptr(d), _ptr(out), _stream(d)),
+          "cn_tridiag_solve_noalloc")
     return out
 
 

@@ -154,6 +154,7 @@ struct Plan {
   int64_t o_part = -1;  // workspace for per-block partial sums
   int64_t nparts = 0;
   int64_t ntiles1 = 0;  // level-1 tiles of a uniform CN plan (partial sums of the adjoint)
+  std::vector<char> host_tab;  // no-allocation plans: the tables, copied into scratch per call
   ~Plan() {
     if (tables) (void)hipFree(tables);
   }
@@ -554,6 +555,10 @@ struct cn_handle_s {
   // until cn_destroy instead of being freed.
   bool captured = false;
   std::vector<void*> retired;
+  // cn_tridiag_solve_noalloc: this device's address of the fixed scratch array, and the plans
+  // of that entry point (their tables live in host memory and are copied into the array)
+  char* scratch = nullptr;
+  std::map<std::string, std::unique_ptr<Plan>> static_plans;
 };
 
 namespace {
@@ -567,6 +572,32 @@ bool capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
   return st != hipStreamCaptureStatusNone;
+}
+
+// ------------------------------------------------------------ fixed scratch (no allocation)
+// Device memory of cn_tridiag_solve_noalloc: the plan tables (offsets, launch lists) at the
+// start, then the workspace (slots, reduced solutions).  One copy per GPU, held until the
+// process ends.  In host code `scratch` is only a host-side stand-in for the symbol: its device
+// address on each GPU comes from hipGetSymbolAddress (scratch_setup) and only that address is
+// passed to kernels and copies.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kMaxDevices] = {};
+
+// Resolves this device's address of `scratch` once per device; `device` must be current.
+cn_status scratch_setup(int device, char** addr) {
+  if (device < 0 || device >= kMaxDevices) return CN_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CN_ERR_HIP;
+    g_scratch_addr[device] = (char*)p;
+  }
+  *addr = g_scratch_addr[device];
+  return CN_OK;
 }
 
 // Replaces handle buffer *p (size *bytes) by a new allocation of `need` bytes.  The old buffer
@@ -1037,6 +1068,7 @@ const char* cn_status_string(cn_status st) {
     case CN_ERR_NO_MEMORY: return "CN_ERR_NO_MEMORY";
     case CN_ERR_HIP: return "CN_ERR_HIP";
     case CN_ERR_NOT_RESERVED: return "CN_ERR_NOT_RESERVED";
+    case CN_ERR_SCRATCH_TOO_SMALL: return "CN_ERR_SCRATCH_TOO_SMALL";
   }
   return "unknown cn_status";
 }
@@ -1058,7 +1090,8 @@ cn_status cn_create(cn_handle_t* handle, int device) {
     delete h;
     return CN_ERR_NO_MEMORY;
   }
-  if (hipMemset(h->status, 0, sizeof(int)) != hipSuccess) {
+  if (hipMemset(h->status, 0, sizeof(int)) != hipSuccess ||
+      scratch_setup(device, &h->scratch) != CN_OK) {
     (void)hipFree(h->status);
     delete h;
     return CN_ERR_HIP;
@@ -1071,6 +1104,7 @@ cn_status cn_destroy(cn_handle_t h) {
   if (!h) return CN_ERR_INVALID_ARG;
   (void)hipDeviceSynchronize();
   h->plans.clear();
+  h->static_plans.clear();
   if (h->ws) (void)hipFree(h->ws);
   if (h->rows_buf) (void)hipFree(h->rows_buf);
   if (h->ws2) (void)hipFree(h->ws2);
@@ -1121,6 +1155,45 @@ cn_status cn_tridiag_solve(cn_handle_t h, const cn_layout* L, const void* a, con
   u.d = (const cd*)d;
   u.x = (cd*)x;
   return run_plan(h, P, u, s);
+}
+
+cn_status cn_tridiag_solve_noalloc(cn_handle_t h, const cn_layout* L, const void* a,
+                                   const void* b, const void* c, const void* d, void* x,
+                                   cn_stream_t stream) {
+  if (!h || !a || !b || !c || !d || !x) return CN_ERR_INVALID_ARG;
+  if (!h->scratch) return CN_ERR_HIP;
+  int64_t rows = 0, span = 0;
+  cn_status st = validate(L, rows, span);
+  if (st != CN_OK) return st;
+  // the plan of this layout, built on the host on the first call (no device memory); its
+  // tables are bound to the start of the scratch array and its workspace follows them
+  const std::string key = plan_key(L, nsd::SRC_EXPL);
+  auto it = h->static_plans.find(key);
+  if (it == h->static_plans.end()) {
+    std::unique_ptr<Plan> P(new Plan());
+    std::vector<char> tab;
+    st = build_plan(L, nsd::SRC_EXPL, false, *P, tab);
+    if (st != CN_OK) return st;
+    P->host_tab.swap(tab);
+    bind_tables(*P, h->scratch);
+    it = h->static_plans.emplace(key, std::move(P)).first;
+  }
+  Plan* P = it->second.get();
+  const size_t tab_bytes = (P->host_tab.size() + 255) & ~size_t(255);
+  if (tab_bytes + P->ws_bytes > kScratchBytes) return CN_ERR_SCRATCH_TOO_SMALL;
+  hipStream_t s = (hipStream_t)stream;
+  // the tables are copied on every call: another call may have used the array since
+  if (!P->host_tab.empty() &&
+      hipMemcpyAsync(h->scratch, P->host_tab.data(), P->host_tab.size(), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
+    return CN_ERR_HIP;
+  UserArgs u;
+  u.a = (const cd*)a;
+  u.b = (const cd*)b;
+  u.c = (const cd*)c;
+  u.d = (const cd*)d;
+  u.x = (cd*)x;
+  return run_plan(h, P, u, s, h->scratch + tab_bytes);
 }
 
 cn_status cn_tridiag_solve_adjoint(cn_handle_t h, const cn_layout* L, const void* a,
