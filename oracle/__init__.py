@@ -14,7 +14,9 @@ What it computes (arXiv 2205.00856):
                            (1 + i tau H)^{-1} (1 - i tau H), whose right side is not T^dagger.
 * ``adi_step``          -- one Lie-split ADI step (operator splitting, Sec. 3) on a 2D grid.
 * ``thomas_adjoint``    -- reverse mode of the solve (plain definition, lambda = T^{-H} G).
-* ``cn_propagate_grad`` -- reverse mode of many CN steps with every state stored.
+* ``cn_propagate_grad`` -- reverse mode of many CN steps with every state stored (with ``W``,
+                           of the absorbing step: lambda = T^{-H} G, G_k = B^H lambda with
+                           B = 1 - i tau H no longer equal to T^H).
 
 Everything runs in FP64 / complex128 in the C file ``cn_oracle.c`` (built with gcc -O2
 -ffp-contract=off, OpenMP only across independent systems).
@@ -73,6 +75,7 @@ def _load():
     lib.oracle_adi_step.argtypes = [i64, i64, P, d, d, d, P, ci]
     lib.oracle_thomas_adjoint.argtypes = [i64, P, P, P, P, P, P, P, P, P]
     lib.oracle_cn_propagate_grad.argtypes = [i64, P, d, d, i64, P, P, P, P, P, P, P]
+    lib.oracle_cn_propagate_grad_w.argtypes = [i64, P, d, d, i64, P, P, P, P, P, P, P, P]
     lib.oracle_max_threads.argtypes = []
     _lib = lib
     return lib
@@ -201,18 +204,19 @@ def thomas_adjoint(a, b, c, x, G):
     return lam, ga, gb, gc
 
 
-def cn_propagate_grad(psi0, V, dx, dt, nsteps, G_T, xgrid=None, E=None):
-    """Returns (grad psi0, dL/dV, dL/dE or None)."""
+def cn_propagate_grad(psi0, V, dx, dt, nsteps, G_T, xgrid=None, E=None, W=None):
+    """Returns (grad psi0, dL/dV, dL/dE or None); with W the potential is V - iW."""
     lib = _load()
     psi0 = _c(psi0, np.complex128)
     G_T = _c(G_T, np.complex128)
     V = _c(V, np.float64)
     xg = None if xgrid is None else _c(xgrid, np.float64)
     Ea = None if E is None else _c(E, np.float64)
+    Wa = None if W is None else _c(W, np.float64)
     n = psi0.shape[0]
     gpsi0 = np.empty(n, np.complex128)
     dV = np.empty(n, np.float64)
     dE = np.empty(int(nsteps), np.float64) if Ea is not None else None
-    _check(lib.oracle_cn_propagate_grad(n, _p(V), dx, dt, int(nsteps), _p(xg), _p(Ea), _p(psi0),
-                                        _p(G_T), _p(gpsi0), _p(dV), _p(dE)))
+    _check(lib.oracle_cn_propagate_grad_w(n, _p(V), dx, dt, int(nsteps), _p(xg), _p(Ea), _p(Wa),
+                                          _p(psi0), _p(G_T), _p(gpsi0), _p(dV), _p(dE)))
     return gpsi0, dV, dE

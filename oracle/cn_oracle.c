@@ -233,34 +233,40 @@ int oracle_thomas_adjoint(int64_t n, const cplx* a, const cplx* b, const cplx* c
   return st;
 }
 
-/* Reverse mode of nsteps CN steps psi_{k+1} = T_k^{-1} (1 - i tau H_k) psi_k with
- * H_k = H_0 + diag(V + xgrid * E[k]) (xgrid/E may be NULL).  Plain form: every state is
- * stored (memory n*(nsteps+1)), then the adjoint recursion runs backwards:
- *   lambda_k = T_k^{-H} G_{k+1};   G_k = T_k lambda_k   (T_k^H = 1 - i tau H_k for real V)
+/* Reverse mode of nsteps CN steps psi_{k+1} = T_k^{-1} B_k psi_k, T_k = 1 + i tau H_k and
+ * B_k = 1 - i tau H_k, with H_k = H_0 + diag(V + xgrid * E[k] - i W) (xgrid/E and W may be
+ * NULL).  Plain form: every state is stored (memory n*(nsteps+1)), then the adjoint recursion
+ * runs backwards:
+ *   lambda_k = T_k^{-H} G_{k+1};   G_k = B_k^H lambda_k
  *   dL/dV_j  += tau * Im(conj(lambda_k,j) (psi_{k,j} + psi_{k+1,j}))
  *   dL/dE_k   = sum_j x_j * tau * Im(conj(lambda_k,j) (psi_{k,j} + psi_{k+1,j}))
+ * (V enters T as + i tau dV and B as - i tau dV, so d psi_{k+1} = T_k^{-1} (-i tau dV)
+ * (psi_k + psi_{k+1})).  For real potentials B_k^H = T_k; with W, B_k^H has the diagonal
+ * 1 + i tau conj(h_j) = 1 - tau W_j + i tau (1/dx^2 + v_j) and the off-diagonals -i kappa.
  * G_T is the loss gradient at the final state (convention as in oracle_thomas_adjoint);
  * on return gpsi0 holds the gradient with respect to psi_0.  dV (length n) and dE (length
  * nsteps, may be NULL) are overwritten. */
-int oracle_cn_propagate_grad(int64_t n, const double* V, double dx, double dt, int64_t nsteps,
-                             const double* xgrid, const double* E, const cplx* psi0,
-                             const cplx* G_T, cplx* gpsi0, double* dV, double* dE) {
+int oracle_cn_propagate_grad_w(int64_t n, const double* V, double dx, double dt, int64_t nsteps,
+                               const double* xgrid, const double* E, const double* W,
+                               const cplx* psi0, const cplx* G_T, cplx* gpsi0, double* dV,
+                               double* dE) {
   double tau = 0.5 * dt;
+  double kappa = tau / (2.0 * dx * dx);
   cplx* states = (cplx*)malloc(sizeof(cplx) * (size_t)(n * (nsteps + 1)));
   cplx* buf = (cplx*)malloc(sizeof(cplx) * (size_t)(6 * n));
   cplx *a = buf, *b = buf + n, *c = buf + 2 * n, *lam = buf + 3 * n, *g = buf + 4 * n;
   int st = 0;
   memcpy(states, psi0, sizeof(cplx) * (size_t)n);
   for (int64_t k = 0; k < nsteps; ++k)
-    st |= oracle_cn_step(n, V, dx, dt, xgrid, E ? E[k] : 0.0, states + k * n,
-                         states + (k + 1) * n);
+    st |= oracle_cn_step_w(n, V, dx, dt, xgrid, E ? E[k] : 0.0, W, states + k * n,
+                           states + (k + 1) * n);
   memcpy(g, G_T, sizeof(cplx) * (size_t)n);
   for (int64_t j = 0; j < n; ++j) dV[j] = 0.0;
   for (int64_t k = nsteps - 1; k >= 0; --k) {
     double Ek = E ? E[k] : 0.0;
     const cplx* pk = states + k * n;
     const cplx* pk1 = states + (k + 1) * n;
-    oracle_cn_coeffs(n, V, dx, dt, xgrid, Ek, a, b, c);
+    oracle_cn_coeffs_w(n, V, dx, dt, xgrid, Ek, W, a, b, c);
     st |= oracle_thomas_adjoint(n, a, b, c, pk1, g, lam, NULL, NULL, NULL);
     double acc = 0.0;
     for (int64_t j = 0; j < n; ++j) {
@@ -269,11 +275,14 @@ int oracle_cn_propagate_grad(int64_t n, const double* V, double dx, double dt, i
       if (xgrid) acc += xgrid[j] * t;
     }
     if (dE) dE[k] = acc;
-    /* G_k = T_k lambda_k: the tridiagonal product with the coefficients of T_k */
+    /* G_k = B_k^H lambda_k, B_k = 1 - i tau H_k: diagonal conj(1 - i tau h_j), off-diagonals
+     * conj(i kappa) */
     for (int64_t j = 0; j < n; ++j) {
-      cplx s = a[j] * lam[j];
-      if (j > 0) s += b[j] * lam[j - 1];
-      if (j < n - 1) s += c[j] * lam[j + 1];
+      double v = V[j] + (xgrid ? xgrid[j] * Ek : 0.0);
+      cplx h = (1.0 / (dx * dx) + v) - I * (W ? W[j] : 0.0);
+      cplx s = conj(1.0 - I * tau * h) * lam[j];
+      if (j > 0) s += conj(I * kappa) * lam[j - 1];
+      if (j < n - 1) s += conj(I * kappa) * lam[j + 1];
       g[j] = s;
     }
   }
@@ -281,6 +290,13 @@ int oracle_cn_propagate_grad(int64_t n, const double* V, double dx, double dt, i
   free(buf);
   free(states);
   return st;
+}
+
+int oracle_cn_propagate_grad(int64_t n, const double* V, double dx, double dt, int64_t nsteps,
+                             const double* xgrid, const double* E, const cplx* psi0,
+                             const cplx* G_T, cplx* gpsi0, double* dV, double* dE) {
+  return oracle_cn_propagate_grad_w(n, V, dx, dt, nsteps, xgrid, E, NULL, psi0, G_T, gpsi0, dV,
+                                    dE);
 }
 
 int oracle_max_threads(void) {

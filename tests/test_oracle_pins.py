@@ -410,3 +410,94 @@ def test_absorbing_pin_rejects_t_dagger_right_side(oracle_mod):
     assert rel(right, g * mode) <= 1e-13
     assert rel(wrong, g * mode) > 1e-3
     assert abs(np.linalg.norm(wrong) - np.linalg.norm(mode)) <= 1e-12 * np.linalg.norm(mode)
+
+
+def _propagate_torch_w(torch, psi0, V, W, dx, dt, steps, xg, E):
+    """Dense restatement of the absorbing step: H = -1/2 D2 + diag(V + x E_k - i W)."""
+    n = psi0.shape[0]
+    D2 = (torch.diag(torch.ones(n - 1, dtype=torch.float64), -1) - 2 * torch.eye(n, dtype=torch.float64)
+          + torch.diag(torch.ones(n - 1, dtype=torch.float64), 1))
+    psi = psi0
+    for k in range(steps):
+        H = (-0.5 * D2 / dx**2 + torch.diag(V + xg * E[k])).to(torch.complex128) \
+            - 1j * torch.diag(W).to(torch.complex128)
+        A = torch.eye(n, dtype=torch.complex128) + 0.5j * dt * H
+        B = torch.eye(n, dtype=torch.complex128) - 0.5j * dt * H
+        psi = torch.linalg.solve(A, B @ psi)
+    return psi
+
+
+def test_absorbing_propagate_grad_matches_dense_autograd(oracle_mod):
+    """Reverse mode with an absorbing potential: lambda = T^{-H} G and G_k = B^H lambda with
+    B = 1 - i tau H != T^H; pinned to torch autograd through dense non-Hermitian steps."""
+    torch = pytest.importorskip("torch")
+    n, dx, dt, steps = 32, 0.4, 0.05, 12
+    g = np.random.default_rng(15)
+    x = workloads.grid_1d(n, dx)
+    V = workloads.softcore(x)
+    W = workloads.absorber(n, frac=0.25, strength=3.0)
+    E = g.normal(0, 0.05, steps)
+    psi0 = workloads.gaussian(x, 2.0, 2.0, 1.5, dx)
+    phi = workloads.gaussian(x, 3.0, 1.5, 0.8, dx)
+    tV = torch.tensor(V, requires_grad=True)
+    tE = torch.tensor(E, requires_grad=True)
+    tpsi = torch.tensor(psi0, requires_grad=True)
+    out = _propagate_torch_w(torch, tpsi, tV, torch.tensor(W), dx, dt, steps, torch.tensor(x), tE)
+    loss = torch.abs((torch.conj(torch.tensor(phi)) * out).sum() * dx) ** 2
+    loss.backward()
+    psiT = oracle_mod.cn_propagate(psi0, V, dx, dt, steps, x, E, W=W)
+    assert rel(psiT, out.detach().numpy()) <= 1e-12
+    G_T = 2 * (np.sum(np.conj(phi) * psiT) * dx) * phi * dx
+    gpsi0, dV, dE = oracle_mod.cn_propagate_grad(psi0, V, dx, dt, steps, G_T, x, E, W=W)
+    assert rel(dV, tV.grad.numpy()) <= 1e-10
+    assert rel(dE, tE.grad.numpy()) <= 1e-10
+    assert rel(gpsi0, tpsi.grad.numpy()) <= 1e-10
+    # the Hermitian recursion G_k = T_k lambda_k is wrong here: it must miss the pin
+    g_herm, _, _ = oracle_mod.cn_propagate_grad(psi0, V, dx, dt, steps, G_T, x, E, W=None)
+    assert rel(g_herm, tpsi.grad.numpy()) > 1e-3
+
+
+def test_absorbing_propagate_grad_matches_finite_differences(oracle_mod):
+    n, dx, dt, steps = 40, 0.3, 0.04, 10
+    g = np.random.default_rng(19)
+    x = workloads.grid_1d(n, dx)
+    V = workloads.softcore(x)
+    W = workloads.absorber(n, frac=0.3, strength=2.0)
+    E = g.normal(0, 0.05, steps)
+    psi0 = workloads.gaussian(x, 2.0, 2.0, 1.0, dx)
+    phi = workloads.gaussian(x, 1.0, 1.5, 0.8, dx)
+
+    def loss(Vv, Ev):
+        p = oracle_mod.cn_propagate(psi0, Vv, dx, dt, steps, x, Ev, W=W)
+        return abs(np.sum(np.conj(phi) * p) * dx) ** 2
+
+    psiT = oracle_mod.cn_propagate(psi0, V, dx, dt, steps, x, E, W=W)
+    G_T = 2 * (np.sum(np.conj(phi) * psiT) * dx) * phi * dx
+    _, dV, dE = oracle_mod.cn_propagate_grad(psi0, V, dx, dt, steps, G_T, x, E, W=W)
+    h = 1e-5
+    for j in (3, 17, 20, 33, 38):
+        Vp, Vm = V.copy(), V.copy()
+        Vp[j] += h
+        Vm[j] -= h
+        fd = (loss(Vp, E) - loss(Vm, E)) / (2 * h)
+        assert abs(fd - dV[j]) <= 1e-7 * max(abs(fd), 1e-3)
+    for k in (0, 4, 9):
+        Ep, Em = E.copy(), E.copy()
+        Ep[k] += h
+        Em[k] -= h
+        fd = (loss(V, Ep) - loss(V, Em)) / (2 * h)
+        assert abs(fd - dE[k]) <= 1e-7 * max(abs(fd), 1e-3)
+
+
+def test_absorbing_propagate_grad_without_w_is_the_hermitian_recursion(oracle_mod):
+    """W = 0 gives the real-potential recursion G_k = T_k lambda_k, pinned above."""
+    n, dx, dt, steps = 30, 0.3, 0.04, 6
+    x = workloads.grid_1d(n, dx)
+    V = workloads.softcore(x)
+    psi0 = workloads.gaussian(x, 0.0, 2.0, 1.0, dx)
+    G_T = workloads.complex_normal(np.random.default_rng(3), n)
+    a = oracle_mod.cn_propagate_grad(psi0, V, dx, dt, steps, G_T, x, np.zeros(steps))
+    b = oracle_mod.cn_propagate_grad(psi0, V, dx, dt, steps, G_T, x, np.zeros(steps),
+                                     W=np.zeros(n))
+    for u, v in zip(a, b):
+        assert rel(u, v) <= 1e-15
