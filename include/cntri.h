@@ -86,6 +86,15 @@ typedef struct {
                               points that accumulate per-system gradients or materialise
                               per-system arrays (adjoints, cn_assemble, cn_rhs) return
                               CN_ERR_UNSUPPORTED for 1                                       */
+  int32_t levels;          /* partition levels before the RS stage (Sec. 4.1.6, Eq. (6);
+                              Sec. 5.5.1): 0 = automatic (the reduced systems are partitioned
+                              again until one tile holds them); L in 1..8 = the caller's
+                              systems and the reduced systems of the first L-1 levels are
+                              partitioned into tiles, and the reduced system left after L
+                              levels is solved by the serial RS stage of Table 1 (Thomas's
+                              elimination, one thread per system).  A system that fits one
+                              tile at some level needs no further level.  Zero-initialise the
+                              struct so that levels is 0 by default.                         */
 } cn_layout;
 
 /* Crank-Nicolson operator of Sec. 2, Eqs. (2)-(4) on a uniform grid with Dirichlet walls:
@@ -98,12 +107,18 @@ typedef struct {
  * v_j - i W_j, which makes H non-Hermitian.  T's diagonal becomes 1 + tau W_j + i tau (...) and
  * the explicit side is 1 - i tau H (diagonal 1 - tau W_j - i tau (...)), which is no longer
  * T^dagger: the step stays the Cayley form (1 + i tau H)^{-1} (1 - i tau H).  cn_assemble,
- * cn_rhs, cn_step and cn_propagate take it; cn_step and cn_propagate then run materialised
- * (cn_assemble, cn_rhs and cn_tridiag_solve's kernels through a handle buffer of 4 * span
- * complex values, allocated on the first such call for a layout, so a captured call needs one
- * call outside capture first, else CN_ERR_NOT_RESERVED) with no cross-step fusion.  The
- * adjoint entry points and cn_autotune return CN_ERR_UNSUPPORTED for it, as do shared
- * coefficients.  Zero-initialise the struct so that absorb is NULL by default. */
+ * cn_rhs, cn_step, cn_propagate, cn_step_adjoint and cn_propagate_adjoint take it.  The steps
+ * run the fused kernels with W read beside V (one pass per step in cn_propagate over two-pass
+ * plans, as for real potentials; 4 rows per lane); a layout whose plan needs a configuration
+ * these kernels are not built for (explicit partitions with 8 or 16 rows per lane), or
+ * CN_ABSORB_FUSED=0 in the environment, runs the step materialised instead (cn_assemble, cn_rhs
+ * and cn_tridiag_solve's kernels through a handle buffer of 4 * span complex values, allocated
+ * on the first such call for a layout, so a captured call needs one call outside capture
+ * first, else CN_ERR_NOT_RESERVED; the adjoints then return CN_ERR_UNSUPPORTED).  In reverse
+ * mode T^H = 1 + tau W - i tau (...) and B^H = 1 - tau W + i tau (...) for B = 1 - i tau H:
+ * the operators of a step with dt -> -dt and W -> -W.  cn_autotune returns CN_ERR_UNSUPPORTED
+ * for it, as does a layout with shared coefficients.  Zero-initialise the struct so that absorb
+ * is NULL by default. */
 typedef struct {
   const double* V;
   double v_scale;
@@ -117,7 +132,8 @@ typedef struct {
 /* Host-only check of a layout (no device access): CN_OK, or the negative status that every
  * entry point would return for it (null layout, batch < 1, n < 1, strides < 1, systems that
  * share elements, offsets not starting at 0 or decreasing, a partition that is not a power of two
- * in [32, 16384], rows_per_thread not in {0, 2, 4, 8, 16}, shared_coefficients not 0 or 1;
+ * in [32, 16384], rows_per_thread not in {0, 2, 4, 8, 16}, shared_coefficients not 0 or 1,
+ * levels not in 0..8;
  * CN_ERR_UNSUPPORTED for shared coefficients in an uneven batch). */
 cn_status cn_check_layout(const cn_layout* layout);
 
@@ -193,9 +209,9 @@ cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_ope
                        cn_stream_t stream);
 
 /* One step of the adjoint recursion of cn_propagate (uniform batch of one system).
- * With psi_np1 = T_n^{-1} (1 - i tau H_n) psi_n and g_np1 the gradient at psi_np1:
- *   lambda = T_n^{-H} g_np1   (T_n^H = 1 - i tau H_n for real v),
- *   g_n = T_n lambda,
+ * With psi_np1 = T_n^{-1} B_n psi_n, B_n = 1 - i tau H_n, and g_np1 the gradient at psi_np1:
+ *   lambda = T_n^{-H} g_np1   (T_n^H = B_n for real v),
+ *   g_n = B_n^H lambda        (= T_n lambda for real v),
  *   dV_accum_j += v_scale * tau * Im(conj(lambda_j) (psi_n,j + psi_np1,j)),
  *   dE_partial[0] = sum_j xgrid_j * tau * Im(conj(lambda_j) (psi_n,j + psi_np1,j))
  * (dE_partial may be NULL; it needs xgrid).  The sum is deterministic. */
@@ -209,8 +225,9 @@ cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_
  * ((d/dRe + i d/dIm) convention); on return it is the gradient at the initial state.  Each
  * segment of K steps is recomputed forward from its checkpoint; the recursion then runs
  * backwards through it on g itself, g_N = g and
- *   g_k = T_k lambda_k,  lambda_k = T_k^{-H} g_{k+1},  i.e.  g_k = (1 - i tau H_k)^{-1}
- *   (1 + i tau H_k) g_{k+1}: a Crank-Nicolson step with dt -> -dt and E_k on both sides,
+ *   g_k = B_k^H lambda_k,  lambda_k = T_k^{-H} g_{k+1},  i.e.  g_k = T_k^{-H} B_k^H g_{k+1}
+ *   (for real v: (1 - i tau H_k)^{-1} (1 + i tau H_k) g_{k+1}): a Crank-Nicolson step with
+ *   dt -> -dt (and W -> -W) and E_k on both sides,
  * with lambda_k = (g_k + g_{k+1}) / 2, accumulating
  *   dV_accum_j += v_scale tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (may be NULL)
  *   dE[k] = sum_j xgrid_j tau Im(conj(lambda_k,j)(psi_k,j + psi_k+1,j))   (needs xgrid; may be NULL)
@@ -244,6 +261,16 @@ cn_status cn_autotune(cn_handle_t handle, const cn_layout* layout, int cn_mode,
  * of the handle has been captured.  Each output pointer may be NULL.  Host only. */
 cn_status cn_handle_info(cn_handle_t handle, int64_t* device_bytes, int64_t* retired_buffers,
                          int32_t* captured);
+
+/* Plan log.  With cn_profile(h, 1), every launch of a plan run by cn_tridiag_solve, cn_step
+ * (one step) and the adjoint solves outside graph capture is bracketed by HIP events on the
+ * caller's stream (host-side event objects are created per launch); cn_profile(h, 0) stops it.
+ * cn_profile_report waits for the recorded launches and writes one line per launch, in launch
+ * order: "L<level> <phase> <tile T(M,W) or -> grid=<x>x<y> threads=<n> ms=<duration>", the
+ * stage times of the method (partition reductions, reduced systems, substitutions, the serial
+ * RS stage); then it clears the log.  buf is truncated to buflen. */
+cn_status cn_profile(cn_handle_t handle, int enable);
+cn_status cn_profile_report(cn_handle_t handle, char* buf, int64_t buflen);
 
 /* Synchronises the stream, returns CN_NUMERICAL_BREAKDOWN if any kernel of this handle met a
  * non-finite result since the last call (and clears the flag), else CN_OK. */

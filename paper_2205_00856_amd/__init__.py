@@ -4,7 +4,8 @@ The solver itself is the HIP library libcntri.so (C ABI in include/cntri.h); thi
 binds it for torch device tensors and adds autograd wrappers.
 """
 from .api import (Handle, Layout, assemble, autotune, describe_plan, get_status, handle,  # noqa: F401
-                  propagate, propagate_adjoint, reserve, rhs, solve, solve_adjoint, solve_noalloc, step,
+                  profile, profile_report, propagate, propagate_adjoint, reserve, rhs, solve, solve_adjoint,
+                  solve_noalloc, step,
                   step_adjoint)
 
 __version__ = "0.1.0"

@@ -31,6 +31,7 @@ class CnLayout(ctypes.Structure):
         ("partition", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32),
         ("shared_coefficients", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
     ]
 
 
@@ -92,6 +93,8 @@ def lib():
                         ctypes.c_int),
         "cn_handle_info": ([H, ctypes.POINTER(i64), ctypes.POINTER(i64),
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "cn_profile": ([H, ctypes.c_int], ctypes.c_int),
+        "cn_profile_report": ([H, ctypes.c_char_p, i64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -104,7 +107,8 @@ def lib():
 EXPORTED = ["cn_check_layout", "cn_create", "cn_destroy", "cn_status_string", "cn_reserve", "cn_tridiag_solve",
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
             "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
-            "cn_propagate_adjoint", "cn_handle_info", "cn_tridiag_solve_noalloc"]
+            "cn_propagate_adjoint", "cn_handle_info", "cn_tridiag_solve_noalloc", "cn_profile",
+            "cn_profile_report"]
 
 
 def status_string(st: int) -> str:

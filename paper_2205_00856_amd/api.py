@@ -20,6 +20,7 @@ from ._lib import CnLayout, CnOperator, check
 
 __all__ = ["Layout", "Handle", "handle", "solve", "solve_noalloc", "solve_adjoint", "assemble", "rhs", "step",
            "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune",
+           "profile", "profile_report",
            "propagate_adjoint"]
 
 
@@ -39,6 +40,7 @@ class Layout:
     partition: int = 0
     rows_per_thread: int = 0
     shared_coefficients: bool = False  # uniform batch: all systems use system 0's a, b, c / V, x
+    levels: int = 0  # partition levels before a serial RS stage (0 = automatic nesting)
     _offs_np: Optional[np.ndarray] = field(default=None, repr=False)
 
     @staticmethod
@@ -83,6 +85,7 @@ class Layout:
         L.partition = int(self.partition)
         L.rows_per_thread = int(self.rows_per_thread)
         L.shared_coefficients = 1 if self.shared_coefficients else 0
+        L.levels = int(self.levels)
         return L
 
     def coef_span(self) -> int:
@@ -259,12 +262,13 @@ def assemble(V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
 
 
 def rhs(psi, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dx_per_system=None,
-        layout: Optional[Layout] = None, W=None):
-    """Materialised explicit half-step d = (1 - i dt/2 H) psi (cn_rhs)."""
+        layout: Optional[Layout] = None, W=None, out=None):
+    """Materialised explicit half-step d = (1 - i dt/2 H) psi (cn_rhs), into out if given."""
     L = _layout_for(psi, layout)
     _need(psi, torch.complex128, "psi", L.span())
     _check_op(L, V, xgrid, dx_per_system, W)
-    d = torch.empty_like(psi)
+    d = torch.empty_like(psi) if out is None else out
+    _need(d, torch.complex128, "out", L.span())
     op = _operator(V, dx, dt, xgrid, v_scale, dx_per_system, W)
     h = handle(psi.device.index)
     Lc = L.c()
@@ -314,15 +318,15 @@ def propagate(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0, dx_per_sy
 
 
 def propagate_adjoint(ckpt, g, V, dx, dt, nsteps, K, E=None, xgrid=None, v_scale=1.0, dV=None,
-                      dE=None, seg=None, layout: Optional[Layout] = None):
+                      dE=None, seg=None, layout: Optional[Layout] = None, W=None):
     """Reverse mode of propagate from its checkpoints (cn_propagate_adjoint).  g (in: gradient at
     psi_T, out: gradient at psi_0) is updated in place; dV (float64) accumulates; dE (float64,
-    nsteps) is written when given (needs xgrid)."""
+    nsteps) is written when given (needs xgrid).  W: the absorbing potential of the forward."""
     L = _layout_for(g, layout)
     span = L.span()
     _need(g, torch.complex128, "g", span)
     _need(ckpt, torch.complex128, "ckpt", ((nsteps + K - 1) // K) * span)
-    _check_op(L, V, xgrid, None)
+    _check_op(L, V, xgrid, None, W)
     if seg is None:
         seg = torch.empty((K + 1) * span, dtype=torch.complex128, device=g.device)
     _need(seg, torch.complex128, "seg", (K + 1) * span)
@@ -333,7 +337,7 @@ def propagate_adjoint(ckpt, g, V, dx, dt, nsteps, K, E=None, xgrid=None, v_scale
             raise ValueError("E needs one value per step")
     if dE is not None:
         _need(dE, torch.float64, "dE", nsteps)
-    op = _operator(V, dx, dt, xgrid, v_scale, None)
+    op = _operator(V, dx, dt, xgrid, v_scale, None, W)
     h = handle(g.device.index)
     Lc = L.c()
     Ep = None if Earr is None else Earr.ctypes.data_as(ctypes.c_void_p)
@@ -344,23 +348,42 @@ def propagate_adjoint(ckpt, g, V, dx, dt, nsteps, K, E=None, xgrid=None, v_scale
 
 
 def step_adjoint(psi_n, psi_np1, g_np1, V, dx, dt, E=0.0, xgrid=None, v_scale=1.0, dV=None,
-                 dE_out=None, g_out=None, layout: Optional[Layout] = None):
+                 dE_out=None, g_out=None, layout: Optional[Layout] = None, W=None):
     """One step of the adjoint recursion (cn_step_adjoint).  Returns g_n; accumulates into dV
-    (float64, in place) and writes dE_out[0] when given (needs xgrid)."""
+    (float64, in place) and writes dE_out[0] when given (needs xgrid).  W: absorbing potential."""
     L = _layout_for(psi_n, layout)
     span = L.span()
     for t, nm in ((psi_n, "psi_n"), (psi_np1, "psi_np1"), (g_np1, "g_np1")):
         _need(t, torch.complex128, nm, span)
-    _check_op(L, V, xgrid, None)
+    _check_op(L, V, xgrid, None, W)
     if g_out is None:
         g_out = torch.empty_like(psi_n)
-    op = _operator(V, dx, dt, xgrid, v_scale, None)
+    op = _operator(V, dx, dt, xgrid, v_scale, None, W)
     h = handle(psi_n.device.index)
     Lc = L.c()
     check(_lib.lib().cn_step_adjoint(h.ptr, ctypes.byref(Lc), ctypes.byref(op), float(E),
                                      _ptr(psi_n), _ptr(psi_np1), _ptr(g_np1), _ptr(g_out),
                                      _ptr(dV), _ptr(dE_out), _stream(psi_n)), "cn_step_adjoint")
     return g_out
+
+
+def profile(enable: bool = True, device=None):
+    """Plan log on/off (cn_profile): HIP events around every launch of the following calls."""
+    h = handle(device)
+    check(_lib.lib().cn_profile(h.ptr, 1 if enable else 0), "cn_profile")
+
+
+def profile_report(device=None) -> list:
+    """The logged launches since the last report (cn_profile_report): a list of
+    (label, milliseconds) in launch order."""
+    h = handle(device)
+    buf = ctypes.create_string_buffer(1 << 20)
+    check(_lib.lib().cn_profile_report(h.ptr, buf, 1 << 20), "cn_profile_report")
+    out = []
+    for line in buf.value.decode().splitlines():
+        label, _, ms = line.rpartition(" ms=")
+        out.append((label, float(ms)))
+    return out
 
 
 def get_status(device=None) -> int:

@@ -49,10 +49,12 @@ def cn_solve(a, b, c, d, layout: Optional[api.Layout] = None):
 
 class CNPropagate(torch.autograd.Function):
     """Checkpointed propagation.  E (nsteps field values) and V are float64 tensors; the
-    field enters through xgrid (float64, same length as psi) when given."""
+    field enters through xgrid (float64, same length as psi) when given.  W (float64, or None)
+    is an absorbing potential, V - iW (constant: it receives no gradient)."""
 
     @staticmethod
-    def forward(ctx, psi0, V, E, dx: float, dt: float, xgrid, K: int, v_scale: float = 1.0):
+    def forward(ctx, psi0, V, E, dx: float, dt: float, xgrid, K: int, v_scale: float = 1.0,
+                W=None):
         nsteps = int(E.shape[0]) if E is not None else 0
         if nsteps < 1:
             raise ValueError("CNPropagate needs at least one step (E has one value per step)")
@@ -63,7 +65,8 @@ class CNPropagate(torch.autograd.Function):
         ckpt = torch.empty(nseg * psi0.shape[0], dtype=psi0.dtype, device=psi0.device)
         psi = psi0.detach().clone()
         api.propagate(psi, V.detach(), dx, dt, nsteps, E=Eh, xgrid=xgrid, v_scale=v_scale,
-                      ckpt=ckpt, K=K, layout=L)
+                      ckpt=ckpt, K=K, layout=L, W=W)
+        ctx.W = W
         ctx.save_for_backward(V, xgrid if xgrid is not None else torch.empty(0), ckpt)
         ctx.meta = (Eh, dx, dt, K, v_scale, nsteps, xgrid is not None, E.device, E.dtype)
         return psi
@@ -79,10 +82,10 @@ class CNPropagate(torch.autograd.Function):
         dE = torch.zeros(nsteps, dtype=torch.float64, device=dev) if has_x else None
         g = gT.contiguous().clone()
         api.propagate_adjoint(ckpt, g, V.detach(), dx, dt, nsteps, K, E=Eh, xgrid=xgrid,
-                              v_scale=v_scale, dV=dV, dE=dE)
+                              v_scale=v_scale, dV=dV, dE=dE, W=ctx.W)
         gE = dE.to(device=Edev, dtype=Edt) if has_x else None
-        return g, dV, gE, None, None, None, None, None
+        return g, dV, gE, None, None, None, None, None, None
 
 
-def cn_propagate(psi0, V, E, dx, dt, xgrid=None, K=50, v_scale=1.0):
-    return CNPropagate.apply(psi0, V, E, dx, dt, xgrid, K, v_scale)
+def cn_propagate(psi0, V, E, dx, dt, xgrid=None, K=50, v_scale=1.0, W=None):
+    return CNPropagate.apply(psi0, V, E, dx, dt, xgrid, K, v_scale, W)

@@ -29,9 +29,11 @@ nsk::Tables& nsk::tables() {
     reg_tile_ct(x);
     reg_tile_cn_lo(x);
     reg_tile_cn_hi(x);
+    reg_tile_cnw(x);
     reg_tile_slots(x);
     reg_cols(x);
     reg_pers(x);
+    reg_mrhs(x);
     reg_aux(x);
     return x;
   }();
@@ -51,6 +53,7 @@ const void* const (&g_kern)[kNumCfg][nsk::kNumSrc][nsk::kNumPh] = nsk::tables().
 const void* const (&g_pers)[kNumCfg][nsk::kNumSrc] = nsk::tables().pers;
 const void* const (&g_cols)[kNumColCfg][nsk::kNumSrc][3] = nsk::tables().cols;
 const void* aux_fn(int k) { return nsk::tables().aux[k]; }
+const void* const (&g_mrhs)[kNumCfg][3] = nsk::tables().mrhs;
 
 int col_cfg(int64_t T, int M) {
   for (int i = 0; i < kNumColCfg; ++i)
@@ -105,6 +108,23 @@ bool rev_enabled() {
 }
 int rev_for(int64_t rows) { return (rev_enabled() && rows >= ((int64_t)1 << 21)) ? 1 : 0; }
 
+// one matrix with several right-hand sides through k_tile_mrhs, the matrix loaded once per tile
+// (CN_MRHS=0 turns it off: every right-hand side then has workgroups of its own)
+bool mrhs_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_MRHS");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// Right-hand sides per workgroup of a k_tile_mrhs launch over K tiles of a batch: as many as
+// keep at least 1024 workgroups (four per CU) in the launch.
+int64_t mrhs_per_wg(int64_t K, int64_t batch) {
+  const int64_t groups = std::min<int64_t>(batch, std::max<int64_t>(1, (1024 + K - 1) / K));
+  return (batch + groups - 1) / groups;
+}
+
 // XCD-contiguous order of whole-system workgroups (CN_XCD_REMAP=0 turns it off)
 bool xcd_remap_enabled() {
   static const bool on = [] {
@@ -125,7 +145,17 @@ int single_cfg(int64_t n) {
 }
 
 // ------------------------------------------------------------------------------- plans
-enum class Src { EXPL = nsd::SRC_EXPL, CT = nsd::SRC_EXPL_CT, CN = nsd::SRC_CN };
+enum class Src { EXPL = nsd::SRC_EXPL, CT = nsd::SRC_EXPL_CT, CN = nsd::SRC_CN, CNW = nsd::SRC_CNW };
+
+// steps with an absorbing potential take the fused kernels (CN_ABSORB_FUSED=0 turns them off;
+// the steps then run materialised)
+bool absorb_fused_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_ABSORB_FUSED");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
 
 struct Launch {
   const void* fn;
@@ -164,6 +194,7 @@ struct Knobs {
   int64_t partition = 0;
   int rpt = 0;
   int shared = 0;  // level-1 systems share system 0's coefficients
+  int levels = 0;  // > 0: serial RS stage on the reduced systems left after this many levels
 };
 
 struct Builder {
@@ -242,6 +273,36 @@ std::string cfg_str(int ci) {
   return s;
 }
 
+// The RS stage of Table 1 on the reduced systems of a level, serially (Thomas's elimination, one
+// thread per system): the top of a plan whose nesting depth the caller fixed (cn_layout.levels).
+// bd: the reduced systems (uneven: offsets over the slot rows); x goes to workspace offset o_x.
+void plan_serial_rs(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int level,
+                    int64_t o_sU, int64_t o_sD, int64_t o_x) {
+  const int64_t rows = bd.offs[bd.batch];
+  Launch l;
+  l.fn = aux_fn(nsk::AUX_RS_SERIAL);
+  l.grid = dim3((unsigned)((bd.batch + 63) / 64));
+  l.threads = 64;
+  l.a = KArgs{};
+  l.a.vscale = 1.0;
+  l.a.batch = bd.batch;
+  l.level = level;
+  l.src = nsd::SRC_SLOTS;
+  l.ph = nsd::PH_SINGLE;
+  l.cfg = -1;
+  l.t_offs = B.add_tab(bd.offs.data(), (bd.batch + 1) * sizeof(int64_t));
+  l.o_sU = o_sU;
+  l.o_sD = o_sD;
+  l.o_x = o_x;
+  l.o_oU = B.add_ws(rows * sizeof(cd));  // eliminated super-diagonal c' per row
+  l.o_oD = B.add_ws(rows * sizeof(cd));  // eliminated right-hand side d' per row
+  L.push_back(l);
+  char line[128];
+  snprintf(line, sizeof(line), "L%d serial RS systems=%lld rows=%lld; ", level,
+           (long long)bd.batch, (long long)rows);
+  B.desc += line;
+}
+
 // Appends the launches that solve one level; x goes to the caller (level 1) or to workspace
 // offset o_x.  At level >= 2 the source is the slot arrays at (o_sU, o_sD).
 void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src, int level,
@@ -257,8 +318,8 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   char line[256];
   if (!bd.uneven) {
     const int64_t n = bd.n, batch = bd.batch;
-    if (bd.bs == 1 && batch >= 64 && bd.es >= batch && src != nsd::SRC_SLOTS && cols_enabled() &&
-        !kn.shared) {
+    if (bd.bs == 1 && batch >= 64 && bd.es >= batch && src != nsd::SRC_SLOTS &&
+        src != nsd::SRC_CNW && cols_enabled() && !kn.shared) {
       int cc = -1;
       if (level == 1 && kn.partition > 0) cc = col_cfg(kn.partition, kn.rpt);
       if (cc < 0) cc = col_cfg(64, 16);
@@ -296,7 +357,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       }
       const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
       const int64_t oP = B.add_ws(G * sizeof(cd));
-      const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+      const int64_t oH = nsd::cn_src(src) ? B.add_ws(2 * G * sizeof(cd)) : -1;
       snprintf(line, sizeof(line), "L%d columns multi %s n=%lld batch=%lld tiles=%lld; ", level, cs,
                (long long)n, (long long)batch, (long long)K);
       B.desc += line;
@@ -309,7 +370,10 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       ib.batch = batch;
       ib.offs.resize(batch + 1);
       for (int64_t s2 = 0; s2 <= batch; ++s2) ib.offs[s2] = s2 * K;
-      plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+      if (kn.levels > 0 && level >= kn.levels)
+        plan_serial_rs(B, L, ib, level + 1, oU, oD, oP);
+      else
+        plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
       add_col(nsd::PH_SUBST);
       L.back().a.rev = rev_for(n * batch);
       L.back().o_psi_if = oP;
@@ -322,6 +386,11 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     } else if (n <= kSingleMax && (batch >= 64 || n <= 1024 || level > 1)) {
       ci_single = single_cfg(n);
     }
+    // one matrix, several right-hand sides: k_tile_mrhs launches (grid y = groups of nrhs)
+    auto mrhs_of = [&](int ci) {
+      return (level == 1 && kn.shared && src == nsd::SRC_EXPL && batch >= 2 && mrhs_enabled() &&
+              g_mrhs[ci][nsd::PH_SINGLE] && g_mrhs[ci][nsd::PH_REDUCE] && g_mrhs[ci][nsd::PH_SUBST]);
+    };
     if (ci_single >= 0) {
       const int ci = ci_single;
       KArgs a = base;
@@ -330,6 +399,19 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       a.es = bd.es;
       a.bs = bd.bs;
       a.xcd_remap = xcd_remap_enabled() ? 1 : 0;
+      if (mrhs_of(ci)) {
+        a.xcd_remap = 0;
+        a.batch = batch;
+        a.nrhs = (int)mrhs_per_wg(1, batch);
+        const int64_t groups = (batch + a.nrhs - 1) / a.nrhs;
+        add_launch(L, ci, src, nsd::PH_SINGLE, dim3(1, (unsigned)groups), level, a);
+        L.back().fn = g_mrhs[ci][nsd::PH_SINGLE];
+        set_common(L.back());
+        snprintf(line, sizeof(line), "L%d single %s n=%lld batch=%lld rhs/wg=%d; ", level,
+                 cfg_str(ci).c_str(), (long long)n, (long long)batch, a.nrhs);
+        B.desc += line;
+        return;
+      }
       add_launch(L, ci, src, nsd::PH_SINGLE, dim3(1, (unsigned)batch), level, a);
       set_common(L.back());
       snprintf(line, sizeof(line), "L%d single %s n=%lld batch=%lld; ", level, cfg_str(ci).c_str(),
@@ -342,17 +424,28 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     const int64_t K = (n + T - 1) / T, G = K * batch;
     const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
     const int64_t oP = B.add_ws(G * sizeof(cd));
-    const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
-    const int64_t oH2 = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+    const int64_t oH = nsd::cn_src(src) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+    const int64_t oH2 = nsd::cn_src(src) ? B.add_ws(2 * G * sizeof(cd)) : -1;
     KArgs a = base;
     a.n = n;
     a.ntiles = K;
     a.es = bd.es;
     a.bs = bd.bs;
-    snprintf(line, sizeof(line), "L%d multi %s n=%lld batch=%lld tiles=%lld; ", level,
-             cfg_str(ci).c_str(), (long long)n, (long long)batch, (long long)K);
+    const bool mr = mrhs_of(ci);
+    unsigned gy = (unsigned)batch;
+    if (mr) {
+      a.batch = batch;
+      a.nrhs = (int)mrhs_per_wg(K, batch);
+      gy = (unsigned)((batch + a.nrhs - 1) / a.nrhs);
+      snprintf(line, sizeof(line), "L%d multi %s n=%lld batch=%lld tiles=%lld rhs/wg=%d; ",
+               level, cfg_str(ci).c_str(), (long long)n, (long long)batch, (long long)K, a.nrhs);
+    } else {
+      snprintf(line, sizeof(line), "L%d multi %s n=%lld batch=%lld tiles=%lld; ", level,
+               cfg_str(ci).c_str(), (long long)n, (long long)batch, (long long)K);
+    }
     B.desc += line;
-    add_launch(L, ci, src, nsd::PH_REDUCE, dim3((unsigned)K, (unsigned)batch), level, a);
+    add_launch(L, ci, src, nsd::PH_REDUCE, dim3((unsigned)K, gy), level, a);
+    if (mr) L.back().fn = g_mrhs[ci][nsd::PH_REDUCE];
     set_common(L.back());
     L.back().o_oU = oU;
     L.back().o_oD = oD;
@@ -363,8 +456,12 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     ib.batch = batch;
     ib.offs.resize(batch + 1);
     for (int64_t s = 0; s <= batch; ++s) ib.offs[s] = s * K;
-    plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
-    add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)K, (unsigned)batch), level, a);
+    if (kn.levels > 0 && level >= kn.levels)
+      plan_serial_rs(B, L, ib, level + 1, oU, oD, oP);
+    else
+      plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+    add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)K, gy), level, a);
+    if (mr) L.back().fn = g_mrhs[ci][nsd::PH_SUBST];
     L.back().a.rev = batch == 1 ? rev_for(n) : 0;  // one-dimensional grids only
     set_common(L.back());
     L.back().o_psi_if = oP;
@@ -375,7 +472,8 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   const int64_t batch = bd.batch;
   const int64_t t_offs = B.add_tab(bd.offs.data(), (batch + 1) * sizeof(int64_t));
   int64_t handled = 0;  // systems up to this length went to the persistent launch
-  if (level == 1 && src != nsd::SRC_SLOTS && kn.partition > 0 && persist_enabled()) {
+  if (level == 1 && src != nsd::SRC_SLOTS && src != nsd::SRC_CNW && kn.partition > 0 &&
+      persist_enabled()) {
     // with an explicit partition: one persistent launch, whole systems from a device queue,
     // longest first (configurations without a persistent kernel use T = 1024, M = 4)
     int ci = find_cfg(kn.partition, kn.rpt > 0 ? kn.rpt : 4);
@@ -468,15 +566,19 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   }
   // automatic plan of a caller's uneven batch: the long systems are solved two-pass over
   // 2048-row tiles of 8 rows per lane (measured best for lengths up to 65536)
+  // (with an absorbing potential: 1024-row tiles of 4 rows per lane, the configuration its fused
+  // pass is built for)
   int ci = (level == 1 && kn.partition == 0 && src != nsd::SRC_SLOTS)
-               ? find_cfg(2048, 8)
+               ? (src == nsd::SRC_CNW ? find_cfg(1024, 4) : find_cfg(2048, 8))
                : multi_cfg(nl / (int64_t)large.size(), (int64_t)large.size(), kn, level, src);
   const int64_t T = kCfgs[ci].T();
   std::vector<int64_t> tbase(batch + 1, 0);
   std::vector<int> wgs, wgt;
   for (int64_t s = 0; s < batch; ++s) {
+    // tiles only for the systems of this launch: longer than one tile and not taken by the
+    // persistent launch (an uncounted system's reduced system would be left unwritten)
     const int64_t len = bd.offs[s + 1] - bd.offs[s];
-    const int64_t K = (len > kSingleMax) ? (len + T - 1) / T : 0;
+    const int64_t K = (len > kSingleMax && len > handled) ? (len + T - 1) / T : 0;
     tbase[s + 1] = tbase[s] + K;
   }
   // workgroups of the longest systems first
@@ -492,8 +594,8 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   const int64_t G = tbase[batch];
   const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
   const int64_t oP = B.add_ws(G * sizeof(cd));
-  const int64_t oH = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
-  const int64_t oH2 = (src == nsd::SRC_CN) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+  const int64_t oH = nsd::cn_src(src) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+  const int64_t oH2 = nsd::cn_src(src) ? B.add_ws(2 * G * sizeof(cd)) : -1;
   const int64_t t_tb = B.add_tab(tbase.data(), (batch + 1) * sizeof(int64_t));
   const int64_t t_s = B.add_tab(wgs.data(), wgs.size() * sizeof(int));
   const int64_t t_t = B.add_tab(wgt.data(), wgt.size() * sizeof(int));
@@ -515,7 +617,10 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   ib.uneven = true;
   ib.batch = batch;
   ib.offs = tbase;
-  plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+  if (kn.levels > 0 && level >= kn.levels)
+    plan_serial_rs(B, L, ib, level + 1, oU, oD, oP);
+  else
+    plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
   add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)wgs.size()), level, a);
   set_common(L.back());
   L.back().a.rev = rev_for(nl);
@@ -559,6 +664,13 @@ struct cn_handle_s {
   // of that entry point (their tables live in host memory and are copied into the array)
   char* scratch = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> static_plans;
+  // plan log (cn_profile): HIP events around every launch of run_plan, with a label each
+  bool profiling = false;
+  struct Rec {
+    std::string label;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Rec> recs;
 };
 
 namespace {
@@ -633,6 +745,7 @@ cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
       L->rows_per_thread != 8 && L->rows_per_thread != 16)
     return CN_ERR_INVALID_ARG;
   if (L->shared_coefficients != 0 && L->shared_coefficients != 1) return CN_ERR_INVALID_ARG;
+  if (L->levels < 0 || L->levels > 8) return CN_ERR_INVALID_ARG;
   if (L->offsets && L->shared_coefficients) return CN_ERR_UNSUPPORTED;
   if (L->offsets) {
     if (L->offsets[0] != 0) return CN_ERR_INVALID_ARG;
@@ -657,9 +770,9 @@ cn_status validate(const cn_layout* L, int64_t& rows, int64_t& span) {
 std::string plan_key(const cn_layout* L, int src) {
   std::string k;
   char buf[160];
-  snprintf(buf, sizeof(buf), "%d|%lld|%lld|%lld|%lld|%d|%d|%d|", src, (long long)L->n,
+  snprintf(buf, sizeof(buf), "%d|%lld|%lld|%lld|%lld|%d|%d|%d|%d|", src, (long long)L->n,
            (long long)L->batch, (long long)L->elem_stride, (long long)L->batch_stride,
-           L->partition, L->rows_per_thread, L->shared_coefficients);
+           L->partition, L->rows_per_thread, L->shared_coefficients, L->levels);
   k = buf;
   if (L->offsets) {
     k += "U";
@@ -692,6 +805,7 @@ cn_status build_plan(const cn_layout* L, int src, bool adjoint_ws, Plan& P,
   kn.partition = L->partition;
   kn.rpt = L->rows_per_thread;
   kn.shared = L->shared_coefficients;
+  kn.levels = L->levels;
   if (kn.partition > 0) {
     const bool columns = !L->offsets && L->batch_stride == 1 && L->batch >= 64 &&
                          L->elem_stride >= L->batch && cols_enabled() &&
@@ -705,7 +819,9 @@ cn_status build_plan(const cn_layout* L, int src, bool adjoint_ws, Plan& P,
   plan_level(B, P.L, bd, src, 1, -1, -1, -1, kn);
   P.span = span;
   P.rows = rows;
-  if (src == nsd::SRC_CN && adjoint_ws) {
+  for (const Launch& l : P.L)
+    if (!l.fn) return CN_ERR_UNSUPPORTED;  // a configuration without kernels for this source
+  if (nsd::cn_src(src) && adjoint_ws) {
     P.o_aux = B.add_ws(rows * sizeof(cd) + 16);
     P.nparts = (rows + 255) / 256;
     P.o_part = B.add_ws((rows / 64 + 64) * sizeof(double));
@@ -782,6 +898,8 @@ struct UserArgs {
   double* acc_part = nullptr;
   double acc_tau = 0.0;
   int acc_half = 0;
+  const double* W = nullptr;  // absorbing potential (SRC_CNW)
+  double wscale = 1.0;
 };
 
 // Kernel arguments of one launch of a plan for the caller's arrays u and workspace ws.
@@ -808,6 +926,8 @@ KArgs plan_args(cn_handle_t h, const Launch& l, const UserArgs& u, char* ws) {
     a.acc_part = u.acc_part;
     a.acc_tau = u.acc_tau;
     a.acc_half = u.acc_half;
+    a.Wabs = u.W;
+    a.wscale = u.wscale;
   }
   a.x = (l.o_x >= 0) ? (cd*)(ws + l.o_x) : u.x;
   if (l.o_sU >= 0) a.sU = (const cd*)(ws + l.o_sU);
@@ -827,13 +947,39 @@ cn_status launch_k(const void* fn, const Launch& l, KArgs& a, hipStream_t s) {
   return CN_OK;
 }
 
+const char* phase_name(int ph) {
+  switch (ph) {
+    case nsd::PH_SINGLE: return "single";
+    case nsd::PH_REDUCE: return "reduce";
+    case nsd::PH_SUBST: return "subst";
+    case nsd::PH_FUSE: return "fuse";
+  }
+  return "persistent";
+}
+
 cn_status run_plan(cn_handle_t h, Plan* P, const UserArgs& u, hipStream_t s,
                    void* ws_base = nullptr) {
   char* ws = (char*)(ws_base ? ws_base : h->ws);
+  const bool log = h->profiling && !capturing(s);
   for (const Launch& l : P->L) {
     KArgs a = plan_args(h, l, u, ws);
+    cn_handle_s::Rec r;
+    if (log) {
+      char lab[160];
+      snprintf(lab, sizeof(lab), "L%d %s %s grid=%ux%u threads=%d", l.level,
+               l.fn == aux_fn(nsk::AUX_RS_SERIAL) ? "serial-RS" : phase_name(l.ph),
+               l.cfg >= 0 ? cfg_str(l.cfg).c_str() : "-", l.grid.x, l.grid.y, l.threads);
+      r.label = lab;
+      HIP_TRY(hipEventCreate(&r.e0));
+      HIP_TRY(hipEventCreate(&r.e1));
+      HIP_TRY(hipEventRecord(r.e0, s));
+    }
     cn_status st = launch_k(l.fn, l, a, s);
     if (st != CN_OK) return st;
+    if (log) {
+      HIP_TRY(hipEventRecord(r.e1, s));
+      h->recs.push_back(r);
+    }
   }
   return CN_OK;
 }
@@ -853,7 +999,7 @@ FusePlan fuse_plan(const Plan* P) {
   for (int i = 0; i < (int)P->L.size(); ++i) {
     const Launch& l = P->L[i];
     if (l.level == 1) {
-      if (l.cfg < 0 || l.src != nsd::SRC_CN) return f;
+      if (l.cfg < 0 || !nsd::cn_src(l.src) || !g_kern[l.cfg][l.src][nsd::PH_FUSE]) return f;
       if (l.ph == nsd::PH_SINGLE && l.fn == g_kern[l.cfg][l.src][nsd::PH_SINGLE] && f.red < 0) {
         f.singles.push_back(i);
       } else if (l.ph == nsd::PH_REDUCE && f.red < 0 && l.o_hout2 >= 0 &&
@@ -940,7 +1086,7 @@ cn_status run_chain(cn_handle_t h, Plan* P, const FusePlan& f, int64_t nst, cons
       a.oU = (cd*)(ws + R.o_oU);
       a.oD = (cd*)(ws + R.o_oD);
       a.E_next = vn.E_mat;
-      if ((st = launch_k(g_kern[S.cfg][nsd::SRC_CN][nsd::PH_FUSE], S, a, s)) != CN_OK) return st;
+      if ((st = launch_k(g_kern[S.cfg][S.src][nsd::PH_FUSE], S, a, s)) != CN_OK) return st;
       if (after && (st = after(i)) != CN_OK) return st;
       if ((st = mids(H[(i + 1) & 1], vn)) != CN_OK) return st;
       v = vn;
@@ -960,6 +1106,7 @@ nsd::AuxArgs aux_from(const cn_layout* L, const Plan* P) {
   x.bs = L->batch_stride;
   x.total = P->rows;
   x.vscale = 1.0;
+  x.wscale = 1.0;
   return x;
 }
 
@@ -1052,6 +1199,43 @@ cn_status absorbing_step(cn_handle_t h, const cn_layout* L, const cn_operator* o
   return run_plan(h, Pe, u, s);
 }
 
+// The plan of a Crank-Nicolson step for this operator: SRC_CN for real potentials, SRC_CNW (the
+// fused kernels with the absorbing term) when the potential has one.  *fused is false when an
+// absorbing step has to run materialised instead (fused kernels turned off, or a layout whose
+// configuration they are not built for); P is then null.
+cn_status cn_plan(cn_handle_t h, const cn_layout* L, const cn_operator* op, hipStream_t s,
+                  Plan** P, bool* fused) {
+  *P = nullptr;
+  *fused = true;
+  if (!op->absorb) return get_plan(h, L, nsd::SRC_CN, s, P);
+  if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
+  if (absorb_fused_enabled()) {
+    const cn_status st = get_plan(h, L, nsd::SRC_CNW, s, P);
+    if (st != CN_ERR_UNSUPPORTED) return st;
+    *P = nullptr;
+  }
+  *fused = false;
+  return CN_OK;
+}
+
+// Step arguments of a Crank-Nicolson operator (state in, state out, field E on both sides).
+UserArgs cn_args(const cn_operator* op, double E, const cd* in, cd* out) {
+  UserArgs u;
+  u.psi = in;
+  u.V = op->V;
+  u.xg = op->xgrid;
+  u.dxs = op->dx_per_system;
+  u.vscale = op->v_scale;
+  u.E_mat = E;
+  u.E_rhs = E;
+  u.dx = op->dx;
+  u.dt = op->dt;
+  u.x = out;
+  u.W = op->absorb;
+  u.wscale = 1.0;
+  return u;
+}
+
 }  // namespace
 
 // =============================================================================== C ABI
@@ -1111,6 +1295,10 @@ cn_status cn_destroy(cn_handle_t h) {
   if (h->seg2) (void)hipFree(h->seg2);
   if (h->mat) (void)hipFree(h->mat);
   for (void* p : h->retired) (void)hipFree(p);
+  for (auto& r : h->recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
   for (hipEvent_t e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -1122,12 +1310,14 @@ cn_status cn_destroy(cn_handle_t h) {
 cn_status cn_reserve(cn_handle_t h, const cn_layout* L) {
   if (!h) return CN_ERR_INVALID_ARG;
   Plan* P = nullptr;
-  for (int src : {nsd::SRC_EXPL, nsd::SRC_EXPL_CT, nsd::SRC_CN}) {
+  size_t ws2 = 0;  // the second workspace of the reverse mode's fused chain
+  for (int src : {nsd::SRC_EXPL, nsd::SRC_EXPL_CT, nsd::SRC_CN, nsd::SRC_CNW}) {
     cn_status st = get_plan(h, L, src, nullptr, &P);
+    if (st == CN_ERR_UNSUPPORTED && src == nsd::SRC_CNW) continue;
     if (st != CN_OK) return st;
+    if (nsd::cn_src(src)) ws2 = std::max(ws2, P->ws_bytes);
   }
-  // the second workspace of the reverse mode's fused chain (P is the Crank-Nicolson plan)
-  if (h->ws2_size < P->ws_bytes) return regrow(h, &h->ws2, &h->ws2_size, P->ws_bytes);
+  if (h->ws2_size < ws2) return regrow(h, &h->ws2, &h->ws2_size, ws2);
   return CN_OK;
 }
 
@@ -1266,23 +1456,12 @@ cn_status cn_step(cn_handle_t h, const cn_layout* L, const cn_operator* op, doub
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (op->absorb)
-    return absorbing_step(h, L, op, E, true, (const cd*)psi_in, (cd*)psi_out, s);
   Plan* P = nullptr;
-  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  bool fused = true;
+  st = cn_plan(h, L, op, s, &P, &fused);
   if (st != CN_OK) return st;
-  UserArgs u;
-  u.psi = (const cd*)psi_in;
-  u.V = op->V;
-  u.xg = op->xgrid;
-  u.dxs = op->dx_per_system;
-  u.vscale = op->v_scale;
-  u.E_mat = E;
-  u.E_rhs = E;
-  u.dx = op->dx;
-  u.dt = op->dt;
-  u.x = (cd*)psi_out;
-  return run_plan(h, P, u, s);
+  if (!fused) return absorbing_step(h, L, op, E, true, (const cd*)psi_in, (cd*)psi_out, s);
+  return run_plan(h, P, cn_args(op, E, (const cd*)psi_in, (cd*)psi_out), s);
 }
 
 cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op, int64_t nsteps,
@@ -1293,9 +1472,12 @@ cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op,
   if (st != CN_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   Plan* P = nullptr;
-  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  bool fused = true;
+  st = cn_plan(h, L, op, s, &P, &fused);
   if (st != CN_OK) return st;
-  if (op->absorb) {
+  if (!fused) {
+    st = get_plan(h, L, nsd::SRC_CN, s, &P);
+    if (st != CN_OK) return st;
     for (int64_t k = 0; k < nsteps; ++k) {
       if (ckpt && k % K == 0)
         HIP_TRY(hipMemcpyAsync((cd*)ckpt + (k / K) * P->span, psi, P->span * sizeof(cd),
@@ -1307,15 +1489,7 @@ cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op,
     }
     return CN_OK;
   }
-  UserArgs u;
-  u.psi = (const cd*)psi;
-  u.V = op->V;
-  u.xg = op->xgrid;
-  u.dxs = op->dx_per_system;
-  u.vscale = op->v_scale;
-  u.dx = op->dx;
-  u.dt = op->dt;
-  u.x = (cd*)psi;
+  UserArgs u = cn_args(op, 0.0, (const cd*)psi, (cd*)psi);
   if (nsteps >= 2 && fuse_enabled()) {
     const FusePlan f = fuse_plan(P);
     if (f.ok) {
@@ -1353,27 +1527,23 @@ cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* 
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
   if (dE_partial && !op->xgrid) return CN_ERR_INVALID_ARG;
-  if (op->absorb) return CN_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   Plan* P = nullptr;
-  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  bool fused = true;
+  st = cn_plan(h, L, op, s, &P, &fused);
   if (st != CN_OK) return st;
+  if (!fused) return CN_ERR_UNSUPPORTED;
   cd* lam = (cd*)((char*)h->ws + P->o_aux);
-  // lambda = T^{-H} g: T^H = 1 - i tau H is the CN matrix with dt -> -dt
-  UserArgs u;
+  // lambda = T^{-H} g: T^H = 1 + tau W - i tau (...) is the CN matrix with dt -> -dt and
+  // W -> -W (for a real potential simply dt -> -dt)
+  UserArgs u = cn_args(op, E, (const cd*)g_np1, lam);
   u.rhs = (const cd*)g_np1;
-  u.psi = (const cd*)g_np1;
-  u.V = op->V;
-  u.xg = op->xgrid;
-  u.dxs = op->dx_per_system;
-  u.vscale = op->v_scale;
-  u.E_mat = u.E_rhs = E;
-  u.dx = op->dx;
   u.dt = -op->dt;
-  u.x = lam;
+  u.wscale = -1.0;
   st = run_plan(h, P, u, s);
   if (st != CN_OK) return st;
-  // g_n = T lambda = (1 + i tau H) lambda: the explicit half-step with dt -> -dt
+  // g_n = B^H lambda with B = 1 - i tau H: the explicit half-step with dt -> -dt and W -> -W
+  // (for a real potential B^H = T = 1 + i tau H)
   nsd::AuxArgs X = aux_from(L, P);
   X.offs = dev_offsets(P);
   X.V = op->V;
@@ -1383,6 +1553,8 @@ cn_status cn_step_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* 
   X.dx = op->dx;
   X.dxs = op->dx_per_system;
   X.dt = -op->dt;
+  X.W = op->absorb;
+  X.wscale = -1.0;
   X.psi = lam;
   X.d = (cd*)g_n;
   st = launch_aux(aux_fn(nsk::AUX_RHS), P->rows, X, s);
@@ -1500,12 +1672,13 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   if (L->offsets) return CN_ERR_UNSUPPORTED;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
-  if (op->absorb) return CN_ERR_UNSUPPORTED;
   if (dE && !op->xgrid) return CN_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   Plan* P = nullptr;
-  st = get_plan(h, L, nsd::SRC_CN, s, &P);
+  bool fused = true;
+  st = cn_plan(h, L, op, s, &P, &fused);
   if (st != CN_OK) return st;
+  if (!fused) return CN_ERR_UNSUPPORTED;
   cd* segs = (cd*)seg;
   const int64_t span = P->span;
   // dE: every step of a segment writes its row of per-tile partials; one launch per segment
@@ -1537,31 +1710,12 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
                            hipMemcpyDeviceToDevice, st));
     if (fzr.ok && ws && k1 - k0 >= 2) {
       auto rargs = [&](int64_t i) {
-        UserArgs u;
-        u.psi = buf + i * span;
-        u.x = buf + (i + 1) * span;
-        u.V = op->V;
-        u.xg = op->xgrid;
-        u.dxs = op->dx_per_system;
-        u.vscale = op->v_scale;
-        u.dx = op->dx;
-        u.dt = op->dt;
-        u.E_mat = u.E_rhs = Ek(k0 + i);
-        return u;
+        return cn_args(op, Ek(k0 + i), buf + i * span, buf + (i + 1) * span);
       };
       return run_chain(h, P, fzr, k1 - k0, rargs, nullptr, nullptr, st, ws);
     }
     for (int64_t k = k0; k < k1; ++k) {
-      UserArgs u;
-      u.psi = buf + (k - k0) * span;
-      u.x = buf + (k - k0 + 1) * span;
-      u.V = op->V;
-      u.xg = op->xgrid;
-      u.dxs = op->dx_per_system;
-      u.vscale = op->v_scale;
-      u.dx = op->dx;
-      u.dt = op->dt;
-      u.E_mat = u.E_rhs = Ek(k);
+      const UserArgs u = cn_args(op, Ek(k), buf + (k - k0) * span, buf + (k - k0 + 1) * span);
       cn_status r = run_plan(h, P, u, st, ws);
       if (r != CN_OK) return r;
     }
@@ -1594,26 +1748,19 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   hipEvent_t start = h->ev[0], rec_done[2] = {h->ev[1], h->ev[2]},
              adj_done[2] = {h->ev[3], h->ev[4]};
   // The recursion runs on g in place, step k = nsteps-1 .. 0 (chain step i = nsteps-1-k):
-  //   g_k = T_k lambda_k with lambda_k = T_k^{-H} g_{k+1}, i.e.
-  //   g_k = (1 - i tau H_k)^{-1} (1 + i tau H_k) g_{k+1},
-  // a CN step with dt -> -dt and E_k on both sides (the two factors commute), and
-  //   lambda_k = (g_k + g_{k+1}) / 2   (sum of (1 - i tau H_k) lambda_k = g_{k+1} and
-  //                                      (1 + i tau H_k) lambda_k = g_k),
+  //   g_k = B_k^H lambda_k with lambda_k = T_k^{-H} g_{k+1}, i.e.
+  //   g_k = T_k^{-H} B_k^H g_{k+1}  (the two factors commute: B_k = 2 - T_k),
+  // a CN step with dt -> -dt (and W -> -W: T_k^H = 1 + tau W - i tau (...), B_k^H = 1 - tau W +
+  // i tau (...)) and E_k on both sides; for a real potential T_k^H = B_k, B_k^H = T_k, and
+  //   lambda_k = (g_k + g_{k+1}) / 2   (T_k^H + B_k^H = 2),
   // which the store of step k forms for the accumulation.  g_N is the gradient at the final
   // state; g_0, the result, is the gradient at the initial one.
   auto args = [&](int64_t i) {
     const int64_t k = nsteps - 1 - i, sg = k / K, k0 = k0_of(sg);
     const cd* buf = buf_of(sg);
-    UserArgs u;
-    u.psi = (const cd*)g;
-    u.x = (cd*)g;
-    u.V = op->V;
-    u.xg = op->xgrid;
-    u.dxs = op->dx_per_system;
-    u.vscale = op->v_scale;
-    u.dx = op->dx;
+    UserArgs u = cn_args(op, Ek(k), (const cd*)g, (cd*)g);
     u.dt = -op->dt;
-    u.E_mat = u.E_rhs = Ek(k);
+    u.wscale = -1.0;
     u.acc_pa = buf + (k - k0) * span;
     u.acc_pb = buf + (k - k0 + 1) * span;
     u.acc_dV = dV_accum;
@@ -1681,6 +1828,31 @@ cn_status cn_handle_info(cn_handle_t h, int64_t* device_bytes, int64_t* retired_
   if (retired_buffers) *retired_buffers = (int64_t)h->retired.size();
   if (captured) *captured = h->captured ? 1 : 0;
   return CN_OK;
+}
+
+cn_status cn_profile(cn_handle_t h, int enable) {
+  if (!h) return CN_ERR_INVALID_ARG;
+  h->profiling = enable != 0;
+  return CN_OK;
+}
+
+cn_status cn_profile_report(cn_handle_t h, char* buf, int64_t buflen) {
+  if (!h || !buf || buflen < 1) return CN_ERR_INVALID_ARG;
+  std::string out;
+  cn_status st = CN_OK;
+  for (auto& r : h->recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+      st = CN_ERR_HIP;
+    char line[224];
+    snprintf(line, sizeof(line), "%s ms=%.6f\n", r.label.c_str(), (double)ms);
+    out += line;
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  h->recs.clear();
+  snprintf(buf, (size_t)buflen, "%s", out.c_str());
+  return st;
 }
 
 cn_status cn_get_status(cn_handle_t h, cn_stream_t stream) {

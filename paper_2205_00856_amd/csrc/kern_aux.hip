@@ -40,7 +40,7 @@ __global__ void k_assemble(AuxArgs A) {
   const double tau = 0.5 * A.dt, idx2 = 1.0 / (dx * dx), kap = tau * 0.5 * idx2;
   const double v = A.vscale * A.V[e] + (A.xg ? A.xg[e] * A.E : 0.0);
   // with the absorbing term -iW in H the diagonal of 1 + i tau H gains + tau W
-  A.a[e] = mk(A.W ? fma(tau, A.W[e], 1.0) : 1.0, tau * (idx2 + v));
+  A.a[e] = mk(A.W ? fma(tau, A.wscale * A.W[e], 1.0) : 1.0, tau * (idx2 + v));
   A.b[e] = mk(0.0, (r > 0) ? -kap : 0.0);
   A.c[e] = mk(0.0, (r < n - 1) ? -kap : 0.0);
 }
@@ -58,7 +58,7 @@ __global__ void k_rhs(AuxArgs A) {
   const cd h = csel(r < n - 1, A.psi[(r < n - 1) ? e + st : e], czero());
   const cd s = cadd(l, h);
   // the diagonal of 1 - i tau H is 1 - tau W - i w (with the absorbing term, not T^dagger's)
-  const double f = A.W ? fma(-tau, A.W[e], 1.0) : 1.0;
+  const double f = A.W ? fma(-tau, A.wscale * A.W[e], 1.0) : 1.0;
   const cd q = A.W ? mk(f * p.x, f * p.y) : p;
   A.d[e] = mk(fma(w, p.y, fma(-kap, s.y, q.x)), fma(-w, p.x, fma(kap, s.x, q.y)));
 }
@@ -116,6 +116,52 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* part, int64_
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// RS stage (Table 1) on whole reduced systems, serially: thread s takes reduced system s (rows
+// offs[s] .. offs[s+1]-1 of the slot arrays; row k has sub-diagonal DB_{k-1}, diagonal UA_k +
+// DA_{k-1}, super-diagonal UC_k and right-hand side UD_k + DD_{k-1}, plus the deferred left
+// neighbour term i kap psi_{J-1} of a fused pass when ud_halo is set) and solves it by Thomas's
+// elimination: c'_k = c_k / m_k, d'_k = (d_k - b_k d'_{k-1}) / m_k with m_k = a_k - b_k c'_{k-1},
+// then x_k = d'_k - c'_k x_{k+1}.  c' and d' go to oU and oD; x to A.x.
+__global__ __launch_bounds__(64) void k_rs_serial(KArgs A) {
+  const int64_t s = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (s >= A.batch) return;
+  const int64_t o0 = A.offs[s], n = A.offs[s + 1] - o0;
+  if (n <= 0) return;
+  const cd zero = czero();
+  double kap = 0.0;
+  if (A.ud_halo) kap = cn_kappa(A.dt, A.dxs ? A.dxs[s] : A.dx);
+  cd cprev = zero, dprev = zero;
+  bool bad = false;
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t g = o0 + k;
+    cd a = A.sU[3 * g], c = A.sU[3 * g + 1], d = A.sU[3 * g + 2], b = zero;
+    if (k > 0) {
+      b = A.sD[3 * (g - 1)];
+      a = cadd(a, A.sD[3 * (g - 1) + 1]);
+      d = cadd(d, A.sD[3 * (g - 1) + 2]);
+      if (A.ud_halo) {
+        const cd h = A.ud_halo[2 * (g - 1) + 1];
+        d = cadd(d, mk(-kap * h.y, kap * h.x));
+      }
+    }
+    if (k == n - 1) c = zero;
+    const cd m = csub(a, cmul(b, cprev));
+    const cd im = crecip(m);
+    cprev = cmul(c, im);
+    dprev = cmul(csub(d, cmul(b, dprev)), im);
+    A.oU[g] = cprev;
+    A.oD[g] = dprev;
+  }
+  cd x = zero;
+  for (int64_t k = n - 1; k >= 0; --k) {
+    const int64_t g = o0 + k;
+    x = csub(A.oD[g], cmul(A.oU[g], x));
+    A.x[g] = x;
+    bad |= !cfinite(x);
+  }
+  if (bad) atomicOr(A.status, 1);
+}
+
 }  // namespace nsd
 
 namespace nsk {
@@ -125,5 +171,6 @@ void reg_aux(Tables& t) {
   t.aux[AUX_SOLVE_GRADS] = (const void*)&nsd::k_solve_grads;
   t.aux[AUX_ADJ_ACCUM] = (const void*)&nsd::k_adj_accum;
   t.aux[AUX_SUM_PARTIALS] = (const void*)&nsd::k_sum_partials;
+  t.aux[AUX_RS_SERIAL] = (const void*)&nsd::k_rs_serial;
 }
 }  // namespace nsk

@@ -30,6 +30,7 @@ enum AuxKernel : int {
   AUX_SOLVE_GRADS,
   AUX_ADJ_ACCUM,
   AUX_SUM_PARTIALS,
+  AUX_RS_SERIAL,
   kNumAux
 };
 
@@ -37,6 +38,7 @@ struct Tables {
   const void* tile[kNumCfg][kNumSrc][kNumPh];
   const void* pers[kNumCfg][kNumSrc];
   const void* cols[kNumColCfg][kNumSrc][3];
+  const void* mrhs[kNumCfg][3];  // one matrix, several right-hand sides (explicit source)
   const void* aux[kNumAux];
 };
 
@@ -47,9 +49,11 @@ void reg_tile_expl(Tables& t);
 void reg_tile_ct(Tables& t);
 void reg_tile_cn_lo(Tables& t);
 void reg_tile_cn_hi(Tables& t);
+void reg_tile_cnw(Tables& t);
 void reg_tile_slots(Tables& t);
 void reg_cols(Tables& t);
 void reg_pers(Tables& t);
+void reg_mrhs(Tables& t);
 void reg_aux(Tables& t);
 
 template <int M, int W>

@@ -12,8 +12,13 @@ enum Src : int {
   SRC_EXPL = 0,     // explicit a, b, c, d arrays
   SRC_EXPL_CT = 1,  // explicit arrays, conjugate-transposed matrix T^H (adjoint solve)
   SRC_CN = 2,       // Crank-Nicolson operator assembled in-kernel from V, dx, dt (+ x E)
-  SRC_SLOTS = 3     // reduced system of the level below, read from its two slot arrays
+  SRC_SLOTS = 3,    // reduced system of the level below, read from its two slot arrays
+  SRC_CNW = 4       // Crank-Nicolson operator with an absorbing potential, v - i W (H not
+                    // Hermitian): T's diagonal 1 + tau W + i tau (...), explicit side 1 - tau W
+                    // - i tau (...), off-diagonals -i kappa and +i kappa as in SRC_CN
 };
+// sources whose rows are the Crank-Nicolson operator assembled in-kernel
+__host__ __device__ constexpr bool cn_src(int S) { return S == SRC_CN || S == SRC_CNW; }
 enum Phase : int {
   PH_SINGLE = 0,  // the tile holds the whole system: reduce, RS, SS in one pass
   PH_REDUCE = 1,  // first pass of a multi-tile system: reduce, write the tile's slots
@@ -70,11 +75,16 @@ struct KArgs {
   double acc_tau;
   int acc_half;           // lambda = (x + the value x overwrites) / 2 instead of x (reverse
                           // recursion on g, where lambda_k = (g_k + g_{k+1}) / 2)
-  int64_t batch;          // uniform batch size (column kernel)
+  int64_t batch;          // uniform batch size (column kernel, several right-hand sides)
+  int nrhs;               // k_tile_mrhs: right-hand sides per workgroup
   int cshared;            // uniform batch: every system reads the coefficients (a, b, c or V,
                           // xgrid) of system 0 (several right-hand sides of one matrix)
   int rev;                // workgroups take their tiles in reverse launch order, by rounds of 8
                           // (second pass: the tiles the first pass read last are still cached)
+  // SRC_CNW: absorbing potential W (layout of V) and its factor; the potential is
+  // v - i wscale W (wscale = -1 with dt -> -dt gives the conjugate-transposed operators)
+  const double* Wabs;
+  double wscale;
 };
 
 struct Geo {
@@ -209,7 +219,7 @@ __device__ __forceinline__ void transpose_in(T* buf, int lane, const T (&v)[M], 
 
 // ------------------------------------------------------------------ Crank-Nicolson rows
 // Raw coalesced loads of one wavefront's rows (state or given right-hand side, V, xgrid).
-template <int M, bool XG>
+template <int M, bool XG, bool WA = false>
 struct CnRaw {
   cd p[M];
   cd hp;
@@ -217,17 +227,20 @@ struct CnRaw {
   double hv;
   double x[XG ? M : 1];
   double hx;
+  double w[WA ? M : 1];  // absorbing potential (SRC_CNW)
+  double hw;
 };
 
-template <int M, bool XG, bool IN>
+template <int M, bool XG, bool IN, bool WA>
 __device__ __forceinline__ void cn_fetch(const KArgs& A, const Geo& G, int64_t w0, int lane,
-                                         CnRaw<M, XG>& r) {
+                                         CnRaw<M, XG, WA>& r) {
   const cd* src = (A.rhs ? A.rhs : A.psi) + G.base;
   stage_fetch<M, IN>(src, G.es, w0, G.n, lane, czero(), r.p, r.hp);
   stage_fetch<M, IN>(A.V + G.cbase, G.es, w0, G.n, lane, 0.0, r.v, r.hv);
   if constexpr (XG) {
     if (A.xg) stage_fetch<M, IN>(A.xg + G.cbase, G.es, w0, G.n, lane, 0.0, r.x, r.hx);
   }
+  if constexpr (WA) stage_fetch<M, IN>(A.Wabs + G.cbase, G.es, w0, G.n, lane, 0.0, r.w, r.hw);
 }
 
 // Magnitude of the off-diagonals of T = 1 + i tau H: tau / (2 dx^2) with tau = dt / 2.
@@ -239,12 +252,14 @@ __device__ __forceinline__ double cn_kappa(double dt, double dx) {
 // fused into the reduction (Sec. 5.3).  The off-diagonals are -i kappa (pure imaginary).
 // vp holds psi at rows J-1 .. J+M of this lane (zero outside the system), vv and xv hold V and
 // xgrid at the same rows (only J .. J+M-1 are read).
-template <int M, bool IN>
+// With WA (SRC_CNW) wv holds the absorbing potential at the same rows: T's diagonal gains
+// + tau W and the explicit side's - tau W.
+template <int M, bool IN, bool WA = false>
 __device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx, int64_t J,
                                         const cd (&vp)[M + 2], const double (&vv)[M + 2],
                                         const double (&xv)[M + 2], double Em, double Er,
                                         bool given, cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M],
-                                        cd (&Dr)[M], cd& bK) {
+                                        cd (&Dr)[M], cd& bK, const double* wv = nullptr) {
   const int64_t n = G.n;
   const double tau = 0.5 * A.dt;
   const double idx2 = 1.0 / (dx * dx);
@@ -255,7 +270,9 @@ __device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx,
     const int64_t r = J + j;
     const bool ok = row_in<IN>(r, n);
     const double vm = fma(xv[j + 1], Em, A.vscale * vv[j + 1]);
-    Ar[j] = mk(1.0, ok ? tau * (idx2 + vm) : 0.0);
+    double tw = 0.0;  // tau W (SRC_CNW)
+    if constexpr (WA) tw = ok ? tau * (A.wscale * wv[j + 1]) : 0.0;
+    Ar[j] = mk(WA ? 1.0 + tw : 1.0, ok ? tau * (idx2 + vm) : 0.0);
     Br[j] = mk(0.0, (ok && row_pos<IN>(r)) ? -kap : 0.0);
     Cr[j] = mk(0.0, (ok && row_notlast<IN>(r, n)) ? -kap : 0.0);
     if (given) {
@@ -264,15 +281,20 @@ __device__ __forceinline__ void cn_rows(const KArgs& A, const Geo& G, double dx,
       const double w = tau * (idx2 + fma(xv[j + 1], Er, A.vscale * vv[j + 1]));
       const cd p = vp[j + 1];
       const cd s = cadd(vp[j], vp[j + 2]);
-      Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
+      if constexpr (WA) {
+        Dr[j] = csel(ok, mk(fma(-tw, p.x, fma(w, p.y, fma(-kap, s.y, p.x))),
+                            fma(-tw, p.y, fma(-w, p.x, fma(kap, s.x, p.y)))), zero);
+      } else {
+        Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s.y, p.x)), fma(-w, p.x, fma(kap, s.x, p.y))), zero);
+      }
     }
   }
   bK = mk(0.0, row_in<IN>(J + M, n) ? -kap : 0.0);
 }
 
-template <int M, int W, int PH, bool XG, bool IN>
+template <int M, int W, int PH, bool XG, bool IN, bool WA = false>
 __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
-                                         int64_t J, int lane, int wave, CnRaw<M, XG>& raw,
+                                         int64_t J, int lane, int wave, CnRaw<M, XG, WA>& raw,
                                          cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
                                          cd& bK, cd& first_state, cd& last_state,
                                          double* ayn) {
@@ -299,9 +321,11 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
 #pragma unroll
     for (int j = 0; j < M + 2; ++j) xv[j] = 0.0;
   }
+  double wv[WA ? M + 2 : 1];
+  if constexpr (WA) transpose_in<M>(bufd, lane, raw.w, raw.hw, wv);
   const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
-  cn_rows<M, IN>(A, G, dx, J, vp, vv, xv, A.E_mat, A.E_rhs, A.rhs != nullptr, Ar, Br, Cr, Dr,
-                 bK);
+  cn_rows<M, IN, WA>(A, G, dx, J, vp, vv, xv, A.E_mat, A.E_rhs, A.rhs != nullptr, Ar, Br, Cr,
+                     Dr, bK, WA ? wv : nullptr);
   first_state = vp[1];
   last_state = vp[M];
   if (ayn) {
@@ -312,6 +336,12 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
     for (int j = 0; j < M; ++j) {
       const double t = tau * (idx2 + fma(xv[j + 1], A.E_next, A.vscale * vv[j + 1]));
       ayn[j] = row_in<IN>(J + j, G.n) ? t : 0.0;
+    }
+    // SRC_CNW: tau W of the next step after the M imaginary parts
+    if constexpr (WA) {
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        ayn[M + j] = row_in<IN>(J + j, G.n) ? tau * (A.wscale * wv[j + 1]) : 0.0;
     }
   }
 }
@@ -360,11 +390,12 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
     else
       bK = csel(row_in<IN>(K, n), cconj(vc[M]), zero);
     first_state = last_state = zero;
-  } else if constexpr (SRC == SRC_CN) {
-    CnRaw<M, true> raw;
-    cn_fetch<M, true, IN>(A, G, w0, lane, raw);
-    cn_build<M, W, PH, true, IN>(A, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr, bK,
-                                 first_state, last_state, ayn);
+  } else if constexpr (cn_src(SRC)) {
+    constexpr bool WA = SRC == SRC_CNW;
+    CnRaw<M, true, WA> raw;
+    cn_fetch<M, true, IN, WA>(A, G, w0, lane, raw);
+    cn_build<M, W, PH, true, IN, WA>(A, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr, bK,
+                                     first_state, last_state, ayn);
   } else {  // SRC_SLOTS: row k of the reduced system = U slot of tile k + D slot of tile k-1
     const cd zero = czero();
 #pragma unroll
@@ -455,7 +486,7 @@ __device__ __forceinline__ void store_tile(const KArgs& A, const Geo& G, TileSme
   for (int j = 0; j < M; ++j) buf[S::addr(lane * M + j + 1)] = x[j];
   wave_sync();
   cd* g = A.x + G.base;
-  const bool acc = (SRC == SRC_CN) && A.acc_pa != nullptr;
+  const bool acc = cn_src(SRC) && A.acc_pa != nullptr;
   double part = 0.0;
   // recompute the row addresses here instead of keeping those of the loads alive across the
   // whole tile (the empty asm hides that they are equal)
@@ -548,7 +579,9 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
   constexpr int PL = (PH == PH_FUSE) ? PH_SUBST : PH;  // the rows are those of a PH_SUBST pass
-  double ayn[M];  // PH_FUSE: diagonal of the next step, from this pass's loads of V and xgrid
+  // PH_FUSE: diagonal of the next step, from this pass's loads of V and xgrid (imaginary parts;
+  // SRC_CNW: then tau W, the real parts less one)
+  double ayn[SRC == SRC_CNW ? 2 * M : M];
   double* ayp = (PH == PH_FUSE) ? ayn : nullptr;
   // wavefront-uniform choice between the interior path and the general one
   if (SRC != SRC_SLOTS && w0 >= 1 && G.n >= w0 + 64 * M + 1) {
@@ -586,7 +619,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
   constexpr int LW = Log2<W>::v;
   // RDR: a Crank-Nicolson first pass reduced in the RD form as well (fewer registers)
   constexpr bool RD = RdSubst<M, W, SRC, PH>::on || RDR;
-  if constexpr (PH == PH_REDUCE && SRC == SRC_CN) {
+  if constexpr (PH == PH_REDUCE && cn_src(SRC)) {
     if (A.halo_out) {
       if (wave == 0 && lane == 0) A.halo_out[2 * G.gt] = fst;
       if (wave == W - 1 && lane == 63) A.halo_out[2 * G.gt + 1] = lst;
@@ -606,7 +639,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
     }
     reduce_block_rd<M>(ay, edges, Dr, bK.y, blk);
   } else {
-    reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
+    reduce_block<M, cn_src(SRC)>(Ar, Br, Cr, Dr, bK, blk);
   }
   if constexpr (W == 1) {
     tree_up<6>(blk, wnode, lane);
@@ -694,11 +727,12 @@ __device__ __forceinline__ void check_rows(const KArgs& A, const Geo& G, int64_t
 // wedge) and from the joint line below the lane (pM).  Wavefront 0 has no left neighbour in the
 // tile: its joint row takes the explicit half-step without psi_{J-1}, whose term the reduced
 // system adds (KArgs::ud_halo); at the start of a system that neighbour is zero anyway.
-template <int M, int W, bool IN>
+template <int M, int W, bool IN, int SRC = SRC_CN>
 __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                           cd* buf, int64_t J, int lane, int wave,
                                           const cd (&xo)[M], cd pM, const double* ayn) {
   static_assert(M >= 2, "the next step is reduced in the RD form");
+  constexpr bool WA = SRC == SRC_CNW;
   using S = Stage<M>;
   if (lane == 63) sm.wedge[wave] = xo[M - 1];
   __syncthreads();
@@ -724,17 +758,29 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
     const double w = ayn[j];
     const cd p = vp[j + 1];
     const cd s2 = cadd(vp[j], vp[j + 2]);
-    Ar[j] = mk(1.0, w);
-    Br[j] = Cr[j] = zero;  // the RD form takes the couplings from kap
-    Dr[j] = csel(row_in<IN>(J + j, G.n),
-                 mk(fma(w, p.y, fma(-kap, s2.y, p.x)), fma(-w, p.x, fma(kap, s2.x, p.y))), zero);
+    const bool ok = row_in<IN>(J + j, G.n);
+    if constexpr (WA) {
+      // the general reduction: full complex diagonal, couplings -i kappa inside the system
+      const double tw = ayn[M + j];
+      Ar[j] = mk(1.0 + tw, w);
+      Br[j] = mk(0.0, (ok && row_pos<IN>(J + j)) ? -kap : 0.0);
+      Cr[j] = mk(0.0, (ok && row_notlast<IN>(J + j, G.n)) ? -kap : 0.0);
+      Dr[j] = csel(ok, mk(fma(-tw, p.x, fma(w, p.y, fma(-kap, s2.y, p.x))),
+                          fma(-tw, p.y, fma(-w, p.x, fma(kap, s2.x, p.y)))), zero);
+    } else {
+      Ar[j] = mk(1.0, w);
+      Br[j] = Cr[j] = zero;  // the RD form takes the couplings from kap
+      Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s2.y, p.x)), fma(-w, p.x, fma(kap, s2.x, p.y))),
+                   zero);
+    }
   }
   const cd bK = mk(0.0, row_in<IN>(J + M, G.n) ? -kap : 0.0);
   Node* wnode = reinterpret_cast<Node*>(buf);
   double* keep = reinterpret_cast<double*>(wnode + 64);
-  // reduced in the RD form: the diagonal and the right-hand side are all it keeps per row
-  tile_core<M, W, SRC_CN, PH_REDUCE, IN, (M >= 2)>(A, G, sm, wnode, keep, kap, J, lane, wave,
-                                                   Ar, Br, Cr, Dr, bK, vp[1], vp[M], dummy);
+  // reduced in the RD form (real potentials): the diagonal and the right-hand side are all it
+  // keeps per row; with the absorbing term, Table 1's reduction of the full rows
+  tile_core<M, W, SRC, PH_REDUCE, IN, !WA>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br,
+                                           Cr, Dr, bK, vp[1], vp[M], dummy);
 }
 
 // Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
@@ -770,24 +816,90 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
       store_tile<M, W, SRC, IN>(A, G, sm, buf, w0, lane, wave, xo);
     }
   }
-  if constexpr (PH == PH_FUSE && SRC == SRC_CN)
-    fuse_next<M, W, IN>(A, G, sm, buf, J, lane, wave, xo, pM, ayn);
+  if constexpr (PH == PH_FUSE && cn_src(SRC))
+    fuse_next<M, W, IN, SRC>(A, G, sm, buf, J, lane, wave, xo, pM, ayn);
 }
 
 // Waves per SIMD that the register allocation of a tile kernel must allow: the fused pass of
 // 8 rows per lane carries the next step's diagonal through its first half and sits one
 // register above the budget of 3 wavefronts; the others keep the compiler's choice.
-template <int M, int PH>
+template <int M, int PH, int SRC = SRC_CN>
 constexpr int tile_min_waves() {
-  return (PH == PH_FUSE && M == 8) ? 3 : 1;
+  return (PH == PH_FUSE && M == 8 && SRC == SRC_CN) ? 3 : 1;
 }
 
 // One workgroup = one tile of T = 64*W*M rows of one system.
 template <int M, int W, int SRC, int PH>
-__global__ __launch_bounds__(64 * W, (tile_min_waves<M, PH>())) void k_tile(KArgs A) {
+__global__ __launch_bounds__(64 * W, (tile_min_waves<M, PH, SRC>())) void k_tile(KArgs A) {
   __shared__ TileSmem<M, W> sm;
   const Geo G = geometry<PH>(A);
   tile_run<M, W, SRC, PH>(A, G, sm);
+}
+
+// ------------------------------------------------------------ several right-hand sides
+// One workgroup = one tile of T = 64*W*M rows of ONE matrix (a, b, c shared by the batch:
+// cshared) and nrhs right-hand sides of it (systems blockIdx.y * nrhs + r).  The matrix rows
+// are loaded and put in lane-block order once; the loop over the right-hand sides loads only
+// d_r and runs the tile's reduction, nesting, top and substitution on it (Sec. 5.2.4: several
+// systems that share a matrix), so the matrix crosses the memory bus once per tile instead of
+// once per right-hand side.
+template <int M, int W, int PH, bool IN>
+__device__ __forceinline__ void tile_run_mrhs(const KArgs& A, const Geo& G0, TileSmem<M, W>& sm,
+                                              int64_t w0, int64_t J, int lane, int wave) {
+  const int64_t n = G0.n;
+  const cd one = mk(1.0, 0.0), zero = czero();
+  cd* buf = sm.lds[wave];
+  cd va[M + 2], vb[M + 2], vc[M + 2];
+  {
+    cd ra[M], rb[M], rc[M], ha, hb, hc;
+    stage_fetch<M, IN>(A.a + G0.cbase, G0.es, w0, n, lane, one, ra, ha);
+    stage_fetch<M, IN>(A.b + G0.cbase, G0.es, w0, n, lane, zero, rb, hb);
+    stage_fetch<M, IN>(A.c + G0.cbase, G0.es, w0, n, lane, zero, rc, hc);
+    transpose_in<M>(buf, lane, ra, ha, va);
+    transpose_in<M>(buf, lane, rb, hb, vb);
+    transpose_in<M>(buf, lane, rc, hc, vc);
+  }
+  const int64_t s0 = G0.sys * A.nrhs;
+  for (int r = 0; r < A.nrhs; ++r) {
+    Geo G = G0;
+    G.sys = s0 + r;
+    if (G.sys >= A.batch) break;  // uniform across the workgroup
+    G.base = G.sys * A.bs;
+    G.gt = G.sys * A.ntiles + G.tile;
+    cd rd[M], hd, vd[M + 2];
+    stage_fetch<M, IN>(A.d + G.base, G.es, w0, n, lane, zero, rd, hd);
+    transpose_in<M>(buf, lane, rd, hd, vd);
+    cd Ar[M], Br[M], Cr[M], Dr[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t q = J + j;
+      const bool ok = row_in<IN>(q, n);
+      const bool pos = ok && row_pos<IN>(q), notlast = ok && row_notlast<IN>(q, n);
+      Ar[j] = csel(ok, va[j + 1], one);
+      Br[j] = csel(pos, vb[j + 1], zero);
+      Cr[j] = csel(notlast, vc[j + 1], zero);
+      Dr[j] = csel(ok, vd[j + 1], zero);
+    }
+    const cd bK = csel(row_in<IN>(J + M, n), vb[M + 1], zero);
+    tile_finish<M, W, SRC_EXPL, PH, IN>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK,
+                                         zero, zero, nullptr);
+    __syncthreads();  // the staging buffers and nodes are reused by the next right-hand side
+  }
+}
+
+template <int M, int W, int PH>
+__global__ __launch_bounds__(64 * W) void k_tile_mrhs(KArgs A) {
+  __shared__ TileSmem<M, W> sm;
+  const Geo G = geometry<PH>(A);
+  constexpr int64_t T = 64 * W * M;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t w0 = G.tile * T + (int64_t)wave * 64 * M;
+  const int64_t J = w0 + (int64_t)lane * M;
+  if (w0 >= 1 && G.n >= w0 + 64 * M + 1)
+    tile_run_mrhs<M, W, PH, true>(A, G, sm, w0, J, lane, wave);
+  else
+    tile_run_mrhs<M, W, PH, false>(A, G, sm, w0, J, lane, wave);
 }
 
 // ------------------------------------------------------------------ interleaved batches
@@ -1143,7 +1255,8 @@ struct AuxArgs {
   const double* xg;
   double vscale, E, dx, dt;
   const double* dxs;
-  const double* W;  // absorbing potential (the potential is V - iW), or null
+  const double* W;  // absorbing potential (the potential is V - i wscale W), or null
+  double wscale;
   const cd* psi;
   cd *a, *b, *c, *d;
   // adjoint accumulation

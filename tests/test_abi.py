@@ -65,11 +65,12 @@ def test_layout_errors_are_reported_on_the_host():
     lib = _lib.lib()
     BAD, UNSUP, OK = _lib.CN_ERR_INVALID_ARG, _lib.CN_ERR_UNSUPPORTED, _lib.CN_OK
 
-    def L(n=10, batch=1, es=1, bs=10, offsets=None, partition=0, rpt=0, shared=0):
+    def L(n=10, batch=1, es=1, bs=10, offsets=None, partition=0, rpt=0, shared=0, levels=0):
         x = _lib.CnLayout()
         x.n, x.batch, x.elem_stride, x.batch_stride = n, batch, es, bs
         x.partition, x.rows_per_thread = partition, rpt
         x.shared_coefficients = shared
+        x.levels = levels
         if offsets is not None:
             o = np.ascontiguousarray(offsets, dtype=np.int64)
             x.offsets = o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
@@ -96,6 +97,10 @@ def test_layout_errors_are_reported_on_the_host():
     assert check(L(partition=16)) == BAD
     assert check(L(partition=1024, rpt=3)) == BAD
     assert check(L(partition=1024, rpt=16)) == OK
+    assert check(L(levels=3)) == OK
+    assert check(L(levels=8)) == OK
+    assert check(L(levels=9)) == BAD
+    assert check(L(levels=-1)) == BAD
     assert check(L(n=1 << 41)) == UNSUP
     assert check(L(n=10, batch=3, es=1, bs=10, shared=1)) == OK   # one matrix, 3 right-hand sides
     assert check(L(shared=2)) == BAD

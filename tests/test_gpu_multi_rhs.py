@@ -39,7 +39,8 @@ def log(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 3), (1000, 7), (4096, 5), (70_001, 6)])
+@pytest.mark.parametrize("n,nrhs", [(1, 3), (1000, 7), (4096, 5), (70_001, 6), (300_007, 16),
+                                    (1_000_003, 3), (5000, 33)])
 def test_solve_one_matrix_many_rhs_contiguous(gpu, oracle_mod, n, nrhs):
     torch, cn = gpu
     log("shared solve", n, nrhs)
@@ -48,10 +49,17 @@ def test_solve_one_matrix_many_rhs_contiguous(gpu, oracle_mod, n, nrhs):
     d = workloads.complex_normal(g, nrhs * n)
     ta, tb, tc, td = to_dev(torch, a, b, c, d)
     L = cn.Layout.contiguous(n, nrhs, shared_coefficients=True)
-    x = cn.solve(ta, tb, tc, td, layout=L).cpu().numpy()
+    assert "rhs/wg=" in cn.describe_plan(L)  # the matrix is loaded once per tile
+    xt = cn.solve(ta, tb, tc, td, layout=L)
+    x = xt.cpu().numpy()
     for s in range(nrhs):
         ref = oracle_mod.thomas(a, b, c, d[s * n:(s + 1) * n])
         assert rel(x[s * n:(s + 1) * n], ref) <= TOL
+    # the same rows through the per-system kernels (matrix copied per right-hand side): the
+    # same arithmetic, so the same bits
+    A, B, C = (t.repeat(nrhs) for t in (ta, tb, tc))
+    xr = cn.solve(A, B, C, td, layout=cn.Layout.contiguous(n, nrhs))
+    assert torch.equal(xt, xr)
     assert cn.get_status() == 0
 
 

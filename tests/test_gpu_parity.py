@@ -536,8 +536,12 @@ def test_uneven_persistent_configs_and_long_fallback(gpu, oracle_mod, T, M):
     ref = oracle_mod.thomas_batched(offs, a, b, c, d, nthreads=8)
     ta, tb, tc, td = to_dev(torch, a, b, c, d)
     L = cn.Layout.uneven(offs, partition=T, rows_per_thread=M)
+    # the multi-workgroup launch and its reduced system cover the long system only
+    K = (64 * T + 17 + T - 1) // T
+    assert f"systems=1 tiles={K};" in cn.describe_plan(L)
     x = cn.solve(ta, tb, tc, td, layout=L)
     assert rel(x.cpu().numpy(), ref) <= TOL
+    assert cn.get_status() == 0
     gx = torch.ones_like(td)
     lam, _, _, _ = cn.solve_adjoint(ta, tb, tc, x, gx, need_abc=False, layout=L)
     lam_ref = np.concatenate([
@@ -545,6 +549,7 @@ def test_uneven_persistent_configs_and_long_fallback(gpu, oracle_mod, T, M):
                                   np.ones(o1 - o0, complex))[0]
         for o0, o1 in zip(offs[:-1], offs[1:]) if o1 > o0])
     assert rel(lam.cpu().numpy(), lam_ref) <= TOL
+    assert cn.get_status() == 0
 
 
 def test_autotune_keeps_results(gpu, oracle_mod):
@@ -617,3 +622,72 @@ def test_column_kernels(gpu, oracle_mod, T, M, n, batch):
     tV, tp = to_dev(torch, V.ravel(), psi.ravel())
     cn.step(tp, tV, 0.1, 0.02, out=tp, layout=L)
     assert rel(tp.cpu().numpy().reshape(n, batch), pref) <= TOL
+
+
+# ------------------------------------------------------ nesting depth fixed by the caller
+@pytest.mark.parametrize("n,T,M,levels", [(300_007, 1024, 4, 1), (300_007, 1024, 4, 2),
+                                          (3_000_017, 128, 2, 1), (3_000_017, 128, 2, 2),
+                                          (3_000_017, 128, 2, 3), (5, 128, 2, 1)])
+def test_solve_with_fixed_levels(gpu, oracle_mod, n, T, M, levels):
+    """cn_layout.levels = L: L partition levels, then the serial RS stage on what is left."""
+    torch, cn = gpu
+    log("levels", n, T, M, levels)
+    a, b, c, d = workloads.random_system(n, 90 + levels, "herm")
+    ref = oracle_mod.thomas(a, b, c, d)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    L = cn.Layout.contiguous(n, 1, partition=T, rows_per_thread=M, levels=levels)
+    plan = cn.describe_plan(L)
+    if n > T:
+        assert plan.count("multi") <= levels
+    x = cn.solve(ta, tb, tc, td, layout=L)
+    assert rel(x.cpu().numpy(), ref) <= TOL
+    assert cn.get_status() == 0
+
+
+def test_fixed_levels_batches_and_propagation(gpu, oracle_mod):
+    """The serial RS stage on the reduced systems of a uniform batch (one thread each), of an
+    uneven batch, and inside fused propagation (its rows take the deferred joint-row term)."""
+    torch, cn = gpu
+    n, batch = 20_000, 7
+    a, b, c, d = workloads.random_system(n * batch, 5, "dd")
+    offs = np.arange(batch + 1) * n
+    ref = oracle_mod.thomas_batched(offs, a, b, c, d, nthreads=8)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    L = cn.Layout.contiguous(n, batch, partition=512, levels=1)
+    assert "serial RS" in cn.describe_plan(L)
+    assert rel(cn.solve(ta, tb, tc, td, layout=L).cpu().numpy(), ref) <= TOL
+    lengths = np.array([5000, 1, 0, 9000, 17_000])
+    uo = np.concatenate([[0], np.cumsum(lengths)])
+    a, b, c, d = workloads.random_system(int(uo[-1]), 6, "herm")
+    ref = oracle_mod.thomas_batched(uo, a, b, c, d, nthreads=8)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    Lu = cn.Layout.uneven(uo, levels=1)
+    assert "serial RS" in cn.describe_plan(Lu)
+    assert rel(cn.solve(ta, tb, tc, td, layout=Lu).cpu().numpy(), ref) <= TOL
+    # propagation with a field: the fused chain with the serial RS stage as its reduced system
+    w = workloads.differentiated(n=100_003, steps=12)
+    refp = oracle_mod.cn_propagate(w["psi0"], w["V"], w["dx"], w["dt"], 12, w["x"], w["E"])
+    tV, tp, tx = to_dev(torch, w["V"], w["psi0"], w["x"])
+    Lp = cn.Layout.contiguous(w["n"], 1, levels=1)
+    assert "serial RS" in cn.describe_plan(Lp, True)
+    cn.propagate(tp, tV, w["dx"], w["dt"], 12, E=w["E"], xgrid=tx, layout=Lp)
+    assert rel(tp.cpu().numpy(), refp) <= TOL
+    assert cn.get_status() == 0
+
+
+def test_plan_log_reports_stage_times(gpu):
+    torch, cn = gpu
+    n = 1_000_003
+    a, b, c, d = workloads.random_system(n, 3, "herm")
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    L = cn.Layout.contiguous(n, 1, partition=1024, rows_per_thread=4, levels=1)
+    cn.solve(ta, tb, tc, td, layout=L)
+    cn.profile(True)
+    cn.solve(ta, tb, tc, td, layout=L)
+    cn.profile(False)
+    rep = cn.profile_report()
+    labels = [r[0] for r in rep]
+    assert [lab.split()[1] for lab in labels] == ["reduce", "serial-RS", "subst"]
+    assert all(ms > 0 for _, ms in rep)
+    cn.solve(ta, tb, tc, td, layout=L)
+    assert cn.profile_report() == []  # off: nothing logged
