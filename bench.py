@@ -330,9 +330,17 @@ def large_system(torch, np, cn, dev, sweep=True, oracle_parity=True):
     d = torch.from_numpy(w["d"]).to(dev)
     x = torch.empty_like(d)
     rows = []
-    parts = (0, 128, 256, 512, 1024, 2048, 4096) if sweep else (0,)
+    parts = (0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384) if sweep else (0,)
     x_auto = None
     for T in parts:
+        if T in (64, 8192, 16384):
+            # the first-level partition of a launch is one workgroup's tile of T = 64 W M rows,
+            # with M rows per lane held in registers (2 <= M <= 16) and W <= 16 wavefronts
+            rows.append({"partition": T, "status": "unsupported",
+                         "why": "a tile of 64 rows would leave each lane one row (no interior "
+                                "rows to reduce); 8192 and 16384 rows of a, b, c, d (64 B each) "
+                                "are 0.5 and 1 MiB, beyond one CU's 512 KiB of registers"})
+            continue
         M = 2 if T == 128 else (0 if T == 0 else 4)
         L = cn.Layout.contiguous(N, 1, partition=T, rows_per_thread=M)
         cn.solve(a, b, c, d, out=x, layout=L)
@@ -344,6 +352,9 @@ def large_system(torch, np, cn, dev, sweep=True, oracle_parity=True):
                      "ms_min": float(np.min(ts)),
                      "GBps_144": BYTES_PER_UNKNOWN_SOLVE_2PASS * N / (med * 1e-3) / 1e9,
                      "plan": cn.describe_plan(L)})
+    if sweep:
+        levels_sweep, model = nesting_sweep(torch, np, cn, a, b, c, d, x, N)
+        tuned = autotune_leg(torch, np, cn, a, b, c, d, x, N, rows[0]["ms_median"])
     # T's Hermitian part is I, so |x - x*| <= |T x - d|: the residual over |x| bounds the
     # relative forward error of the last solve
     r = a * x
@@ -369,6 +380,10 @@ def large_system(torch, np, cn, dev, sweep=True, oracle_parity=True):
         "paper_optimum_single_level_partition": math.sqrt(N),
         "sweep": rows,
     }
+    if sweep:
+        out["nesting_sweep"] = levels_sweep
+        out["paper_model"] = model
+        out["autotune"] = tuned
     if oracle_parity:
         ref = {}
 
@@ -382,6 +397,70 @@ def large_system(torch, np, cn, dev, sweep=True, oracle_parity=True):
         if "x" in ref:
             out["parity_rel_l2"] = rel_l2(x_auto, ref["x"])
     return out
+
+
+def nesting_sweep(torch, np, cn, a, b, c, d, x, N):
+    """The paper's nesting depth on the 2^28 solve (Sec. 5.5.1, Eqs. (7)-(9)): L partition
+    levels of T-row tiles (cn_layout.levels = L), then the serial RS stage on the n / T^L joint
+    rows left, for several T and L; stage times from the plan log.  The model
+    t = alpha L T + beta n / T^L (parallel stages proportional to the block, the serial RS to
+    the rows it eliminates) is fitted to the measured times; delta = sqrt(alpha / beta) and the
+    optimal ratio per level (beta n / alpha)^(1/(L+1)) = n^(1/(L+1)) / delta^(2/(L+1)) are set
+    beside the measured optimum and the paper's n^(1/(L+1))."""
+    pts = []
+    grid = [(1, 1024), (1, 2048), (1, 4096), (2, 128), (2, 256), (2, 512), (2, 1024),
+            (3, 128), (3, 256), (3, 512)]
+    for Lv, T in grid:
+        M = 2 if T == 128 else 4
+        L = cn.Layout.contiguous(N, 1, partition=T, rows_per_thread=M, levels=Lv)
+        cn.solve(a, b, c, d, out=x, layout=L)
+        reps = 3 if N // T ** Lv <= (1 << 16) else 1
+        ts = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), reps)
+        cn.profile(True)
+        cn.solve(a, b, c, d, out=x, layout=L)
+        cn.profile(False)
+        st = cn.profile_report()
+        par = sum(ms for lab, ms in st if "serial-RS" not in lab)
+        rs = sum(ms for lab, ms in st if "serial-RS" in lab)
+        top = N // T ** Lv + 1
+        pts.append({"levels": Lv, "partition": T, "rows_per_thread": M,
+                    "ms_median": float(np.median(ts)), "stage_ms_partition_levels": par,
+                    "stage_ms_serial_rs": rs, "serial_rs_rows": top,
+                    "beta_us_per_rs_row": rs * 1e3 / top, "plan": cn.describe_plan(L)})
+    # least squares for t = alpha L T + beta N / T^L
+    A = np.array([[p["levels"] * p["partition"], N / p["partition"] ** p["levels"]] for p in pts])
+    t = np.array([p["ms_median"] for p in pts])
+    (alpha, beta), *_ = np.linalg.lstsq(A, t, rcond=None)
+    model = {"form": "t_ms = alpha * L * T + beta * n / T^L (n = 2^28)",
+             "alpha_ms": float(alpha), "beta_ms": float(beta),
+             "fit_rel_residual": float(np.linalg.norm(A @ [alpha, beta] - t) / np.linalg.norm(t))}
+    if alpha > 0 and beta > 0:
+        delta = math.sqrt(alpha / beta)
+        model["delta"] = delta
+        model["optimal_ratio_fitted"] = {str(Lv): (beta * N / alpha) ** (1.0 / (Lv + 1))
+                                         for Lv in (1, 2, 3, 4)}
+    model["optimal_ratio_paper"] = {str(Lv): N ** (1.0 / (Lv + 1)) for Lv in (1, 2, 3, 4)}
+    best = {}
+    for p in pts:
+        k = str(p["levels"])
+        if k not in best or p["ms_median"] < best[k]["ms_median"]:
+            best[k] = {"partition": p["partition"], "ms_median": p["ms_median"]}
+    model["measured_best_per_L"] = best
+    # beta straight from the serial RS stage time per eliminated row (one level: 2^16..2^18
+    # joint rows whose slots come from HBM; smaller top systems sit in the L2 and cost less)
+    model["beta_us_per_rs_row_L1"] = float(np.median([p["beta_us_per_rs_row"] for p in pts
+                                                      if p["levels"] == 1]))
+    return pts, model
+
+
+def autotune_leg(torch, np, cn, a, b, c, d, x, N, heuristic_ms):
+    """cn_autotune on the 2^28 solve: the timed candidates and the chosen plan, timed again
+    against the automatic (heuristic) plan."""
+    L = cn.Layout.contiguous(N, 1)
+    rep = cn.autotune(L, d, x, a=a, b=b, c=c)
+    ts = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), 10)
+    return {"report": rep, "tuned_ms": float(np.median(ts)), "heuristic_ms": heuristic_ms,
+            "tuned_plan": cn.describe_plan(L)}
 
 
 def long_propagate(torch, np, cn, dev, parity=True):
@@ -588,6 +667,16 @@ def extras(torch, np, cn, workloads, dev):
                                                        dx_per_system=dxs, layout=L), 3)
         med_prop = float(np.median(tsq)) / wl["steps"]
         del pprop, p0
+        # the autotuner on this batch: its candidates timed, then the chosen plan (which later
+        # calls with this automatic layout take) against the automatic one timed above
+        La = cn.Layout.uneven(wl["offsets"])
+        outbuf = torch.empty_like(psi)
+        tune_rep = cn.autotune(La, psi, outbuf, V=V, dt=wl["dt"], dx_per_system=dxs)
+        tst = timed_events(torch, lambda: cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs,
+                                                  out=psi, layout=La), 10)
+        tuned = {"report": tune_rep, "tuned_ms_per_step": float(np.median(tst)),
+                 "heuristic_ms_per_step": med, "tuned_plan": cn.describe_plan(La, True)[:300]}
+        del outbuf
         # the fixed-plan baseline: one persistent launch over all systems (1024-row tiles)
         Lp = cn.Layout.uneven(wl["offsets"], partition=1024, rows_per_thread=4)
         cn.reserve(Lp)
@@ -600,7 +689,8 @@ def extras(torch, np, cn, workloads, dev):
                                "ms_per_step_propagate": med_prop,
                                "propagate_vs_single_steps_rel_l2": prop_vs_steps,
                                "persistent_plan_ms_per_step": float(np.median(tsp)),
-                               "persistent_plan": cn.describe_plan(Lp, True)[:200]}
+                               "persistent_plan": cn.describe_plan(Lp, True)[:200],
+                               "autotune": tuned}
         # the workload's whole run: 50 steps of cn_propagate from psi0, against the oracle's
         # 50 batched steps (its timed run is the CPU baseline)
         p50 = torch.from_numpy(wl["psi0"]).to(dev)

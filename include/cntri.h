@@ -256,6 +256,17 @@ cn_status cn_autotune(cn_handle_t handle, const cn_layout* layout, int cn_mode,
                       const void* c, const void* d, void* x, char* report, int64_t report_len,
                       cn_stream_t stream);
 
+/* Persistent autotune cache.  path names a JSON file (read now if it exists, rewritten by every
+ * later cn_autotune of this handle), or NULL / "" to stop using one.  Entries are keyed by the
+ * layout's class: the device architecture (hipDeviceProp gcnArchName without its feature
+ * suffix), the source (solve or CN step) and the layout's shape in power-of-two buckets (rows
+ * per system and batch for uniform batches, with unit or other strides and shared
+ * coefficients; batch, total rows and longest system for uneven ones), plus levels.  A layout
+ * whose partition and rows_per_thread are 0 takes the cached configuration of its class when
+ * the handle has no tuned plan for it in memory.  Host only (no device access); returns
+ * CN_ERR_INVALID_ARG when autotune cannot write the file. */
+cn_status cn_tune_cache(cn_handle_t handle, const char* path);
+
 /* Device memory held by the handle (workspaces and plan tables, excluding retired buffers),
  * the number of buffers retired after graph capture (freed by cn_destroy), and whether a call
  * of the handle has been captured.  Each output pointer may be NULL.  Host only. */

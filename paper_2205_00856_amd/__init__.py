@@ -5,7 +5,7 @@ binds it for torch device tensors and adds autograd wrappers.
 """
 from .api import (Handle, Layout, assemble, autotune, describe_plan, get_status, handle,  # noqa: F401
                   profile, profile_report, propagate, propagate_adjoint, reserve, rhs, solve, solve_adjoint,
-                  solve_noalloc, step,
+                  solve_noalloc, step, tune_cache,
                   step_adjoint)
 
 __version__ = "0.1.0"

@@ -94,6 +94,7 @@ def lib():
         "cn_handle_info": ([H, ctypes.POINTER(i64), ctypes.POINTER(i64),
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "cn_profile": ([H, ctypes.c_int], ctypes.c_int),
+        "cn_tune_cache": ([H, ctypes.c_char_p], ctypes.c_int),
         "cn_profile_report": ([H, ctypes.c_char_p, i64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -108,7 +109,7 @@ EXPORTED = ["cn_check_layout", "cn_create", "cn_destroy", "cn_status_string", "c
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
             "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
             "cn_propagate_adjoint", "cn_handle_info", "cn_tridiag_solve_noalloc", "cn_profile",
-            "cn_profile_report"]
+            "cn_profile_report", "cn_tune_cache"]
 
 
 def status_string(st: int) -> str:

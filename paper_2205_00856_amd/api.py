@@ -20,7 +20,7 @@ from ._lib import CnLayout, CnOperator, check
 
 __all__ = ["Layout", "Handle", "handle", "solve", "solve_noalloc", "solve_adjoint", "assemble", "rhs", "step",
            "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune",
-           "profile", "profile_report",
+           "profile", "profile_report", "tune_cache",
            "propagate_adjoint"]
 
 
@@ -365,6 +365,13 @@ def step_adjoint(psi_n, psi_np1, g_np1, V, dx, dt, E=0.0, xgrid=None, v_scale=1.
                                      _ptr(psi_n), _ptr(psi_np1), _ptr(g_np1), _ptr(g_out),
                                      _ptr(dV), _ptr(dE_out), _stream(psi_n)), "cn_step_adjoint")
     return g_out
+
+
+def tune_cache(path: Optional[str], device=None):
+    """Persistent autotune cache file (cn_tune_cache); None stops using one."""
+    h = handle(device)
+    check(_lib.lib().cn_tune_cache(h.ptr, None if path is None else path.encode()),
+          "cn_tune_cache")
 
 
 def profile(enable: bool = True, device=None):

@@ -664,6 +664,9 @@ struct cn_handle_s {
   // of that entry point (their tables live in host memory and are copied into the array)
   char* scratch = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> static_plans;
+  // persistent autotune cache (cn_tune_cache): file path and entries, layout class -> "T,M"
+  std::string cache_path;
+  std::map<std::string, std::string> cache;
   // plan log (cn_profile): HIP events around every launch of run_plan, with a label each
   bool profiling = false;
   struct Rec {
@@ -846,14 +849,131 @@ void bind_tables(Plan& P, char* tb) {
   }
 }
 
+// ------------------------------------------------------------------ autotune cache
+// A layout's class for the persistent cache: the device architecture, the source, and the
+// layout's shape in power-of-two buckets (rows per system, batch; for uneven batches the total
+// rows and the longest system), so that a tuned plan carries over to layouts of the same kind.
+std::string arch_name() {
+  static const std::string a = [] {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
+      return std::string("unknown");
+    std::string n = p.gcnArchName;
+    const size_t c = n.find(':');
+    return c == std::string::npos ? n : n.substr(0, c);
+  }();
+  return a;
+}
+
+int log2_bucket(int64_t v) {
+  int b = 0;
+  while (((int64_t)1 << (b + 1)) <= v) ++b;
+  return b;
+}
+
+std::string cache_class(const cn_layout* L, int src) {
+  char buf[192];
+  if (L->offsets) {
+    int64_t maxlen = 0;
+    for (int64_t s = 0; s < L->batch; ++s) maxlen = std::max(maxlen, L->offsets[s + 1] - L->offsets[s]);
+    snprintf(buf, sizeof(buf), "%s|src%d|uneven|batch2^%d|rows2^%d|max2^%d|levels%d",
+             arch_name().c_str(), src, log2_bucket(L->batch), log2_bucket(L->offsets[L->batch]),
+             log2_bucket(maxlen), L->levels);
+  } else {
+    snprintf(buf, sizeof(buf), "%s|src%d|uniform|n2^%d|batch2^%d|es%s|bs%s|shared%d|levels%d",
+             arch_name().c_str(), src, log2_bucket(L->n), log2_bucket(L->batch),
+             L->elem_stride == 1 ? "1" : "N", L->batch_stride == 1 ? "1" : "N",
+             L->shared_coefficients, L->levels);
+  }
+  return buf;
+}
+
+// The cache file is a JSON object of objects (written one entry per line):
+//   {"<class>": {"partition": T, "rows_per_thread": M, "ms": t}, ...}
+// The reader takes every "<class>": {...} pair whose object holds the two integers.
+cn_status cache_load(cn_handle_t h) {
+  h->cache.clear();
+  FILE* f = fopen(h->cache_path.c_str(), "r");
+  if (!f) return CN_OK;  // no file yet
+  std::string txt;
+  char chunk[4096];
+  size_t got;
+  while ((got = fread(chunk, 1, sizeof(chunk), f)) > 0) txt.append(chunk, got);
+  fclose(f);
+  size_t pos = 0;
+  for (;;) {
+    const size_t q0 = txt.find('"', pos);
+    if (q0 == std::string::npos) break;
+    const size_t q1 = txt.find('"', q0 + 1);
+    if (q1 == std::string::npos) break;
+    const size_t ob = txt.find_first_not_of(" \t\r\n:", q1 + 1);
+    if (ob == std::string::npos || txt[ob] != '{') {  // a key inside an entry: skip it
+      pos = q1 + 1;
+      continue;
+    }
+    const size_t cb = txt.find('}', ob);
+    if (cb == std::string::npos) break;
+    const std::string body = txt.substr(ob, cb - ob);
+    int T = 0, M = 0;
+    const size_t pp = body.find("\"partition\":"), pm = body.find("\"rows_per_thread\":");
+    if (pp != std::string::npos && pm != std::string::npos &&
+        sscanf(body.c_str() + pp + 12, "%d", &T) == 1 &&
+        sscanf(body.c_str() + pm + 18, "%d", &M) == 1) {
+      char v[32];
+      snprintf(v, sizeof(v), "%d,%d", T, M);
+      h->cache[txt.substr(q0 + 1, q1 - q0 - 1)] = v;
+    }
+    pos = cb + 1;
+  }
+  return CN_OK;
+}
+
+cn_status cache_store(cn_handle_t h, const std::map<std::string, float>& ms) {
+  const std::string tmp = h->cache_path + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return CN_ERR_INVALID_ARG;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : h->cache) {
+    int T = 0, M = 0;
+    sscanf(kv.second.c_str(), "%d,%d", &T, &M);
+    auto it = ms.find(kv.first);
+    fprintf(f, "  \"%s\": {\"partition\": %d, \"rows_per_thread\": %d, \"ms\": %.6f}%s\n",
+            kv.first.c_str(), T, M, it == ms.end() ? -1.0 : (double)it->second,
+            ++i < h->cache.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  const bool ok = fclose(f) == 0 && rename(tmp.c_str(), h->cache_path.c_str()) == 0;
+  return ok ? CN_OK : CN_ERR_INVALID_ARG;
+}
+
 cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Plan** out) {
   int64_t rows = 0, span = 0;
   cn_status st = validate(L, rows, span);
   if (st != CN_OK) return st;
   std::string key = plan_key(L, src);
+  cn_layout Lc;  // the cached tuned configuration of this layout's class, if any
   {
     auto tk = h->tuned.find(key);
-    if (tk != h->tuned.end() && h->plans.count(tk->second)) key = tk->second;
+    if (tk != h->tuned.end() && h->plans.count(tk->second)) {
+      key = tk->second;
+    } else if (!h->cache.empty() && L->partition == 0 && L->rows_per_thread == 0) {
+      auto ck = h->cache.find(cache_class(L, src));
+      if (ck != h->cache.end()) {
+        int T = 0, M = 0;
+        if (sscanf(ck->second.c_str(), "%d,%d", &T, &M) == 2 && (T > 0 || M > 0)) {
+          Lc = *L;
+          Lc.partition = T;
+          Lc.rows_per_thread = M;
+          int64_t r2 = 0, s2 = 0;
+          if (validate(&Lc, r2, s2) == CN_OK) {
+            L = &Lc;
+            key = plan_key(L, src);
+          }
+        }
+      }
+    }
   }
   auto it = h->plans.find(key);
   const bool cap = s != nullptr ? capturing(s) : false;
@@ -1602,6 +1722,7 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
   std::string rep;
   float best = 1e30f;
   std::string best_key;
+  int best_T = 0, best_M = 0;
   for (const Cand& cd_ : cands) {
     cn_layout L2 = *L;
     L2.partition = cd_.T;
@@ -1652,6 +1773,8 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
     if (med < best) {
       best = med;
       best_key = plan_key(&L2, src);
+      best_T = cd_.T;
+      best_M = cd_.M;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1659,6 +1782,17 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
   if (best_key.empty()) return CN_ERR_UNSUPPORTED;
   h->tuned[plan_key(L, src)] = best_key;
   rep += "chosen: " + h->plans[best_key]->desc;
+  if (!h->cache_path.empty()) {
+    char v[32];
+    snprintf(v, sizeof(v), "%d,%d", best_T, best_M);
+    const std::string cls = cache_class(L, src);
+    h->cache[cls] = v;
+    std::map<std::string, float> ms;
+    ms[cls] = best;
+    const cn_status cst = cache_store(h, ms);
+    if (cst != CN_OK) return cst;
+    rep += " (cached)";
+  }
   if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
   return CN_OK;
 }
@@ -1828,6 +1962,16 @@ cn_status cn_handle_info(cn_handle_t h, int64_t* device_bytes, int64_t* retired_
   if (retired_buffers) *retired_buffers = (int64_t)h->retired.size();
   if (captured) *captured = h->captured ? 1 : 0;
   return CN_OK;
+}
+
+cn_status cn_tune_cache(cn_handle_t h, const char* path) {
+  if (!h) return CN_ERR_INVALID_ARG;
+  h->cache_path = path ? path : "";
+  if (h->cache_path.empty()) {
+    h->cache.clear();
+    return CN_OK;
+  }
+  return cache_load(h);
 }
 
 cn_status cn_profile(cn_handle_t h, int enable) {

@@ -691,3 +691,71 @@ def test_plan_log_reports_stage_times(gpu):
     assert all(ms > 0 for _, ms in rep)
     cn.solve(ta, tb, tc, td, layout=L)
     assert cn.profile_report() == []  # off: nothing logged
+
+
+def test_autotune_cache_file(gpu, oracle_mod, tmp_path):
+    """cn_autotune writes its choice to the persistent cache (a JSON file keyed by the layout's
+    class); a fresh handle that reads the file plans the automatic layout with the cached
+    configuration, and its results stay the oracle's."""
+    torch, cn = gpu
+    import ctypes
+    import json
+
+    from paper_2205_00856_amd import _lib
+
+    path = str(tmp_path / "tune.json")
+    n = 200_003
+    a, b, c, d = workloads.random_system(n, 31, "herm")
+    ref = oracle_mod.thomas(a, b, c, d)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    L = cn.Layout.contiguous(n, 1)
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    assert lib.cn_create(ctypes.byref(h), 0) == _lib.CN_OK
+    try:
+        assert lib.cn_tune_cache(h, path.encode()) == _lib.CN_OK
+        out = torch.empty_like(td)
+        buf = ctypes.create_string_buffer(4096)
+        Lc = L.c()
+        st = lib.cn_autotune(h, ctypes.byref(Lc), 0, None, 0.0, ctypes.c_void_p(ta.data_ptr()),
+                             ctypes.c_void_p(tb.data_ptr()), ctypes.c_void_p(tc.data_ptr()),
+                             ctypes.c_void_p(td.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                             buf, 4096, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == _lib.CN_OK
+        log(buf.value.decode())
+        assert "(cached)" in buf.value.decode()
+    finally:
+        torch.cuda.synchronize()
+        lib.cn_destroy(h)
+    entries = json.load(open(path))
+    (cls, ent), = entries.items()
+    assert cls.startswith("gfx") and "|src0|uniform|n2^17|" in cls
+    assert set(ent) == {"partition", "rows_per_thread", "ms"}
+    # a fresh handle with the cache: the automatic layout takes the cached configuration
+    h2 = ctypes.c_void_p()
+    assert lib.cn_create(ctypes.byref(h2), 0) == _lib.CN_OK
+    try:
+        assert lib.cn_tune_cache(h2, path.encode()) == _lib.CN_OK
+        Lc = L.c()
+        assert lib.cn_describe_plan(h2, ctypes.byref(Lc), 0, buf, 4096) == _lib.CN_OK
+        desc = buf.value.decode()
+        if ent["partition"] > 0:
+            assert f"T={ent['partition']}(M={ent['rows_per_thread']}" in desc
+        x = torch.empty_like(td)
+        st = lib.cn_tridiag_solve(h2, ctypes.byref(Lc), ctypes.c_void_p(ta.data_ptr()),
+                                  ctypes.c_void_p(tb.data_ptr()), ctypes.c_void_p(tc.data_ptr()),
+                                  ctypes.c_void_p(td.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == _lib.CN_OK
+        torch.cuda.synchronize()
+        assert rel(x.cpu().numpy(), ref) <= TOL
+        # a hand-written entry for the same class is honoured as well
+        with open(path, "w") as f:
+            json.dump({cls: {"partition": 256, "rows_per_thread": 4, "ms": -1}}, f)
+        assert lib.cn_tune_cache(h2, path.encode()) == _lib.CN_OK
+        L2 = cn.Layout.contiguous(n + 1, 1).c()  # same class, a plan not built yet
+        assert lib.cn_describe_plan(h2, ctypes.byref(L2), 0, buf, 4096) == _lib.CN_OK
+        assert "T=256(M=4" in buf.value.decode()
+    finally:
+        torch.cuda.synchronize()
+        lib.cn_destroy(h2)
