@@ -13,6 +13,8 @@ What it computes (arXiv 2205.00856):
                            absorbing potential (V - iW); the step is then the Cayley form
                            (1 + i tau H)^{-1} (1 - i tau H), whose right side is not T^dagger.
 * ``adi_step``          -- one Lie-split ADI step (operator splitting, Sec. 3) on a 2D grid.
+* ``radial_step``       -- one Lie-split partial-wave step (Sec. 3): CN in r per l with the
+                           centrifugal term, then CN in l per r with the field coupling.
 * ``thomas_adjoint``    -- reverse mode of the solve (plain definition, lambda = T^{-H} G).
 * ``cn_propagate_grad`` -- reverse mode of many CN steps with every state stored (with ``W``,
                            of the absorbing step: lambda = T^{-H} G, G_k = B^H lambda with
@@ -76,6 +78,7 @@ def _load():
     lib.oracle_thomas_adjoint.argtypes = [i64, P, P, P, P, P, P, P, P, P]
     lib.oracle_cn_propagate_grad.argtypes = [i64, P, d, d, i64, P, P, P, P, P, P, P]
     lib.oracle_cn_propagate_grad_w.argtypes = [i64, P, d, d, i64, P, P, P, P, P, P, P, P]
+    lib.oracle_radial_step.argtypes = [i64, i64, i64, P, d, d, d, P]
     lib.oracle_max_threads.argtypes = []
     _lib = lib
     return lib
@@ -220,3 +223,14 @@ def cn_propagate_grad(psi0, V, dx, dt, nsteps, G_T, xgrid=None, E=None, W=None):
     _check(lib.oracle_cn_propagate_grad_w(n, _p(V), dx, dt, int(nsteps), _p(xg), _p(Ea), _p(Wa),
                                           _p(psi0), _p(G_T), _p(gpsi0), _p(dV), _p(dE)))
     return gpsi0, dV, dE
+
+
+def radial_step(psi, V, dr, dt, E, l0, nl):
+    """One partial-wave step; psi is l-major (nl x nr), V has nr values (r_j = j dr)."""
+    lib = _load()
+    psi = _c(psi, np.complex128).copy()
+    V = _c(V, np.float64)
+    nr = V.shape[0]
+    assert psi.shape[0] == nl * nr
+    _check(lib.oracle_radial_step(nr, int(l0), int(nl), _p(V), dr, dt, E, _p(psi)))
+    return psi

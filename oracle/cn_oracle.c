@@ -299,6 +299,58 @@ int oracle_cn_propagate_grad(int64_t n, const double* V, double dx, double dt, i
                                     dE);
 }
 
+/* Partial-wave (radial) Crank-Nicolson step of the kind Sec. 3 describes for atoms in strong
+ * fields expanded in spherical harmonics: radial functions psi_l(r_j), l = l0 .. l0+nl-1, on
+ * r_j = j dr (j = 1..nr, psi = 0 at r = 0 and r = (nr+1) dr), stored l-major:
+ * psi[(l - l0) * nr + j - 1].  One Lie-split step of dt:
+ *  1. for every l, a CN step in r with H_l = -1/2 d^2/dr^2 + V(r) + l(l+1)/(2 r^2);
+ *  2. for every r_j, a CN step in l with the length-gauge coupling H_E = E r_j C, where C is
+ *     the matrix of cos(theta) between the m = 0 spherical harmonics, tridiagonal in l:
+ *     C_{l,l+1} = C_{l+1,l} = (l+1) / sqrt((2l+1)(2l+3)).
+ * Both parts are CN steps (1 + i dt/2 H)^{-1} (1 - i dt/2 H) with a Hermitian H. */
+static double coupling_c(int64_t l) {
+  return (double)(l + 1) / sqrt((double)(2 * l + 1) * (double)(2 * l + 3));
+}
+
+int oracle_radial_step(int64_t nr, int64_t l0, int64_t nl, const double* V, double dr,
+                       double dt, double E, cplx* psi) {
+  int bad = 0;
+  double* veff = (double*)malloc(sizeof(double) * (size_t)nr);
+  for (int64_t k = 0; k < nl; ++k) {
+    const double l = (double)(l0 + k);
+    for (int64_t j = 0; j < nr; ++j) {
+      const double r = (double)(j + 1) * dr;
+      veff[j] = V[j] + l * (l + 1.0) / (2.0 * r * r);
+    }
+    bad |= oracle_cn_step(nr, veff, dr, dt, NULL, 0.0, psi + k * nr, psi + k * nr);
+  }
+  free(veff);
+  const double tau = 0.5 * dt;
+  cplx* buf = (cplx*)malloc(sizeof(cplx) * (size_t)(7 * nl));
+  cplx *a = buf, *b = buf + nl, *c = buf + 2 * nl, *d = buf + 3 * nl, *x = buf + 4 * nl,
+       *w = buf + 5 * nl;
+  for (int64_t j = 0; j < nr; ++j) {
+    const double r = (double)(j + 1) * dr;
+    for (int64_t k = 0; k < nl; ++k) {
+      /* T = 1 + i tau E r C: off-diagonals i tau E r c */
+      a[k] = 1.0;
+      b[k] = (k > 0) ? I * tau * E * r * coupling_c(l0 + k - 1) : 0.0;
+      c[k] = (k < nl - 1) ? I * tau * E * r * coupling_c(l0 + k) : 0.0;
+    }
+    for (int64_t k = 0; k < nl; ++k) {
+      /* d = (1 - i tau E r C) psi */
+      cplx s = psi[k * nr + j];
+      if (k > 0) s -= b[k] * psi[(k - 1) * nr + j];
+      if (k < nl - 1) s -= c[k] * psi[(k + 1) * nr + j];
+      d[k] = s;
+    }
+    bad |= oracle_thomas(nl, a, b, c, d, x, w);
+    for (int64_t k = 0; k < nl; ++k) psi[k * nr + j] = x[k];
+  }
+  free(buf);
+  return bad;
+}
+
 int oracle_max_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

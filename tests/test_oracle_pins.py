@@ -501,3 +501,62 @@ def test_absorbing_propagate_grad_without_w_is_the_hermitian_recursion(oracle_mo
                                      W=np.zeros(n))
     for u, v in zip(a, b):
         assert rel(u, v) <= 1e-15
+
+
+# --------------------------------------------------- partial-wave (radial) step, Sec. 3
+def _legendre_cos_matrix(l0, nl):
+    """<Y_l0|cos(theta)|Y_l'0> for l, l' = l0 .. l0+nl-1 by Gauss-Legendre quadrature of the
+    normalised Legendre polynomials (independent of any closed form)."""
+    from numpy.polynomial import legendre
+
+    xq, wq = legendre.leggauss(2 * (l0 + nl) + 4)
+    P = np.array([legendre.legval(xq, np.eye(l0 + nl)[l]) * np.sqrt((2 * l + 1) / 2.0)
+                  for l in range(l0, l0 + nl)])
+    return (P * wq * xq) @ P.T
+
+
+def _dense_cn(H, dt, psi):
+    n = H.shape[0]
+    return np.linalg.solve(np.eye(n) + 0.5j * dt * H, (np.eye(n) - 0.5j * dt * H) @ psi)
+
+
+@pytest.mark.parametrize("l0,nl", [(0, 1), (0, 5), (3, 4)])
+def test_radial_step_matches_dense_split(oracle_mod, l0, nl):
+    """The partial-wave step against a dense restatement: H_l = -1/2 D2 + V + l(l+1)/(2 r^2)
+    per wave (D2 the second-difference matrix), then H_E = E r C across waves with C from
+    quadrature, each applied as a dense CN step."""
+    nr, dr, dt, E = 24, 0.25, 0.05, 0.7
+    g = np.random.default_rng(l0 + 10 * nl)
+    r = dr * np.arange(1, nr + 1)
+    V = -1.0 / np.sqrt(r * r + 1.0)
+    psi = workloads.complex_normal(g, nl * nr)
+    got = oracle_mod.radial_step(psi, V, dr, dt, E, l0, nl)
+    ref = psi.reshape(nl, nr).copy()
+    for k in range(nl):
+        l = l0 + k
+        H = hamiltonian_dense(V + l * (l + 1) / (2 * r * r), dr)
+        ref[k] = _dense_cn(H, dt, ref[k])
+    C = _legendre_cos_matrix(l0, nl)
+    for j in range(nr):
+        ref[:, j] = _dense_cn(E * r[j] * C, dt, ref[:, j])
+    assert rel(got, ref.ravel()) <= 1e-13
+    # both halves are unitary: the norm is kept
+    assert abs(np.linalg.norm(got) / np.linalg.norm(psi) - 1) <= 1e-13
+
+
+def test_radial_single_wave_without_field_is_the_1d_step(oracle_mod):
+    nr, dr, dt = 500, 0.1, 0.02
+    g = np.random.default_rng(2)
+    V = g.uniform(-1, 0, nr)
+    psi = workloads.complex_normal(g, nr)
+    got = oracle_mod.radial_step(psi, V, dr, dt, 0.3, 0, 1)
+    np.testing.assert_array_equal(got, oracle_mod.cn_step(psi, V, dr, dt))
+
+
+def test_legendre_quadrature_pin_is_tridiagonal(oracle_mod):
+    """The quadrature matrix is the tridiagonal coupling the radial step uses: zero off the
+    first off-diagonals, symmetric, and the known closed form there."""
+    C = _legendre_cos_matrix(0, 8)
+    off = np.array([(l + 1) / np.sqrt((2 * l + 1) * (2 * l + 3)) for l in range(7)])
+    assert np.allclose(np.diag(C, 1), off, atol=1e-14)
+    assert np.allclose(C - np.diag(np.diag(C, 1), 1) - np.diag(np.diag(C, 1), -1), 0, atol=1e-14)
