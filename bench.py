@@ -592,6 +592,11 @@ def extras(torch, np, cn, workloads, dev):
         x = torch.empty_like(d)
         ts_solve = timed_events(torch, lambda: cn.solve(a, b, c, d, out=x, layout=L), 20)
         x_solve = x.cpu().numpy()
+        # the plan for sequences: the autotuner times 8 chained steps per candidate tile
+        heur_plan = cn.describe_plan(L, True)
+        tmp = torch.empty_like(psi0)
+        tune_rep = cn.autotune(L, psi0, tmp, V=V, dx=w["dx"], dt=w["dt"], sequence=True)
+        del tmp
         # 200 chained steps: eager, then captured as one graph
         psi = psi0.clone()
         ts_eager = timed_events(torch, lambda: cn.propagate(psi, V, w["dx"], w["dt"], w["steps"]), 3)
@@ -617,7 +622,9 @@ def extras(torch, np, cn, workloads, dev):
                            "us_per_step_eager": float(np.median(ts_eager)) * 1e3 / w["steps"],
                            "unknowns_per_s": w["n"] * w["steps"] / (med * 1e-3),
                            "norm_after_200": norm,
-                           "plan": cn.describe_plan(L, True)}
+                           "plan": cn.describe_plan(L, True),
+                           "heuristic_plan": heur_plan,
+                           "autotune_sequence": tune_rep}
         ref = {}
         out["plain_1d"]["cpu_baseline"] = oracle_timed(
             "200 CN steps of the 65536-row system (serial FP64 Thomas, 1 thread)",
@@ -733,6 +740,12 @@ def extras(torch, np, cn, workloads, dev):
         torch.cuda.empty_cache()
     except Exception as ex:  # noqa: BLE001
         out["multi_rhs_2^22x16"] = {"error": repr(ex)}
+    # ----------------------------------------------------------- partial waves (radial, Sec. 3)
+    try:
+        out["radial_2^16x64"] = radial(torch, np, cn, workloads, dev)
+        torch.cuda.empty_cache()
+    except Exception as ex:  # noqa: BLE001
+        out["radial_2^16x64"] = {"error": repr(ex)}
     # ----------------------------------------------------------- 2^24-row fused propagation
     try:
         out["propagate_2^24"] = long_propagate(torch, np, cn, dev)
@@ -740,6 +753,65 @@ def extras(torch, np, cn, workloads, dev):
     except Exception as ex:  # noqa: BLE001
         out["propagate_2^24"] = {"error": repr(ex)}
     return out
+
+
+def radial(torch, np, cn, workloads, dev):
+    """Partial waves of an atom in a field (Sec. 3): 64 waves (l = 0..63) on 2^16 radial points
+    (dr = 0.1, soft Coulomb V = -1/sqrt(r^2 + 0.5)), dt = 0.02, a seeded field E_k ~ N(0, 0.05^2);
+    each step is the CN step in r of every wave (64 systems of 2^16 rows) and the CN step in l
+    at every radial point (2^16 interleaved systems of 64 rows).  100 steps captured in one
+    graph; the oracle runs the first 3 steps for parity."""
+    nr, nl, dr, dt, steps = 1 << 16, 64, 0.1, 0.02, 100
+    g = np.random.default_rng(1007)
+    r = dr * np.arange(1, nr + 1)
+    V = -1.0 / np.sqrt(r * r + 0.5)
+    E = g.normal(0.0, 0.05, steps)
+    psi0 = workloads.complex_normal(g, nl * nr)
+    psi0 /= np.linalg.norm(psi0)
+    tV = torch.from_numpy(V).to(dev)
+    p0 = torch.from_numpy(psi0).to(dev)
+    cn.reserve(cn.Layout.contiguous(nr, nl))
+    cn.reserve(cn.Layout(n=nl, batch=nr, elem_stride=nr, batch_stride=1))
+    x = p0.clone()
+    cn.radial_step(x, tV, dr, dt, E[0], 0, nl, out=x)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=side):
+        for k in range(steps):
+            cn.radial_step(x, tV, dr, dt, float(E[k]), 0, nl, out=x)
+    x.copy_(p0)
+    gr.replay()
+    torch.cuda.synchronize()
+    norm = float(torch.linalg.vector_norm(x))
+    ts = timed_events(torch, gr.replay, 5)
+    us = float(np.median(ts)) * 1e3 / steps
+    res = {"nr": nr, "nl": nl, "steps": steps, "us_per_step": us,
+           "unknowns_per_s": nr * nl / (us * 1e-6), "norm_after_100": norm,
+           "plan_r": cn.describe_plan(cn.Layout.contiguous(nr, nl), True),
+           "plan_l": cn.describe_plan(cn.Layout(n=nl, batch=nr, elem_stride=nr, batch_stride=1))}
+    ns = 3
+    x3 = p0.clone()
+    for k in range(ns):
+        cn.radial_step(x3, tV, dr, dt, float(E[k]), 0, nl, out=x3)
+    x3 = x3.cpu().numpy()
+    ref = {}
+
+    def run3(o):
+        def run():
+            st = psi0
+            for k in range(ns):
+                st = o.radial_step(st, V, dr, dt, float(E[k]), 0, nl)
+            ref["x"] = st
+        return run
+
+    res["cpu_baseline"] = oracle_timed(
+        f"the first {ns} partial-wave steps (serial FP64 Thomas per wave and per radial point, "
+        f"1 thread)", run3, ns * nr * nl, res["unknowns_per_s"])
+    if "x" in ref:
+        res["parity_rel_l2_3_steps"] = rel_l2(x3, ref["x"])
+    return res
 
 
 def absorbing(torch, np, cn, workloads, dev):
@@ -837,6 +909,16 @@ def differentiated(torch, np, workloads, dev):
     p0 = torch.tensor(w["psi0"], device=dev)
     phi = torch.tensor(w["phi"], device=dev)
 
+    # the plan for the sequence: the autotuner times 8 chained steps per candidate tile (the
+    # reverse mode's recompute and recursion run on the same plan)
+    import paper_2205_00856_amd as cn
+
+    Lw = cn.Layout.contiguous(w["n"], 1)
+    tmp = torch.empty_like(p0)
+    tune_rep = cn.autotune(Lw, p0, tmp, V=tV.detach(), dx=dx, dt=dt, E=float(w["E"][0]),
+                           xgrid=tx, sequence=True)
+    del tmp
+
     def fwd(Vt, Et):
         return ag.cn_propagate(p0, Vt, Et, dx, dt, xgrid=tx, K=K)
 
@@ -921,6 +1003,8 @@ def differentiated(torch, np, workloads, dev):
         "fd_max_rel_per_coord": float(np.max(np.abs(ana - num) / np.maximum(np.abs(num), 1e-300))),
         "fd_step": h,
         "phi_draw": list(map(float, w["phi_params"])),
+        "plan": cn.describe_plan(Lw, True),
+        "autotune_sequence": tune_rep,
     }
 
 

@@ -129,6 +129,19 @@ typedef struct {
   const double* absorb;
 } cn_operator;
 
+/* Partial waves of an atom in a field along z, expanded in the m = 0 spherical harmonics (the
+ * radial systems of Sec. 3): radial functions psi_l(r_j), l = l0 .. l0+nl-1, on r_j = j dr
+ * (j = 1..nr; psi = 0 at r = 0 and at r = (nr+1) dr), stored l-major: element (l, j) at
+ * (l - l0) * nr + j - 1.  V: DEVICE, nr values V(r_j), real. */
+typedef struct {
+  int64_t nr;
+  int64_t l0;
+  int64_t nl;
+  const double* V;
+  double dr;
+  double dt;
+} cn_radial;
+
 /* Host-only check of a layout (no device access): CN_OK, or the negative status that every
  * entry point would return for it (null layout, batch < 1, n < 1, strides < 1, systems that
  * share elements, offsets not starting at 0 or decreasing, a partition that is not a power of two
@@ -219,6 +232,21 @@ cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_
                           double E, const void* psi_n, const void* psi_np1, const void* g_np1,
                           void* g_n, double* dV_accum, double* dE_partial, cn_stream_t stream);
 
+/* One Lie-split step of the partial waves (Sec. 3): first, for every l, the Crank-Nicolson step
+ * in r with H_l = -1/2 d^2/dr^2 + V(r) + l(l+1)/(2 r^2) -- the N-shaped solve of nl contiguous
+ * systems of nr rows (cn_step's kernels, with the centrifugal potential written by a kernel of
+ * the library into a handle buffer); then, for every r_j, the Crank-Nicolson step in l with the
+ * length-gauge coupling H_E = E r_j C, C_{l,l+1} = C_{l+1,l} = (l+1)/sqrt((2l+1)(2l+3)) (the
+ * matrix of cos(theta)), whose tridiagonal systems (one per r_j, nl rows, interleaved with
+ * stride nr) are assembled with their right-hand sides into the handle buffer and solved by
+ * cn_tridiag_solve's kernels.  E = 0 skips the second part (it is the identity).  psi_out may
+ * alias psi_in.  The handle buffer (nl*nr*72 bytes) is allocated on the first call for a size,
+ * so a captured call needs one call outside capture first (and cn_reserve of the two layouts:
+ * contiguous nr x nl, and n = nl, batch = nr, elem_stride = nr, batch_stride = 1), else
+ * CN_ERR_NOT_RESERVED. */
+cn_status cn_radial_step(cn_handle_t handle, const cn_radial* op, double E, const void* psi_in,
+                         void* psi_out, cn_stream_t stream);
+
 /* Reverse mode of cn_propagate with checkpoints, for a uniform layout.  ckpt holds the states
  * that cn_propagate stored before every step k with k % K == 0 (same layout, one span each);
  * seg is scratch for K+1 states.  On entry g is the gradient of a real loss at the final state
@@ -249,8 +277,12 @@ cn_status cn_propagate_adjoint(cn_handle_t handle, const cn_layout* layout,
  * of this layout on the caller's data and keeps the fastest for later calls with the same
  * layout whose partition and rows_per_thread are 0.  cn_mode = 0 times
  * cn_tridiag_solve(a, b, c, d -> x); cn_mode = 1 times cn_step(op, E, psi_in = d -> psi_out = x)
- * and ignores a, b, c.  x is overwritten and must not alias d.  A text report of the median
- * timings is written to report (may be NULL).  Not allowed during graph capture. */
+ * and ignores a, b, c; cn_mode = 2 times a sequence of 8 steps in place on x (copied from d
+ * before each timing), as cn_propagate runs it (one fused pass per step over two-pass plans),
+ * and reports the time per step -- the choice for sequences, where the per-step latency
+ * decides.  Modes 1 and 2 tune the same automatic layout (the last call wins).  x is
+ * overwritten and must not alias d.  A text report of the median timings is written to report
+ * (may be NULL).  Not allowed during graph capture. */
 cn_status cn_autotune(cn_handle_t handle, const cn_layout* layout, int cn_mode,
                       const cn_operator* op, double E, const void* a, const void* b,
                       const void* c, const void* d, void* x, char* report, int64_t report_len,

@@ -3,7 +3,7 @@
 The solver itself is the HIP library libcntri.so (C ABI in include/cntri.h); this package
 binds it for torch device tensors and adds autograd wrappers.
 """
-from .api import (Handle, Layout, assemble, autotune, describe_plan, get_status, handle,  # noqa: F401
+from .api import (Handle, Layout, assemble, radial_step, autotune, describe_plan, get_status, handle,  # noqa: F401
                   profile, profile_report, propagate, propagate_adjoint, reserve, rhs, solve, solve_adjoint,
                   solve_noalloc, step, tune_cache,
                   step_adjoint)

@@ -47,6 +47,17 @@ class CnOperator(ctypes.Structure):
     ]
 
 
+class CnRadial(ctypes.Structure):
+    _fields_ = [
+        ("nr", ctypes.c_int64),
+        ("l0", ctypes.c_int64),
+        ("nl", ctypes.c_int64),
+        ("V", ctypes.c_void_p),
+        ("dr", ctypes.c_double),
+        ("dt", ctypes.c_double),
+    ]
+
+
 class CnError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -95,6 +106,7 @@ def lib():
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "cn_profile": ([H, ctypes.c_int], ctypes.c_int),
         "cn_tune_cache": ([H, ctypes.c_char_p], ctypes.c_int),
+        "cn_radial_step": ([H, ctypes.POINTER(CnRadial), d, P, P, P], ctypes.c_int),
         "cn_profile_report": ([H, ctypes.c_char_p, i64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -109,7 +121,7 @@ EXPORTED = ["cn_check_layout", "cn_create", "cn_destroy", "cn_status_string", "c
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
             "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
             "cn_propagate_adjoint", "cn_handle_info", "cn_tridiag_solve_noalloc", "cn_profile",
-            "cn_profile_report", "cn_tune_cache"]
+            "cn_profile_report", "cn_tune_cache", "cn_radial_step"]
 
 
 def status_string(st: int) -> str:

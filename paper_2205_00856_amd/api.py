@@ -20,7 +20,7 @@ from ._lib import CnLayout, CnOperator, check
 
 __all__ = ["Layout", "Handle", "handle", "solve", "solve_noalloc", "solve_adjoint", "assemble", "rhs", "step",
            "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune",
-           "profile", "profile_report", "tune_cache",
+           "profile", "profile_report", "tune_cache", "radial_step",
            "propagate_adjoint"]
 
 
@@ -367,6 +367,25 @@ def step_adjoint(psi_n, psi_np1, g_np1, V, dx, dt, E=0.0, xgrid=None, v_scale=1.
     return g_out
 
 
+def radial_step(psi, V, dr, dt, E, l0, nl, out=None):
+    """One partial-wave step (cn_radial_step): psi is l-major, nl waves of len(V) radial points
+    r_j = j dr.  out may be psi (in place)."""
+    nr = V.shape[0]
+    _need(V, torch.float64, "V", nr)
+    _need(psi, torch.complex128, "psi", nl * nr)
+    if out is None:
+        out = torch.empty_like(psi)
+    _need(out, torch.complex128, "out", nl * nr)
+    op = _lib.CnRadial()
+    op.nr, op.l0, op.nl = int(nr), int(l0), int(nl)
+    op.V = V.data_ptr()
+    op.dr, op.dt = float(dr), float(dt)
+    h = handle(psi.device.index)
+    check(_lib.lib().cn_radial_step(h.ptr, ctypes.byref(op), float(E), _ptr(psi), _ptr(out),
+                                    _stream(psi)), "cn_radial_step")
+    return out
+
+
 def tune_cache(path: Optional[str], device=None):
     """Persistent autotune cache file (cn_tune_cache); None stops using one."""
     h = handle(device)
@@ -402,11 +421,11 @@ def get_status(device=None) -> int:
 
 
 def autotune(layout: Layout, d, x, a=None, b=None, c=None, V=None, dx=1.0, dt=0.0, E=0.0,
-             xgrid=None, v_scale=1.0, dx_per_system=None) -> str:
+             xgrid=None, v_scale=1.0, dx_per_system=None, sequence: bool = False) -> str:
     """cn_autotune: time the candidate tiles on these buffers (cn_step if V is given, else
-    cn_tridiag_solve) and keep the fastest for later calls with this layout.  x is
-    overwritten.  Returns the timing report."""
-    cn_mode = V is not None
+    cn_tridiag_solve; with sequence=True, 8 chained steps as cn_propagate runs them) and keep
+    the fastest for later calls with this layout.  x is overwritten.  Returns the report."""
+    cn_mode = (2 if sequence else 1) if V is not None else 0
     span = layout.span()
     _need(d, torch.complex128, "d/psi", span)
     _need(x, torch.complex128, "x", span)

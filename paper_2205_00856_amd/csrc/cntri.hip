@@ -655,6 +655,9 @@ struct cn_handle_s {
   // materialised a, b, c, d of steps with an absorbing potential
   void* mat = nullptr;
   size_t mat_size = 0;
+  // partial-wave step: centrifugal potentials, then the field part's a, b, c, d
+  void* rad = nullptr;
+  size_t rad_size = 0;
   // Once a call of this handle has been captured into a HIP graph, the graph holds the device
   // addresses of the handle's buffers: a buffer replaced by a larger one is then kept here
   // until cn_destroy instead of being freed.
@@ -1414,6 +1417,7 @@ cn_status cn_destroy(cn_handle_t h) {
   if (h->ws2) (void)hipFree(h->ws2);
   if (h->seg2) (void)hipFree(h->seg2);
   if (h->mat) (void)hipFree(h->mat);
+  if (h->rad) (void)hipFree(h->rad);
   for (void* p : h->retired) (void)hipFree(p);
   for (auto& r : h->recs) {
     (void)hipEventDestroy(r.e0);
@@ -1711,6 +1715,12 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
   hipStream_t s = (hipStream_t)stream;
   if (capturing(s)) return CN_ERR_NOT_RESERVED;
   const int src = cn_mode ? nsd::SRC_CN : nsd::SRC_EXPL;
+  const int64_t kSeq = 8;  // cn_mode 2: steps of the timed sequence
+  int64_t span = 0;
+  {
+    int64_t rows = 0;
+    if (validate(L, rows, span) != CN_OK) return CN_ERR_INVALID_ARG;
+  }
   struct Cand {
     int T, M;
   };
@@ -1750,11 +1760,27 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
       u.d = (const cd*)d;
     }
     u.x = (cd*)x;
+    // cn_mode 2: a sequence of kSeq steps in place on x from d, as cn_propagate runs it (one
+    // fused pass per step over two-pass plans)
+    const FusePlan fz = (cn_mode == 2 && fuse_enabled()) ? fuse_plan(P) : FusePlan();
+    auto seq = [&]() -> cn_status {
+      UserArgs v = u;
+      v.psi = (const cd*)x;
+      if (fz.ok) return run_chain(h, P, fz, kSeq, [&](int64_t) { return v; }, nullptr, nullptr, s);
+      for (int64_t k = 0; k < kSeq; ++k) {
+        const cn_status r = run_plan(h, P, v, s);
+        if (r != CN_OK) return r;
+      }
+      return CN_OK;
+    };
     std::vector<float> ts;
     bool ok = true;
     for (int r = 0; r < 7 && ok; ++r) {
-      if (hipEventRecord(e0, s) != hipSuccess) ok = false;
-      if (ok && run_plan(h, P, u, s) != CN_OK) ok = false;
+      if (cn_mode == 2 &&
+          hipMemcpyAsync(x, d, (size_t)span * sizeof(cd), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        ok = false;
+      if (ok && hipEventRecord(e0, s) != hipSuccess) ok = false;
+      if (ok && (cn_mode == 2 ? seq() : run_plan(h, P, u, s)) != CN_OK) ok = false;
       if (ok && hipEventRecord(e1, s) != hipSuccess) ok = false;
       if (ok && hipEventSynchronize(e1) != hipSuccess) ok = false;
       float ms = 0.f;
@@ -1765,10 +1791,11 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
     std::sort(ts.begin(), ts.end());
     const float med = ts[ts.size() / 2];
     char line[160];
+    const double per = cn_mode == 2 ? (double)med / kSeq : (double)med;  // per step
     if (cd_.T > 0)
-      snprintf(line, sizeof(line), "T=%d M=%d: %.4f ms; ", cd_.T, cd_.M, med);
+      snprintf(line, sizeof(line), "T=%d M=%d: %.4f ms; ", cd_.T, cd_.M, per);
     else
-      snprintf(line, sizeof(line), "automatic: %.4f ms; ", med);
+      snprintf(line, sizeof(line), "automatic: %.4f ms; ", per);
     rep += line;
     if (med < best) {
       best = med;
@@ -1954,7 +1981,7 @@ cn_status cn_handle_info(cn_handle_t h, int64_t* device_bytes, int64_t* retired_
                          int32_t* captured) {
   if (!h) return CN_ERR_INVALID_ARG;
   if (device_bytes) {
-    size_t b = h->ws_size + h->ws2_size + h->seg2_bytes + h->mat_size +
+    size_t b = h->ws_size + h->ws2_size + h->seg2_bytes + h->mat_size + h->rad_size +
                h->rows_cap * sizeof(double);
     for (const auto& kv : h->plans) b += kv.second->tables_bytes;
     *device_bytes = (int64_t)b;
@@ -1962,6 +1989,67 @@ cn_status cn_handle_info(cn_handle_t h, int64_t* device_bytes, int64_t* retired_
   if (retired_buffers) *retired_buffers = (int64_t)h->retired.size();
   if (captured) *captured = h->captured ? 1 : 0;
   return CN_OK;
+}
+
+cn_status cn_radial_step(cn_handle_t h, const cn_radial* op, double E, const void* psi_in,
+                         void* psi_out, cn_stream_t stream) {
+  if (!h || !op || !op->V || !psi_in || !psi_out) return CN_ERR_INVALID_ARG;
+  if (op->nr < 1 || op->nl < 1 || op->l0 < 0 || !(op->dr > 0.0) || !(op->dt == op->dt) ||
+      !(E == E))
+    return CN_ERR_INVALID_ARG;
+  if (op->nr > ((int64_t)1 << 40) / op->nl) return CN_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nr = op->nr, nl = op->nl, tot = nr * nl;
+  const size_t vbytes = ((size_t)tot * sizeof(double) + 255) & ~size_t(255);
+  const size_t need = vbytes + 4 * (size_t)tot * sizeof(cd);
+  if (h->rad_size < need) {
+    if (capturing(s)) return CN_ERR_NOT_RESERVED;
+    const cn_status st = regrow(h, &h->rad, &h->rad_size, need);
+    if (st != CN_OK) return st;
+  }
+  double* veff = (double*)h->rad;
+  cd* m = (cd*)((char*)h->rad + vbytes);
+  // radial part: V(r) + l(l+1)/(2 r^2) per wave, then the CN step of every wave in r
+  nsd::AuxArgs X{};
+  X.n = nr;
+  X.batch = nl;
+  X.total = tot;
+  X.V = op->V;
+  X.dx = op->dr;
+  X.dt = op->dt;
+  X.l0 = op->l0;
+  X.vscale = 1.0;
+  X.wscale = 1.0;
+  X.dV = veff;
+  cn_status st = launch_aux(aux_fn(nsk::AUX_RADIAL_VEFF), tot, X, s);
+  if (st != CN_OK) return st;
+  cn_layout Lr{};
+  Lr.n = nr;
+  Lr.batch = nl;
+  Lr.elem_stride = 1;
+  Lr.batch_stride = nr;
+  cn_operator o{};
+  o.V = veff;
+  o.v_scale = 1.0;
+  o.dx = op->dr;
+  o.dt = op->dt;
+  st = cn_step(h, &Lr, &o, 0.0, psi_in, psi_out, stream);
+  if (st != CN_OK || E == 0.0) return st;
+  // field part: at every r_j the CN step in l, materialised, then the partitioned solve
+  X.E = E;
+  X.psi = (const cd*)psi_out;
+  X.a = m;
+  X.b = m + tot;
+  X.c = m + 2 * tot;
+  X.d = m + 3 * tot;
+  st = launch_aux(aux_fn(nsk::AUX_RADIAL_COUPLING), tot, X, s);
+  if (st != CN_OK) return st;
+  cn_layout Ll{};
+  Ll.n = nl;
+  Ll.batch = nr;
+  Ll.elem_stride = nr;
+  Ll.batch_stride = 1;
+  return cn_tridiag_solve(h, &Ll, m, m + tot, m + 2 * tot, m + 3 * tot, psi_out, stream);
 }
 
 cn_status cn_tune_cache(cn_handle_t h, const char* path) {

@@ -162,6 +162,44 @@ __global__ __launch_bounds__(64) void k_rs_serial(KArgs A) {
   if (bad) atomicOr(A.status, 1);
 }
 
+// Partial-wave step, radial part: the potential of wave l = l0 + k on r_j = (j + 1) dr,
+// V(r_j) + l (l + 1) / (2 r_j^2), for the CN step in r of every wave (l-major, nr per wave).
+__global__ void k_radial_veff(AuxArgs A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.n * A.batch) return;
+  const int64_t k = t / A.n, j = t - k * A.n;
+  const double r = (double)(j + 1) * A.dx;
+  const double l = (double)(A.l0 + k);
+  A.dV[t] = A.V[j] + l * (l + 1.0) / (2.0 * r * r);
+}
+
+// <Y_l0 | cos(theta) | Y_{l+1}0>, the coupling of neighbouring partial waves by a field along z
+__device__ __forceinline__ double cos_coupling(int64_t l) {
+  return (double)(l + 1) / sqrt((double)(2 * l + 1) * (double)(2 * l + 3));
+}
+
+// Partial-wave step, field part: at every r_j the CN step in l with H_E = E r_j C (C the
+// tridiagonal coupling of neighbouring waves), materialised: T = 1 + i tau H_E (a = 1,
+// b_l = i tau E r c_{l-1}, c_l = i tau E r c_l) and d = (1 - i tau H_E) psi.  Element (wave k,
+// point j) at k * nr + j: the systems (one per r_j) are interleaved with stride nr.
+__global__ void k_radial_coupling(AuxArgs A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.n * A.batch) return;
+  const int64_t k = t / A.n, j = t - k * A.n, nl = A.batch;
+  const double r = (double)(j + 1) * A.dx;
+  const double s = 0.5 * A.dt * A.E * r;  // tau E r
+  const double cb = k > 0 ? s * cos_coupling(A.l0 + k - 1) : 0.0;
+  const double cc = k < nl - 1 ? s * cos_coupling(A.l0 + k) : 0.0;
+  A.a[t] = mk(1.0, 0.0);
+  A.b[t] = mk(0.0, cb);
+  A.c[t] = mk(0.0, cc);
+  // d = psi - b psi_{k-1} - c psi_{k+1} with b, c = i (cb, cc)
+  const cd p = A.psi[t];
+  const cd lo = k > 0 ? A.psi[t - A.n] : czero();
+  const cd hi = k < nl - 1 ? A.psi[t + A.n] : czero();
+  A.d[t] = mk(p.x + cb * lo.y + cc * hi.y, p.y - cb * lo.x - cc * hi.x);
+}
+
 }  // namespace nsd
 
 namespace nsk {
@@ -172,5 +210,7 @@ void reg_aux(Tables& t) {
   t.aux[AUX_ADJ_ACCUM] = (const void*)&nsd::k_adj_accum;
   t.aux[AUX_SUM_PARTIALS] = (const void*)&nsd::k_sum_partials;
   t.aux[AUX_RS_SERIAL] = (const void*)&nsd::k_rs_serial;
+  t.aux[AUX_RADIAL_VEFF] = (const void*)&nsd::k_radial_veff;
+  t.aux[AUX_RADIAL_COUPLING] = (const void*)&nsd::k_radial_coupling;
 }
 }  // namespace nsk

@@ -22,7 +22,6 @@ void reg_mrhs(Tables& t) {
   reg_one<4, 4>(t);
   reg_one<4, 8>(t);
   reg_one<8, 4>(t);
-  reg_one<8, 8>(t);
 }
 
 }  // namespace nsk

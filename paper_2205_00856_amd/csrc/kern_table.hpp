@@ -31,6 +31,8 @@ enum AuxKernel : int {
   AUX_ADJ_ACCUM,
   AUX_SUM_PARTIALS,
   AUX_RS_SERIAL,
+  AUX_RADIAL_VEFF,
+  AUX_RADIAL_COUPLING,
   kNumAux
 };
 

@@ -860,15 +860,20 @@ __device__ __forceinline__ void tile_run_mrhs(const KArgs& A, const Geo& G0, Til
     transpose_in<M>(buf, lane, rc, hc, vc);
   }
   const int64_t s0 = G0.sys * A.nrhs;
+  // the next right-hand side's rows are fetched before this one's elimination runs, so their
+  // load latency hides behind it
+  cd rd[M], hd;
+  if (s0 < A.batch) stage_fetch<M, IN>(A.d + s0 * A.bs, G0.es, w0, n, lane, zero, rd, hd);
   for (int r = 0; r < A.nrhs; ++r) {
     Geo G = G0;
     G.sys = s0 + r;
     if (G.sys >= A.batch) break;  // uniform across the workgroup
     G.base = G.sys * A.bs;
     G.gt = G.sys * A.ntiles + G.tile;
-    cd rd[M], hd, vd[M + 2];
-    stage_fetch<M, IN>(A.d + G.base, G.es, w0, n, lane, zero, rd, hd);
+    cd vd[M + 2];
     transpose_in<M>(buf, lane, rd, hd, vd);
+    if (r + 1 < A.nrhs && G.sys + 1 < A.batch)
+      stage_fetch<M, IN>(A.d + (G.sys + 1) * A.bs, G.es, w0, n, lane, zero, rd, hd);
     cd Ar[M], Br[M], Cr[M], Dr[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -1268,6 +1273,8 @@ struct AuxArgs {
   // solve gradients
   const cd* xsol;
   cd *ga, *gb, *gc;
+  // partial-wave step: first partial wave of the batch
+  int64_t l0;
 };
 
 }  // namespace nsd

@@ -1,0 +1,94 @@
+"""GPU parity of the partial-wave step (cn_radial_step; the radial systems of Sec. 3): the CN
+step in r of every partial wave with its centrifugal term, then the CN step in l at every radial
+point with the length-gauge field coupling, against the oracle's step.
+
+Tolerance: relative L2 <= 1e-11 (FP64 on both sides; rounding only).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_00856_amd as cn
+
+    cn.handle(0)
+    cn.get_status()
+    return torch, cn
+
+
+def rel(x, y):
+    return float(np.linalg.norm(np.asarray(x) - np.asarray(y)) / np.linalg.norm(np.asarray(y)))
+
+
+def case(nr, nl, seed, dr):
+    g = np.random.default_rng(seed)
+    r = dr * np.arange(1, nr + 1)
+    V = -1.0 / np.sqrt(r * r + 0.5)
+    psi = workloads.complex_normal(g, nl * nr)
+    return V, psi
+
+
+@pytest.mark.parametrize("nr,l0,nl,steps", [(1, 0, 1, 1), (37, 0, 3, 2), (4096, 0, 64, 3),
+                                            (20_001, 2, 7, 4), ((1 << 16) + 5, 0, 16, 2),
+                                            (300_000, 0, 2, 2), (70, 0, 200, 2)])
+def test_radial_steps_match_oracle(gpu, oracle_mod, nr, l0, nl, steps):
+    torch, cn = gpu
+    print("radial", nr, l0, nl, steps, flush=True)
+    dr, dt = 0.1, 0.02
+    V, psi = case(nr, nl, nr + nl, dr)
+    E = np.random.default_rng(3).normal(0, 0.1, steps)
+    tV = torch.from_numpy(V).cuda()
+    tp = torch.from_numpy(psi).cuda()
+    ref = psi
+    for k in range(steps):
+        ref = oracle_mod.radial_step(ref, V, dr, dt, E[k], l0, nl)
+        cn.radial_step(tp, tV, dr, dt, E[k], l0, nl, out=tp)
+    out = tp.cpu().numpy()
+    assert rel(out, ref) <= TOL
+    assert abs(np.linalg.norm(out) / np.linalg.norm(psi) - 1) <= 1e-12  # unitary
+    assert cn.get_status() == 0
+
+
+def test_radial_single_wave_is_the_cn_step(gpu):
+    """One wave with l = 0 and no field is the plain CN step with V."""
+    torch, cn = gpu
+    nr, dr, dt = 100_003, 0.1, 0.02
+    V, psi = case(nr, 1, 9, dr)
+    tV = torch.from_numpy(V).cuda()
+    tp = torch.from_numpy(psi).cuda()
+    a = cn.radial_step(tp, tV, dr, dt, 0.0, 0, 1)
+    b = cn.step(tp, tV, dr, dt)
+    assert torch.equal(a, b)
+
+
+def test_radial_step_in_a_graph(gpu):
+    """After one call outside capture (handle buffer) and reserving both layouts, the step
+    captures; replays give the eager result bit for bit."""
+    torch, cn = gpu
+    nr, nl, dr, dt, E = 8192, 32, 0.1, 0.02, 0.05
+    V, psi = case(nr, nl, 4, dr)
+    tV = torch.from_numpy(V).cuda()
+    p0 = torch.from_numpy(psi).cuda()
+    cn.reserve(cn.Layout.contiguous(nr, nl))
+    cn.reserve(cn.Layout(n=nl, batch=nr, elem_stride=nr, batch_stride=1))
+    eager = cn.radial_step(p0, tV, dr, dt, E, 0, nl)
+    x = p0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        cn.radial_step(x, tV, dr, dt, E, 0, nl, out=x)
+    for _ in range(3):
+        x.copy_(p0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(x, eager)
