@@ -56,6 +56,12 @@ def parse():
                    help="time only the 2^24-row fused propagation, for profiling")
     p.add_argument("--only-absorbing", action="store_true",
                    help="time only the 2^24-row steps with an absorbing potential, for profiling")
+    p.add_argument("--only-uneven", action="store_true",
+                   help="time only the uneven batch (steps and a propagation), for profiling")
+    p.add_argument("--only-multi-rhs", action="store_true",
+                   help="time only the 2^22 x 16 shared-matrix solve, for profiling")
+    p.add_argument("--only-radial", action="store_true",
+                   help="time only the partial-wave steps, for profiling")
     p.add_argument("--copy-ref", action="store_true",
                    help="first run a plain 256 MiB device copy three times (a reference of known "
                         "size for scaling hardware byte counters)")
@@ -148,6 +154,15 @@ def main():
         return
     if args.only_absorbing:
         print(json.dumps(absorbing_large(torch, np, cn, workloads, dev)), flush=True)
+        return
+    if args.only_uneven:
+        print(json.dumps(uneven_timing(torch, np, cn, workloads, dev)), flush=True)
+        return
+    if args.only_multi_rhs:
+        print(json.dumps(multi_rhs(torch, np, cn, dev, oracle=False)), flush=True)
+        return
+    if args.only_radial:
+        print(json.dumps(radial(torch, np, cn, workloads, dev, parity=False)), flush=True)
         return
 
     # ---------------------------------------------------------------- headline: ADI 4096^2
@@ -503,7 +518,7 @@ def long_propagate(torch, np, cn, dev, parity=True):
     return out
 
 
-def multi_rhs(torch, np, cn, dev):
+def multi_rhs(torch, np, cn, dev, oracle=True):
     """One 2^22-row matrix (the 2^28 solve's distribution) with 16 right-hand sides: the batch
     reads the matrix of system 0 (shared_coefficients), against the same batch with the matrix
     copied for every right-hand side.  Algorithmic bytes of the shared solve: each right-hand
@@ -536,6 +551,8 @@ def multi_rhs(torch, np, cn, dev):
            "frac_of_peak": algo / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "shared_vs_replicated_rel_l2": same,
            "plan": cn.describe_plan(Ls)}
+    if not oracle:
+        return out
     ref = {}
     a0, b0, c0 = (t.cpu().numpy() for t in (a, b, c))
     dd = d.cpu().numpy()
@@ -755,7 +772,7 @@ def extras(torch, np, cn, workloads, dev):
     return out
 
 
-def radial(torch, np, cn, workloads, dev):
+def radial(torch, np, cn, workloads, dev, parity=True):
     """Partial waves of an atom in a field (Sec. 3): 64 waves (l = 0..63) on 2^16 radial points
     (dr = 0.1, soft Coulomb V = -1/sqrt(r^2 + 0.5)), dt = 0.02, a seeded field E_k ~ N(0, 0.05^2);
     each step is the CN step in r of every wave (64 systems of 2^16 rows) and the CN step in l
@@ -791,6 +808,8 @@ def radial(torch, np, cn, workloads, dev):
            "unknowns_per_s": nr * nl / (us * 1e-6), "norm_after_100": norm,
            "plan_r": cn.describe_plan(cn.Layout.contiguous(nr, nl), True),
            "plan_l": cn.describe_plan(cn.Layout(n=nl, batch=nr, elem_stride=nr, batch_stride=1))}
+    if not parity:
+        return res
     ns = 3
     x3 = p0.clone()
     for k in range(ns):
@@ -812,6 +831,27 @@ def radial(torch, np, cn, workloads, dev):
     if "x" in ref:
         res["parity_rel_l2_3_steps"] = rel_l2(x3, ref["x"])
     return res
+
+
+def uneven_timing(torch, np, cn, workloads, dev):
+    """The uneven batch alone (automatic plan): 10 single steps, then 10 steps of cn_propagate."""
+    wl = workloads.uneven_batch()
+    L = cn.Layout.uneven(wl["offsets"])
+    psi = torch.from_numpy(wl["psi0"]).to(dev)
+    V = torch.from_numpy(wl["V"]).to(dev)
+    dxs = torch.from_numpy(wl["dx"]).to(dev)
+    rows = int(wl["offsets"][-1])
+    cn.reserve(L)
+    cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi, layout=L)
+    ts = timed_events(torch, lambda: cn.step(psi, V, 0.0, wl["dt"], dx_per_system=dxs, out=psi,
+                                             layout=L), 10)
+    tp = timed_events(torch, lambda: cn.propagate(psi, V, 0.0, wl["dt"], 10, dx_per_system=dxs,
+                                                  layout=L), 2)
+    med, medp = float(np.median(ts)), float(np.median(tp)) / 10
+    return {"rows": rows, "ms_per_step": med, "ms_per_step_propagate": medp,
+            "GBps_40_step": 40 * rows / (med * 1e-3) / 1e9,
+            "GBps_40_propagate": 40 * rows / (medp * 1e-3) / 1e9,
+            "plan": cn.describe_plan(L, True)}
 
 
 def absorbing(torch, np, cn, workloads, dev):

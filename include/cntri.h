@@ -238,12 +238,13 @@ cn_status cn_step_adjoint(cn_handle_t handle, const cn_layout* layout, const cn_
  * the library into a handle buffer); then, for every r_j, the Crank-Nicolson step in l with the
  * length-gauge coupling H_E = E r_j C, C_{l,l+1} = C_{l+1,l} = (l+1)/sqrt((2l+1)(2l+3)) (the
  * matrix of cos(theta)), whose tridiagonal systems (one per r_j, nl rows, interleaved with
- * stride nr) are assembled with their right-hand sides into the handle buffer and solved by
- * cn_tridiag_solve's kernels.  E = 0 skips the second part (it is the identity).  psi_out may
- * alias psi_in.  The handle buffer (nl*nr*72 bytes) is allocated on the first call for a size,
- * so a captured call needs one call outside capture first (and cn_reserve of the two layouts:
- * contiguous nr x nl, and n = nl, batch = nr, elem_stride = nr, batch_stride = 1), else
- * CN_ERR_NOT_RESERVED. */
+ * stride nr) are solved by the column kernels with their rows and right-hand sides built from
+ * psi in-kernel (nr >= 64), or, for fewer radial points, assembled into the handle buffer and
+ * solved by cn_tridiag_solve's kernels.  E = 0 skips the second part (it is the identity).
+ * psi_out may alias psi_in.  The handle buffer (nl*nr*8 bytes, 72 with fewer than 64 radial
+ * points) is allocated on the first call for a size, so a captured call needs one call outside
+ * capture first (and cn_reserve of the two layouts: contiguous nr x nl, and n = nl, batch =
+ * nr, elem_stride = nr, batch_stride = 1), else CN_ERR_NOT_RESERVED. */
 cn_status cn_radial_step(cn_handle_t handle, const cn_radial* op, double E, const void* psi_in,
                          void* psi_out, cn_stream_t stream);
 

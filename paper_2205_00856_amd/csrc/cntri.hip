@@ -357,7 +357,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       }
       const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
       const int64_t oP = B.add_ws(G * sizeof(cd));
-      const int64_t oH = nsd::cn_src(src) ? B.add_ws(2 * G * sizeof(cd)) : -1;
+      const int64_t oH = nsd::halo_src(src) ? B.add_ws(2 * G * sizeof(cd)) : -1;
       snprintf(line, sizeof(line), "L%d columns multi %s n=%lld batch=%lld tiles=%lld; ", level, cs,
                (long long)n, (long long)batch, (long long)K);
       B.desc += line;
@@ -1023,6 +1023,7 @@ struct UserArgs {
   int acc_half = 0;
   const double* W = nullptr;  // absorbing potential (SRC_CNW)
   double wscale = 1.0;
+  int64_t l0 = 0;  // SRC_LCOUP: partial wave of row 0
 };
 
 // Kernel arguments of one launch of a plan for the caller's arrays u and workspace ws.
@@ -1051,6 +1052,7 @@ KArgs plan_args(cn_handle_t h, const Launch& l, const UserArgs& u, char* ws) {
     a.acc_half = u.acc_half;
     a.Wabs = u.W;
     a.wscale = u.wscale;
+    a.l0 = u.l0;
   }
   a.x = (l.o_x >= 0) ? (cd*)(ws + l.o_x) : u.x;
   if (l.o_sU >= 0) a.sU = (const cd*)(ws + l.o_sU);
@@ -1435,9 +1437,9 @@ cn_status cn_reserve(cn_handle_t h, const cn_layout* L) {
   if (!h) return CN_ERR_INVALID_ARG;
   Plan* P = nullptr;
   size_t ws2 = 0;  // the second workspace of the reverse mode's fused chain
-  for (int src : {nsd::SRC_EXPL, nsd::SRC_EXPL_CT, nsd::SRC_CN, nsd::SRC_CNW}) {
+  for (int src : {nsd::SRC_EXPL, nsd::SRC_EXPL_CT, nsd::SRC_CN, nsd::SRC_CNW, nsd::SRC_LCOUP}) {
     cn_status st = get_plan(h, L, src, nullptr, &P);
-    if (st == CN_ERR_UNSUPPORTED && src == nsd::SRC_CNW) continue;
+    if (st == CN_ERR_UNSUPPORTED && (src == nsd::SRC_CNW || src == nsd::SRC_LCOUP)) continue;
     if (st != CN_OK) return st;
     if (nsd::cn_src(src)) ws2 = std::max(ws2, P->ws_bytes);
   }
@@ -2000,8 +2002,25 @@ cn_status cn_radial_step(cn_handle_t h, const cn_radial* op, double E, const voi
   if (op->nr > ((int64_t)1 << 40) / op->nl) return CN_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const int64_t nr = op->nr, nl = op->nl, tot = nr * nl;
+  // the field part: at every r_j the CN step in l; its systems (one per r_j) are interleaved
+  cn_layout Ll{};
+  Ll.n = nl;
+  Ll.batch = nr;
+  Ll.elem_stride = nr;
+  Ll.batch_stride = 1;
+  // fused when the column kernels take the layout (at least 64 radial points): the rows are
+  // built from psi in-kernel; otherwise materialised into the handle buffer
+  Plan* Pc = nullptr;
+  bool fused = false;
+  if (E != 0.0) {
+    const cn_status sp = get_plan(h, &Ll, nsd::SRC_LCOUP, s, &Pc);
+    if (sp == CN_OK)
+      fused = true;
+    else if (sp != CN_ERR_UNSUPPORTED)
+      return sp;
+  }
   const size_t vbytes = ((size_t)tot * sizeof(double) + 255) & ~size_t(255);
-  const size_t need = vbytes + 4 * (size_t)tot * sizeof(cd);
+  const size_t need = vbytes + (fused || E == 0.0 ? 0 : 4 * (size_t)tot * sizeof(cd));
   if (h->rad_size < need) {
     if (capturing(s)) return CN_ERR_NOT_RESERVED;
     const cn_status st = regrow(h, &h->rad, &h->rad_size, need);
@@ -2035,7 +2054,16 @@ cn_status cn_radial_step(cn_handle_t h, const cn_radial* op, double E, const voi
   o.dt = op->dt;
   st = cn_step(h, &Lr, &o, 0.0, psi_in, psi_out, stream);
   if (st != CN_OK || E == 0.0) return st;
-  // field part: at every r_j the CN step in l, materialised, then the partitioned solve
+  if (fused) {
+    UserArgs u;
+    u.psi = (const cd*)psi_out;
+    u.x = (cd*)psi_out;
+    u.dx = op->dr;
+    u.dt = op->dt;
+    u.E_mat = E;
+    u.l0 = op->l0;
+    return run_plan(h, Pc, u, s);
+  }
   X.E = E;
   X.psi = (const cd*)psi_out;
   X.a = m;
@@ -2044,11 +2072,6 @@ cn_status cn_radial_step(cn_handle_t h, const cn_radial* op, double E, const voi
   X.d = m + 3 * tot;
   st = launch_aux(aux_fn(nsk::AUX_RADIAL_COUPLING), tot, X, s);
   if (st != CN_OK) return st;
-  cn_layout Ll{};
-  Ll.n = nl;
-  Ll.batch = nr;
-  Ll.elem_stride = nr;
-  Ll.batch_stride = 1;
   return cn_tridiag_solve(h, &Ll, m, m + tot, m + 2 * tot, m + 3 * tot, psi_out, stream);
 }
 

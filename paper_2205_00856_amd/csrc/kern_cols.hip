@@ -23,6 +23,10 @@ void reg_range(Tables& t, std::integer_sequence<int, I...>) {
 }
 }  // namespace
 
-void reg_cols(Tables& t) { reg_range(t, std::make_integer_sequence<int, kNumColCfg>{}); }
+void reg_cols(Tables& t) {
+  reg_range(t, std::make_integer_sequence<int, kNumColCfg>{});
+  // the partial waves' field coupling: the default column tile (64 rows, 16 per lane)
+  reg_src<col_cfg_index<16, 4>(), nsd::SRC_LCOUP>(t);
+}
 
 }  // namespace nsk

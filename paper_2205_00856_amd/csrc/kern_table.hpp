@@ -21,7 +21,7 @@ constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr Cfg kColCfgs[] = {{4, 8}, {8, 4}, {8, 8}, {4, 16}, {16, 4}, {8, 16}};
 constexpr int kNumColCfg = sizeof(kColCfgs) / sizeof(kColCfgs[0]);
 
-constexpr int kNumSrc = 5;  // nsd::Src
+constexpr int kNumSrc = 6;  // nsd::Src
 constexpr int kNumPh = 4;   // nsd::Phase
 
 enum AuxKernel : int {

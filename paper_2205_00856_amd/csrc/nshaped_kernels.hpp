@@ -13,12 +13,18 @@ enum Src : int {
   SRC_EXPL_CT = 1,  // explicit arrays, conjugate-transposed matrix T^H (adjoint solve)
   SRC_CN = 2,       // Crank-Nicolson operator assembled in-kernel from V, dx, dt (+ x E)
   SRC_SLOTS = 3,    // reduced system of the level below, read from its two slot arrays
-  SRC_CNW = 4       // Crank-Nicolson operator with an absorbing potential, v - i W (H not
+  SRC_CNW = 4,      // Crank-Nicolson operator with an absorbing potential, v - i W (H not
                     // Hermitian): T's diagonal 1 + tau W + i tau (...), explicit side 1 - tau W
                     // - i tau (...), off-diagonals -i kappa and +i kappa as in SRC_CN
+  SRC_LCOUP = 5     // partial waves: the CN step in l at radial point r = (system + 1) dx with
+                    // the field coupling E r C (C_{l,l+1} = (l+1)/sqrt((2l+1)(2l+3)), l = l0 +
+                    // row): T = 1 + i tau E r C, explicit side 1 - i tau E r C, both from psi
 };
 // sources whose rows are the Crank-Nicolson operator assembled in-kernel
 __host__ __device__ constexpr bool cn_src(int S) { return S == SRC_CN || S == SRC_CNW; }
+// sources whose right-hand side is built from the state's neighbouring rows: a multi-tile pass
+// that writes the state in place keeps each tile's first and last row for its neighbours
+__host__ __device__ constexpr bool halo_src(int S) { return cn_src(S) || S == SRC_LCOUP; }
 enum Phase : int {
   PH_SINGLE = 0,  // the tile holds the whole system: reduce, RS, SS in one pass
   PH_REDUCE = 1,  // first pass of a multi-tile system: reduce, write the tile's slots
@@ -85,6 +91,7 @@ struct KArgs {
   // v - i wscale W (wscale = -1 with dt -> -dt gives the conjugate-transposed operators)
   const double* Wabs;
   double wscale;
+  int64_t l0;  // SRC_LCOUP: partial wave of row 0
 };
 
 struct Geo {
@@ -1006,6 +1013,35 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
       bK = csel(r0 + M < n, vb[M + 1], zero);
     else
       bK = csel(r0 + M < n, cconj(vc[M]), zero);
+  } else if constexpr (SRC == SRC_LCOUP) {
+    // rows l = l0 + r of the field coupling at radial point r_s = (s + 1) dx of this lane's
+    // system: off-diagonals i tau E r_s c_l (pure imaginary), diagonal 1
+    const double sc = 0.5 * A.dt * A.E_mat * ((double)(G.sys + 1) * A.dx);
+    cd vp[M + 2];
+    col_fetch<M>(A.psi + c0, ob16, G.es, r0, n, zero, vp);
+    if constexpr (PH == PH_SUBST) {
+      // the neighbouring tiles' edge rows may already hold the new state
+      if (wave == 0 && G.tile > 0) vp[0] = A.halo_in[2 * (G.gt - 1) + 1];
+      if (wave == W - 1 && G.tile + 1 < G.ntile) vp[M + 1] = A.halo_in[2 * (G.gt + 1)];
+    }
+    auto cl = [&](int64_t l) {
+      return (double)(l + 1) / sqrt((double)(2 * l + 1) * (double)(2 * l + 3));
+    };
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = r0 + j;
+      const bool ok = r < n;
+      const double cb = (ok && r > 0) ? sc * cl(A.l0 + r - 1) : 0.0;
+      const double cc = (ok && r < n - 1) ? sc * cl(A.l0 + r) : 0.0;
+      Ar[j] = mk(1.0, 0.0);
+      Br[j] = mk(0.0, cb);
+      Cr[j] = mk(0.0, cc);
+      const cd p = vp[j + 1], lo = vp[j], hi = vp[j + 2];
+      Dr[j] = csel(ok, mk(p.x + cb * lo.y + cc * hi.y, p.y - cb * lo.x - cc * hi.x), zero);
+    }
+    bK = mk(0.0, (r0 + M < n) ? sc * cl(A.l0 + r0 + M - 1) : 0.0);
+    fst = vp[1];
+    lst = vp[M];
   } else {  // SRC_CN
     const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
     const double tau = 0.5 * A.dt;
@@ -1050,7 +1086,7 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
     fst = vp[1];
     lst = vp[M];
   }
-  if constexpr (PH == PH_REDUCE && SRC == SRC_CN) {
+  if constexpr (PH == PH_REDUCE && halo_src(SRC)) {
     if (A.halo_out && live) {
       if (wave == 0) A.halo_out[2 * G.gt] = fst;
       if (wave == W - 1) A.halo_out[2 * G.gt + 1] = lst;
@@ -1063,7 +1099,7 @@ __global__ __launch_bounds__(64 * W) void k_cols(KArgs A) {
     for (int j = 0; j < M; ++j) ay[j] = Ar[j].y;
     reduce_block_rd<M>(ay, CnEdges<false>{r0, n, kap}, Dr, bK.y, blk);
   } else {
-    reduce_block<M, SRC == SRC_CN>(Ar, Br, Cr, Dr, bK, blk);
+    reduce_block<M, SRC == SRC_CN || SRC == SRC_LCOUP>(Ar, Br, Cr, Dr, bK, blk);
   }
   sm.blk[wave][lane] = blk;
   __syncthreads();

@@ -92,3 +92,38 @@ def test_radial_step_in_a_graph(gpu):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(x, eager)
+
+
+def test_radial_field_part_is_fused(gpu, oracle_mod):
+    """With 64 or more radial points the field part's rows are built in-kernel: the handle then
+    holds the centrifugal potentials only (8 B per unknown, not the 72 B of the materialised
+    form), and the results are the oracle's."""
+    torch, cn = gpu
+    import ctypes
+
+    from paper_2205_00856_amd import _lib
+
+    nr, nl, dr, dt, E = 5000, 40, 0.1, 0.02, 0.2
+    V, psi = case(nr, nl, 21, dr)
+    ref = oracle_mod.radial_step(psi, V, dr, dt, E, 1, nl)
+    tV = torch.from_numpy(V).cuda()
+    tp = torch.from_numpy(psi).cuda()
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    assert lib.cn_create(ctypes.byref(h), 0) == _lib.CN_OK
+    try:
+        op = _lib.CnRadial()
+        op.nr, op.l0, op.nl, op.V, op.dr, op.dt = nr, 1, nl, tV.data_ptr(), dr, dt
+        out = torch.empty_like(tp)
+        st = lib.cn_radial_step(h, ctypes.byref(op), E, ctypes.c_void_p(tp.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == _lib.CN_OK
+        torch.cuda.synchronize()
+        assert rel(out.cpu().numpy(), ref) <= TOL
+        nbytes = ctypes.c_int64()
+        assert lib.cn_handle_info(h, ctypes.byref(nbytes), None, None) == _lib.CN_OK
+        assert nbytes.value < 40 * nr * nl
+    finally:
+        torch.cuda.synchronize()
+        lib.cn_destroy(h)
