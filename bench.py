@@ -62,6 +62,10 @@ def parse():
                    help="time only the 2^22 x 16 shared-matrix solve, for profiling")
     p.add_argument("--only-radial", action="store_true",
                    help="time only the partial-wave steps, for profiling")
+    p.add_argument("--only-latency", action="store_true",
+                   help="only the step times of the latency-bound sequences (plain 1D, 200 steps "
+                        "in a graph; the differentiated workload's forward and reverse mode), "
+                        "without oracle or finite differences (for profiling)")
     p.add_argument("--copy-ref", action="store_true",
                    help="first run a plain 256 MiB device copy three times (a reference of known "
                         "size for scaling hardware byte counters)")
@@ -163,6 +167,9 @@ def main():
         return
     if args.only_radial:
         print(json.dumps(radial(torch, np, cn, workloads, dev, parity=False)), flush=True)
+        return
+    if args.only_latency:
+        print(json.dumps(latency_legs(torch, np, cn, workloads, dev)), flush=True)
         return
 
     # ---------------------------------------------------------------- headline: ADI 4096^2
@@ -933,6 +940,68 @@ def absorbing_large(torch, np, cn, workloads, dev):
             "materialised_us_per_step": us_m,
             "materialised_frac_of_8TBps_192B": 192.0 * n / (us_m * 1e-6) / 8e12,
             "fused_vs_materialised_rel_l2": agree}
+
+
+def latency_legs(torch, np, cn, workloads, dev):
+    """Step times of the latency-bound sequences alone: the plain 1D workload (200 steps in
+    one graph, with the automatic plan and after the sequence autotuner) and the differentiated
+    workload's 2000-step forward with checkpoints and its reverse mode (C ABI directly)."""
+    out = {}
+    w = workloads.plain_1d()
+    psi0 = torch.from_numpy(w["psi0"]).to(dev)
+    V = torch.from_numpy(w["V"]).to(dev)
+    L = cn.Layout.contiguous(w["n"], 1)
+    cn.reserve(L)
+
+    def graph_us():
+        psi = psi0.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            cn.propagate(psi, V, w["dx"], w["dt"], 1)
+        torch.cuda.current_stream().wait_stream(side)
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            cn.propagate(psi, V, w["dx"], w["dt"], w["steps"])
+        gr.replay()
+        torch.cuda.synchronize()
+        return float(np.median(timed_events(torch, gr.replay, 5))) * 1e3 / w["steps"]
+
+    out["plain_1d_heuristic"] = {"plan": cn.describe_plan(L, True), "us_per_step": graph_us()}
+    tmp = torch.empty_like(psi0)
+    rep = cn.autotune(L, psi0, tmp, V=V, dx=w["dx"], dt=w["dt"], sequence=True)
+    out["plain_1d_tuned"] = {"plan": cn.describe_plan(L, True), "us_per_step": graph_us(),
+                             "autotune": rep}
+    del tmp
+    d = workloads.differentiated()
+    n, steps, K = d["n"], d["steps"], d["ckpt"]
+    Ld = cn.Layout.contiguous(n, 1)
+    tV, tx, p0, g0 = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                      for a in (d["V"], d["x"], d["psi0"], d["phi"]))
+    ckpt = torch.empty(((steps + K - 1) // K) * n, dtype=torch.complex128, device=dev)
+    dV = torch.zeros(n, dtype=torch.float64, device=dev)
+    dE = torch.zeros(steps, dtype=torch.float64, device=dev)
+    psi = p0.clone()
+    g = g0.clone()
+
+    def fwd():
+        psi.copy_(p0)
+        cn.propagate(psi, tV, d["dx"], d["dt"], steps, E=d["E"], xgrid=tx, ckpt=ckpt, K=K,
+                     layout=Ld)
+
+    def bwd():
+        g.copy_(g0)
+        cn.propagate_adjoint(ckpt, g, tV, d["dx"], d["dt"], steps, K, E=d["E"], xgrid=tx, dV=dV,
+                             dE=dE, layout=Ld)
+
+    fwd()
+    bwd()
+    tf = float(np.median(timed_events(torch, fwd, 3)))
+    tb = float(np.median(timed_events(torch, bwd, 3)))
+    out["differentiated"] = {"plan": cn.describe_plan(Ld, True), "forward_ms": tf,
+                             "backward_ms": tb, "forward_us_per_step": tf * 1e3 / steps,
+                             "backward_us_per_step": tb * 1e3 / steps}
+    return out
 
 
 def differentiated(torch, np, workloads, dev):

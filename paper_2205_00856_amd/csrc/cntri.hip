@@ -640,6 +640,9 @@ struct cn_handle_s {
   void* ws = nullptr;
   size_t ws_size = 0;
   int* status = nullptr;
+  // done counts of the fused passes that solve their reduced system themselves, one for chains
+  // on ws and one (at +32) for chains on ws2; zero between launches (same allocation as status)
+  int* sync = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> plans;
   std::map<std::string, std::string> tuned;  // automatic layout key -> key of the tuned plan
   double* rows_buf = nullptr;  // per-step partial sums of one checkpoint segment
@@ -1117,7 +1120,20 @@ struct FusePlan {
   bool ok = false;
   int red = -1, sub = -1;
   std::vector<int> singles, mids;
+  // the fused pass's last workgroup solves the reduced system (one system whose tile joints
+  // fit one whole-system tile of 2 rows per lane of the pass's workgroup): no launch of its own
+  bool inl = false;
 };
+
+// reduced systems of fused passes solved inside the pass (CN_INLINE=0 turns it off: a launch
+// of their own after every pass)
+bool inline_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_INLINE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
 
 FusePlan fuse_plan(const Plan* P) {
   FusePlan f;
@@ -1142,6 +1158,25 @@ FusePlan fuse_plan(const Plan* P) {
     }
   }
   f.ok = f.red >= 0 && f.sub >= 0;
+  if (f.ok && f.mids.size() == 1 && inline_enabled()) {
+    const Launch& R = P->L[f.red];
+    const Launch& S = P->L[f.sub];
+    const Launch& m = P->L[f.mids[0]];
+    // level 1: one system of a uniform layout in K tiles; level 2: its reduced system of K rows
+    // as one whole-system tile, reading the first pass's slots and writing where the second
+    // pass reads.  Taken when that tile of 2 rows per lane is more than half full (64 W < K <=
+    // 128 W): measured on 2^16 .. 2^20-row chains, a fuller in-pass solve saves the launch
+    // (2^20 rows in 512 tiles of 8 rows per lane, with a field: forward 55.2 -> 53.1 ms and
+    // reverse mode 88.2 -> 81.4 ms over 2000 steps), an emptier one costs more than the
+    // launch it saves (every workgroup then waits for its stores and its count to return).
+    const int64_t Wp = kCfgs[S.cfg].W;
+    f.inl = S.t_wgs < 0 && S.grid.y == 1 && R.grid.y == 1 && S.a.ntiles > 64 * Wp &&
+            S.a.ntiles <= 128 * Wp && m.level == 2 &&
+            m.src == nsd::SRC_SLOTS && m.ph == nsd::PH_SINGLE && m.cfg >= 0 &&
+            m.fn == g_kern[m.cfg][nsd::SRC_SLOTS][nsd::PH_SINGLE] && m.grid.x == 1 &&
+            m.grid.y == 1 && m.o_x >= 0 && m.o_x == S.o_psi_if && m.o_sU == R.o_oU &&
+            m.o_sD == R.o_oD;
+  }
   return f;
 }
 
@@ -1173,6 +1208,13 @@ cn_status run_chain(cn_handle_t h, Plan* P, const FusePlan& f, int64_t nst, cons
   const Launch& R = P->L[f.red];
   const Launch& S = P->L[f.sub];
   cd* H[2] = {(cd*)(ws + R.o_hout), (cd*)(ws + R.o_hout2)};
+  // the done count of an inline reduced solve: one per workspace, since chains on the two
+  // workspaces may run at once on two streams
+  int* inl = nullptr;
+  if (f.inl) {
+    if (ws == (char*)h->ws) inl = h->sync;
+    else if (ws == (char*)h->ws2) inl = h->sync + 32;
+  }
   auto mids = [&](const cd* hal, const UserArgs& u) -> cn_status {
     for (int i : f.mids) {
       const Launch& l = P->L[i];
@@ -1211,9 +1253,10 @@ cn_status run_chain(cn_handle_t h, Plan* P, const FusePlan& f, int64_t nst, cons
       a.oU = (cd*)(ws + R.o_oU);
       a.oD = (cd*)(ws + R.o_oD);
       a.E_next = vn.E_mat;
+      a.inl_sync = inl;
       if ((st = launch_k(g_kern[S.cfg][S.src][nsd::PH_FUSE], S, a, s)) != CN_OK) return st;
       if (after && (st = after(i)) != CN_OK) return st;
-      if ((st = mids(H[(i + 1) & 1], vn)) != CN_OK) return st;
+      if (!inl && (st = mids(H[(i + 1) & 1], vn)) != CN_OK) return st;
       v = vn;
     } else {
       if ((st = launch_k(S.fn, S, a, s)) != CN_OK) return st;
@@ -1395,11 +1438,12 @@ cn_status cn_create(cn_handle_t* handle, int device) {
   if (hipSetDevice(device) != hipSuccess) return CN_ERR_HIP;
   cn_handle_s* h = new cn_handle_s();
   h->device = device;
-  if (hipMalloc(&h->status, sizeof(int)) != hipSuccess) {
+  if (hipMalloc(&h->status, 128 * sizeof(int)) != hipSuccess) {
     delete h;
     return CN_ERR_NO_MEMORY;
   }
-  if (hipMemset(h->status, 0, sizeof(int)) != hipSuccess ||
+  h->sync = h->status + 64;
+  if (hipMemset(h->status, 0, 128 * sizeof(int)) != hipSuccess ||
       scratch_setup(device, &h->scratch) != CN_OK) {
     (void)hipFree(h->status);
     delete h;
@@ -1453,7 +1497,15 @@ cn_status cn_describe_plan(cn_handle_t h, const cn_layout* L, int cn_mode, char*
   Plan* P = nullptr;
   cn_status st = get_plan(h, L, cn_mode ? nsd::SRC_CN : nsd::SRC_EXPL, nullptr, &P);
   if (st != CN_OK) return st;
-  snprintf(buf, (size_t)buflen, "%s", P->desc.c_str());
+  std::string d = P->desc;
+  if (cn_mode) {
+    // how cn_propagate runs this plan
+    const FusePlan f = fuse_enabled() ? fuse_plan(P) : FusePlan();
+    if (f.ok)
+      d += f.inl ? "chain: one fused pass per step, reduced system solved in the pass; "
+                 : "chain: one fused pass per step; ";
+  }
+  snprintf(buf, (size_t)buflen, "%s", d.c_str());
   return CN_OK;
 }
 

@@ -92,6 +92,9 @@ struct KArgs {
   const double* Wabs;
   double wscale;
   int64_t l0;  // SRC_LCOUP: partial wave of row 0
+  // PH_FUSE of one system: the reduced system of the tile joints is solved by the pass's last
+  // workgroup (count of workgroups done, zero between launches), or null (a launch of its own)
+  int* inl_sync;
 };
 
 struct Geo {
@@ -612,6 +615,15 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 // the extra arithmetic buys no occupancy): keep holds 64 * M doubles of this wavefront's LDS for
 // the diagonals between the two, and kap is the off-diagonal magnitude (tau / (2 dx^2)) that
 // ss_block_rd recomputes the couplings from.
+// A store that reaches the level of the memory system shared by all XCDs (a relaxed atomic at
+// device scope), used for the values a tile hands to the next level: the last workgroup of a
+// pass that solves the reduced system itself reads them right after the other workgroups have
+// counted themselves done, without a write-back of their L2.
+__device__ __forceinline__ void st_coh(cd* p, cd v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int M, int W, int SRC, int PH>
 struct RdSubst {
   static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M == 8;
@@ -628,8 +640,8 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
   constexpr bool RD = RdSubst<M, W, SRC, PH>::on || RDR;
   if constexpr (PH == PH_REDUCE && cn_src(SRC)) {
     if (A.halo_out) {
-      if (wave == 0 && lane == 0) A.halo_out[2 * G.gt] = fst;
-      if (wave == W - 1 && lane == 63) A.halo_out[2 * G.gt + 1] = lst;
+      if (wave == 0 && lane == 0) st_coh(A.halo_out + 2 * G.gt, fst);
+      if (wave == W - 1 && lane == 63) st_coh(A.halo_out + 2 * G.gt + 1, lst);
     }
   }
 
@@ -668,12 +680,12 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
   cd pJ = czero(), pM = czero();
   if (wave == 0 && lane == 0) {
     if constexpr (PH == PH_REDUCE) {
-      A.oU[3 * G.gt] = blk.UA;
-      A.oU[3 * G.gt + 1] = blk.UC;
-      A.oU[3 * G.gt + 2] = blk.UD;
-      A.oD[3 * G.gt] = blk.DB;
-      A.oD[3 * G.gt + 1] = blk.DA;
-      A.oD[3 * G.gt + 2] = blk.DD;
+      st_coh(A.oU + 3 * G.gt, blk.UA);
+      st_coh(A.oU + 3 * G.gt + 1, blk.UC);
+      st_coh(A.oU + 3 * G.gt + 2, blk.UD);
+      st_coh(A.oD + 3 * G.gt, blk.DB);
+      st_coh(A.oD + 3 * G.gt + 1, blk.DA);
+      st_coh(A.oD + 3 * G.gt + 2, blk.DD);
     } else if constexpr (PH == PH_SINGLE) {
       // RS on the two joint lines of the tile (the bottom one lies past the system end)
       cd ia0 = crecip(blk.UA);
@@ -835,12 +847,57 @@ constexpr int tile_min_waves() {
   return (PH == PH_FUSE && M == 8 && SRC == SRC_CN) ? 3 : 1;
 }
 
+// The reduced system of a PH_FUSE pass over one system, solved in the same launch: every
+// workgroup waits until its own stores of slots and edge rows (device-coherent, tile_core) have
+// completed and counts itself done; the last one to do so reads them after an acquire at device
+// scope and solves the system on the K <= 128 W tile joints as one whole-system tile of 2 rows
+// per lane (the deferred joint-row terms from the new edge rows, as the separate launch would),
+// writing psi at the joints where the next pass reads it.  Nobody waits on anybody, and the
+// pass's own reads of psi at the joints happened before its workgroups counted themselves.
+template <int M, int W>
+__device__ __forceinline__ void fuse_reduced_last(const KArgs& A, TileSmem<M, W>& sm, int& last) {
+  static_assert(sizeof(TileSmem<2, W>) <= sizeof(TileSmem<M, W>), "LDS of the reduced solve");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // this wavefront's stores have completed
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nwg = (int)(gridDim.x * gridDim.y);
+    const int done = atomicAdd(A.inl_sync, 1);
+    last = done == nwg - 1;
+    if (last) atomicExch(A.inl_sync, 0);  // every workgroup has counted: ready for the next pass
+  }
+  __syncthreads();
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  KArgs B = A;
+  B.sU = A.oU;
+  B.sD = A.oD;
+  B.ud_halo = A.halo_out;
+  B.x = const_cast<cd*>(A.psi_if);
+  B.rhs = nullptr;
+  Geo G;
+  G.sys = 0;
+  G.tile = 0;
+  G.n = A.ntiles;
+  G.base = 0;
+  G.cbase = 0;
+  G.es = 1;
+  G.gt = 0;
+  G.ntile = 1;
+  tile_run<2, W, SRC_SLOTS, PH_SINGLE>(B, G, *reinterpret_cast<TileSmem<2, W>*>(&sm));
+}
+
 // One workgroup = one tile of T = 64*W*M rows of one system.
 template <int M, int W, int SRC, int PH>
 __global__ __launch_bounds__(64 * W, (tile_min_waves<M, PH, SRC>())) void k_tile(KArgs A) {
   __shared__ TileSmem<M, W> sm;
   const Geo G = geometry<PH>(A);
   tile_run<M, W, SRC, PH>(A, G, sm);
+  if constexpr (PH == PH_FUSE && cn_src(SRC)) {
+    __shared__ int last;
+    if (A.inl_sync) fuse_reduced_last<M, W>(A, sm, last);
+  }
 }
 
 // ------------------------------------------------------------ several right-hand sides

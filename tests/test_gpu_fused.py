@@ -250,3 +250,85 @@ def test_reverse_mode_captured_after_reserve_only(gpu):
         cn.propagate_adjoint(ckpt, ge, tV, dx, dt, steps, K, dV=dVe, seg=seg, layout=L)
         torch.cuda.synchronize()
         assert torch.equal(gc, ge) and torch.equal(dVc, dVe)
+
+
+# ------------------------------------------------ reduced system solved inside the fused pass
+# One system in K tiles whose K joints fill more than half of a whole-system tile of 2 rows per
+# lane of the pass's workgroup (64 W < K <= 128 W): the pass's last workgroup solves the reduced
+# system, so a step is one launch.  The automatic 2^20 plan (512 tiles of 2048 rows, W = 4, the
+# cap), 100 tiles of 128 rows (W = 1), 196 tiles of 512 (W = 2, a last tile of 163 rows), 301
+# tiles of 2048 (a last tile of one row); with a field and checkpoints.
+@pytest.mark.parametrize("n,T,M", [(1 << 20, 0, 0), (12_800, 128, 2), (100_003, 512, 4),
+                                   (614_401, 2048, 8)])
+def test_propagate_reduced_system_in_pass(gpu, oracle_mod, n, T, M):
+    torch, cn = gpu
+    log("reduced system in the pass", n, T, M)
+    dx, dt, steps, K = 0.05, 0.01, 12, 5
+    inp = workloads.random_cn(n, 5 + n % 89, dx, dt)
+    xg = workloads.grid_1d(n, dx)
+    E = np.random.default_rng(n % 777).normal(0.0, 0.05, steps)
+    L = cn.Layout.contiguous(n, 1, partition=T, rows_per_thread=M)
+    plan = cn.describe_plan(L, cn_mode=True)
+    log(plan)
+    assert "reduced system solved in the pass" in plan
+    tV, tpsi, txg = to_dev(torch, inp["V"], inp["psi"], xg)
+    ckpt = torch.empty(((steps + K - 1) // K) * n, dtype=torch.complex128, device="cuda")
+    cn.propagate(tpsi, tV, dx, dt, steps, E=E, xgrid=txg, ckpt=ckpt, K=K, layout=L)
+    ref = inp["psi"]
+    states = [ref]
+    for k in range(steps):
+        ref = oracle_mod.cn_step(ref, inp["V"], dx, dt, xg, E[k])
+        states.append(ref)
+    assert rel(tpsi.cpu().numpy(), states[steps]) <= TOL
+    ck = ckpt.cpu().numpy().reshape(-1, n)
+    for j in range(ck.shape[0]):
+        assert rel(ck[j], states[j * K]) <= TOL
+    assert cn.get_status() == 0
+
+
+def test_reduced_system_in_pass_graph_and_reverse(gpu, oracle_mod):
+    """The one-launch steps captured as a graph and replayed with eager work between the
+    replays (the done count is back at zero after every pass), and the reverse mode, whose
+    recompute runs the same chain on the second workspace and stream beside the recursion."""
+    torch, cn = gpu
+    n, dx, dt, steps = 100_003, 0.1, 0.02, 9
+    L = cn.Layout.contiguous(n, 1, partition=512, rows_per_thread=4)
+    assert "reduced system solved in the pass" in cn.describe_plan(L, cn_mode=True)
+    inp = workloads.random_cn(n, 29, dx, dt)
+    tV, p0 = to_dev(torch, inp["V"], inp["psi"])
+    cn.reserve(L)
+    eager = p0.clone()
+    cn.propagate(eager, tV, dx, dt, steps, layout=L)
+    ref = oracle_mod.cn_propagate(inp["psi"], inp["V"], dx, dt, steps)
+    assert rel(eager.cpu().numpy(), ref) <= TOL
+    psi = p0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        cn.propagate(psi, tV, dx, dt, steps, layout=L)
+    for _ in range(4):
+        psi.copy_(p0)
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = p0.clone()
+        cn.propagate(junk, tV, dx, dt, 3, layout=L)
+        torch.cuda.synchronize()
+        assert torch.equal(psi, eager)
+    # reverse mode: 4 segments of 5 steps, recomputes overlapped on the second stream
+    nst, K = 20, 5
+    x1 = workloads.grid_1d(n, dx)
+    g = np.random.default_rng(3)
+    GT = workloads.complex_normal(g, n)
+    E = g.normal(0.0, 0.05, nst)
+    tp, tg, tx = to_dev(torch, inp["psi"], GT, x1)
+    ckpt = torch.empty((nst // K) * n, dtype=torch.complex128, device="cuda")
+    cn.propagate(tp, tV, dx, dt, nst, E=E, xgrid=tx, ckpt=ckpt, K=K, layout=L)
+    dV = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dE = torch.zeros(nst, dtype=torch.float64, device="cuda")
+    cn.propagate_adjoint(ckpt, tg, tV, dx, dt, nst, K, E=E, xgrid=tx, dV=dV, dE=dE, layout=L)
+    r0, rV, rE = oracle_mod.cn_propagate_grad(inp["psi"], inp["V"], dx, dt, nst, GT, x1, E)
+    assert rel(tg.cpu().numpy(), r0) <= 1e-10
+    assert rel(dV.cpu().numpy(), rV) <= 1e-10
+    assert rel(dE.cpu().numpy(), rE) <= 1e-10
+    assert cn.get_status() == 0
