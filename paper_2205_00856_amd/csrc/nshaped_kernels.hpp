@@ -629,7 +629,9 @@ struct RdSubst {
   static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M == 8;
 };
 
-template <int M, int W, int SRC, int PH, bool IN, bool RDR = false, typename SM>
+// COH: the slots and edge rows of a PH_REDUCE part are stored device-coherent (st_coh), for a
+// fused pass whose last workgroup solves the reduced system (fuse_reduced_last)
+template <int M, int W, int SRC, int PH, bool IN, bool RDR = false, bool COH = false, typename SM>
 __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, Node* wnode,
                                           double* keep, double kap, int64_t J, int lane, int wave,
                                           cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
@@ -638,10 +640,16 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
   constexpr int LW = Log2<W>::v;
   // RDR: a Crank-Nicolson first pass reduced in the RD form as well (fewer registers)
   constexpr bool RD = RdSubst<M, W, SRC, PH>::on || RDR;
+  auto put = [](cd* p, cd v) {
+    if constexpr (COH)
+      st_coh(p, v);
+    else
+      *p = v;
+  };
   if constexpr (PH == PH_REDUCE && cn_src(SRC)) {
     if (A.halo_out) {
-      if (wave == 0 && lane == 0) st_coh(A.halo_out + 2 * G.gt, fst);
-      if (wave == W - 1 && lane == 63) st_coh(A.halo_out + 2 * G.gt + 1, lst);
+      if (wave == 0 && lane == 0) put(A.halo_out + 2 * G.gt, fst);
+      if (wave == W - 1 && lane == 63) put(A.halo_out + 2 * G.gt + 1, lst);
     }
   }
 
@@ -680,12 +688,12 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
   cd pJ = czero(), pM = czero();
   if (wave == 0 && lane == 0) {
     if constexpr (PH == PH_REDUCE) {
-      st_coh(A.oU + 3 * G.gt, blk.UA);
-      st_coh(A.oU + 3 * G.gt + 1, blk.UC);
-      st_coh(A.oU + 3 * G.gt + 2, blk.UD);
-      st_coh(A.oD + 3 * G.gt, blk.DB);
-      st_coh(A.oD + 3 * G.gt + 1, blk.DA);
-      st_coh(A.oD + 3 * G.gt + 2, blk.DD);
+      put(A.oU + 3 * G.gt, blk.UA);
+      put(A.oU + 3 * G.gt + 1, blk.UC);
+      put(A.oU + 3 * G.gt + 2, blk.UD);
+      put(A.oD + 3 * G.gt, blk.DB);
+      put(A.oD + 3 * G.gt + 1, blk.DA);
+      put(A.oD + 3 * G.gt + 2, blk.DD);
     } else if constexpr (PH == PH_SINGLE) {
       // RS on the two joint lines of the tile (the bottom one lies past the system end)
       cd ia0 = crecip(blk.UA);
@@ -798,8 +806,8 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
   double* keep = reinterpret_cast<double*>(wnode + 64);
   // reduced in the RD form (real potentials): the diagonal and the right-hand side are all it
   // keeps per row; with the absorbing term, Table 1's reduction of the full rows
-  tile_core<M, W, SRC, PH_REDUCE, IN, !WA>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br,
-                                           Cr, Dr, bK, vp[1], vp[M], dummy);
+  tile_core<M, W, SRC, PH_REDUCE, IN, !WA, true>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar,
+                                                 Br, Cr, Dr, bK, vp[1], vp[M], dummy);
 }
 
 // Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
@@ -848,7 +856,7 @@ constexpr int tile_min_waves() {
 }
 
 // The reduced system of a PH_FUSE pass over one system, solved in the same launch: every
-// workgroup waits until its own stores of slots and edge rows (device-coherent, tile_core) have
+// workgroup waits until its own stores of slots and edge rows (device-coherent, fuse_next) have
 // completed and counts itself done; the last one to do so reads them after an acquire at device
 // scope and solves the system on the K <= 128 W tile joints as one whole-system tile of 2 rows
 // per lane (the deferred joint-row terms from the new edge rows, as the separate launch would),
