@@ -214,9 +214,11 @@ cn_status cn_step(cn_handle_t handle, const cn_layout* layout, const cn_operator
  * ckpt + (k / K) * (rows of the layout) for every k divisible by K (K >= 1).
  * Systems solved in two passes (longer than one tile) run one fused pass per step: the
  * substitution of step k and the reduction of step k+1 (whose joint rows take the left
- * neighbour's explicit half-step term in the reduced system instead).  The result equals the
- * chain of cn_step calls up to rounding (not bit for bit); CN_FUSE=0 in the environment turns
- * the fusion off. */
+ * neighbour's explicit half-step term in the reduced system instead).  For one system whose
+ * K tile joints fill more than half of a whole-system tile of 2 rows per lane of the pass's
+ * workgroup (64 W < K <= 128 W), the pass's last workgroup also solves that reduced system, so
+ * a step is one launch (CN_INLINE=0 turns this off).  The result equals the chain of cn_step
+ * calls up to rounding (not bit for bit); CN_FUSE=0 in the environment turns the fusion off. */
 cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_operator* op,
                        int64_t nsteps, const double* E, void* psi, void* ckpt, int64_t K,
                        cn_stream_t stream);

@@ -472,13 +472,19 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   const int64_t batch = bd.batch;
   const int64_t t_offs = B.add_tab(bd.offs.data(), (batch + 1) * sizeof(int64_t));
   int64_t handled = 0;  // systems up to this length went to the persistent launch
+  // with an explicit partition: one persistent launch, whole systems from a device queue,
+  // longest first (configurations without a persistent kernel use T = 1024, M = 4; a source
+  // without persistent kernels, such as the column-only field coupling, takes the other path)
+  int pci = -1;
   if (level == 1 && src != nsd::SRC_SLOTS && src != nsd::SRC_CNW && kn.partition > 0 &&
       persist_enabled()) {
-    // with an explicit partition: one persistent launch, whole systems from a device queue,
-    // longest first (configurations without a persistent kernel use T = 1024, M = 4)
-    int ci = find_cfg(kn.partition, kn.rpt > 0 ? kn.rpt : 4);
-    if (ci >= 0 && !g_pers[ci][src]) ci = -1;
-    if (ci < 0) ci = find_cfg(1024, 4);
+    pci = find_cfg(kn.partition, kn.rpt > 0 ? kn.rpt : 4);
+    if (pci >= 0 && !g_pers[pci][src]) pci = -1;
+    if (pci < 0) pci = find_cfg(1024, 4);
+    if (!g_pers[pci][src]) pci = -1;
+  }
+  if (pci >= 0) {
+    const int ci = pci;
     const int64_t T = kCfgs[ci].T();
     handled = nsd::kMaxSysTiles * T;
     std::vector<int> sys;
@@ -497,8 +503,10 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     if (!sys.empty()) {
       int per_cu = 1;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g_pers[ci][src], 64 * kCfgs[ci].W,
-                                                       0) != hipSuccess || per_cu < 1)
+                                                       0) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();  // the query's failure is handled here: leave no error behind
         per_cu = 1;
+      }
       const int64_t grid = std::min<int64_t>((int64_t)per_cu * num_cus(), (int64_t)sys.size());
       Launch l;
       l.fn = g_pers[ci][src];
@@ -1841,7 +1849,12 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
       if (ok && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ok = false;
       if (ok && r >= 2) ts.push_back(ms);
     }
-    if (!ok) continue;
+    if (!ok) {
+      // a candidate that could not run is left out of the report; its launch error is consumed
+      // here so that no later HIP call of the caller reports it
+      (void)hipGetLastError();
+      continue;
+    }
     std::sort(ts.begin(), ts.end());
     const float med = ts[ts.size() / 2];
     char line[160];

@@ -759,3 +759,21 @@ def test_autotune_cache_file(gpu, oracle_mod, tmp_path):
     finally:
         torch.cuda.synchronize()
         lib.cn_destroy(h2)
+
+
+def test_reserve_leaves_no_hip_error(gpu):
+    """cn_reserve builds the plans of every source for a layout; for sources without kernels of
+    a launch form (the column-only field coupling on an uneven batch with an explicit partition)
+    it must refuse the plan without leaving a HIP error behind, which the caller's next kernel
+    launch would report.  Same for an autotune run whose candidates include refused ones."""
+    torch, cn = gpu
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipPeekAtLastError.restype = ctypes.c_int
+    hip.hipGetLastError()  # start from a clean error state
+    offs = np.cumsum([0, 3000, 70_000, 500, 9000]).astype(np.int64)
+    cn.reserve(cn.Layout.uneven(offs, partition=1024, rows_per_thread=4))
+    assert hip.hipPeekAtLastError() == 0
+    t = torch.ones(1000, device="cuda").sum().item()  # a launch of the caller's after the call
+    assert t == 1000.0
