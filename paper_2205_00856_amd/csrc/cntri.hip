@@ -303,6 +303,32 @@ void plan_serial_rs(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int
   B.desc += line;
 }
 
+void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src, int level,
+                int64_t o_sU, int64_t o_sD, int64_t o_x, const Knobs& kn);
+
+// The reduced systems of a uniform batch split into K tiles per system: batch systems of K
+// rows each, their slots at system * K + tile.  As a uniform batch (element stride 1, batch
+// stride K) the level's launches find a system's slots from its index, with no table lookup;
+// the serial RS stage of a fixed nesting depth takes them as an uneven batch of equal lengths.
+void plan_reduced_uniform(Builder& B, std::vector<Launch>& L, int64_t batch, int64_t K, int level,
+                          int64_t oU, int64_t oD, int64_t oP, const Knobs& kn) {
+  BatchDesc ib;
+  if (kn.levels > 0 && level >= kn.levels) {
+    ib.uneven = true;
+    ib.batch = batch;
+    ib.offs.resize(batch + 1);
+    for (int64_t s = 0; s <= batch; ++s) ib.offs[s] = s * K;
+    plan_serial_rs(B, L, ib, level + 1, oU, oD, oP);
+    return;
+  }
+  ib.uneven = false;
+  ib.n = K;
+  ib.batch = batch;
+  ib.es = 1;
+  ib.bs = K;
+  plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+}
+
 // Appends the launches that solve one level; x goes to the caller (level 1) or to workspace
 // offset o_x.  At level >= 2 the source is the slot arrays at (o_sU, o_sD).
 void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src, int level,
@@ -365,15 +391,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       L.back().o_oU = oU;
       L.back().o_oD = oD;
       L.back().o_hout = oH;
-      BatchDesc ib;
-      ib.uneven = true;
-      ib.batch = batch;
-      ib.offs.resize(batch + 1);
-      for (int64_t s2 = 0; s2 <= batch; ++s2) ib.offs[s2] = s2 * K;
-      if (kn.levels > 0 && level >= kn.levels)
-        plan_serial_rs(B, L, ib, level + 1, oU, oD, oP);
-      else
-        plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+      plan_reduced_uniform(B, L, batch, K, level, oU, oD, oP, kn);
       add_col(nsd::PH_SUBST);
       L.back().a.rev = rev_for(n * batch);
       L.back().o_psi_if = oP;
@@ -451,15 +469,7 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
     L.back().o_oD = oD;
     L.back().o_hout = oH;
     L.back().o_hout2 = oH2;
-    BatchDesc ib;
-    ib.uneven = true;
-    ib.batch = batch;
-    ib.offs.resize(batch + 1);
-    for (int64_t s = 0; s <= batch; ++s) ib.offs[s] = s * K;
-    if (kn.levels > 0 && level >= kn.levels)
-      plan_serial_rs(B, L, ib, level + 1, oU, oD, oP);
-    else
-      plan_level(B, L, ib, nsd::SRC_SLOTS, level + 1, oU, oD, oP, kn);
+    plan_reduced_uniform(B, L, batch, K, level, oU, oD, oP, kn);
     add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)K, gy), level, a);
     if (mr) L.back().fn = g_mrhs[ci][nsd::PH_SUBST];
     L.back().a.rev = batch == 1 ? rev_for(n) : 0;  // one-dimensional grids only
