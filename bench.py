@@ -1082,6 +1082,33 @@ def differentiated(torch, np, workloads, dev):
     ana = np.asarray(ana)
     fwd_s = float(np.median(tf))
     bwd_s = float(np.median(tb))
+    # the reverse mode without checkpoints: each segment's states rebuilt backwards from the
+    # state at its end (psi_T for the last) beside the recursion, for the same gradient at psi_T
+    o = out.detach().clone().requires_grad_(True)
+    loss_of(o).backward()
+    gT = o.grad.detach()
+    psiT_dev = o.detach()
+    dVr = torch.zeros(w["n"], dtype=torch.float64, device=dev)
+    dEr = torch.zeros(w["steps"], dtype=torch.float64, device=dev)
+
+    def bwd_rec():
+        gg = gT.clone()
+        dVr.zero_()
+        cn.propagate_adjoint_reconstruct(psiT_dev, gg, tV.detach(), dx, dt, w["steps"], K,
+                                         E=w["E"], xgrid=tx, dV=dVr, dE=dEr, layout=Lw)
+
+    bwd_rec()
+    trec = float(np.median(timed_events(torch, bwd_rec, 3))) * 1e-3
+    reconstruct = {
+        "backward_ms": trec * 1e3,
+        "adjoint_over_forward": trec / fwd_s,
+        "rel_l2_dV_vs_checkpointed": float(np.linalg.norm(dVr.cpu().numpy() - gV)
+                                           / np.linalg.norm(gV)),
+        "rel_l2_dE_vs_checkpointed": float(np.linalg.norm(dEr.cpu().numpy() - gE)
+                                           / np.linalg.norm(gE)),
+        "memory": f"two segment buffers of {K + 1} states, no checkpoints "
+                  f"(checkpointed: {(w['steps'] + K - 1) // K} stored states + the buffers)",
+    }
     # the oracle beside it: the whole 2000-step propagation (1 thread), against which the
     # GPU's psi_T and loss are compared
     psiT = out.detach().cpu().numpy()
@@ -1114,6 +1141,7 @@ def differentiated(torch, np, workloads, dev):
         "phi_draw": list(map(float, w["phi_params"])),
         "plan": cn.describe_plan(Lw, True),
         "autotune_sequence": tune_rep,
+        "reverse_reconstruction": reconstruct,
     }
 
 

@@ -275,6 +275,25 @@ cn_status cn_propagate_adjoint(cn_handle_t handle, const cn_layout* layout,
                                const void* ckpt, int64_t K, void* seg, void* g,
                                double* dV_accum, double* dE, cn_stream_t stream);
 
+/* The reverse mode of cn_propagate without checkpoints.  The CN step of Sec. 2 is invertible,
+ * so the forward states are rebuilt backwards from the final state psi_T,
+ * psi_k = (1 - i tau H_k)^{-1} (1 + i tau H_k) psi_{k+1} -- a CN step with dt -> -dt and the
+ * field E_k on both sides, the exact inverse of the forward step -- one
+ * segment of K steps at a time into seg, beside the gradient recursion of cn_propagate_adjoint
+ * (same arguments and results otherwise: g in place from the gradient at psi_T to the gradient
+ * at psi_0, dV accumulated, dE written).  The rebuild of the next segment runs on a second
+ * stream while the recursion works through the current one, as the checkpoint recompute does.
+ * Memory: seg holds min(K, nsteps) + 1 states; no trajectory is stored.  Rounding of the
+ * rebuilt states grows with the number of steps (the steps are unitary, so it grows slowly;
+ * about 1e-13 relative after 2000 steps of 2^20 rows).  psi_T: DEVICE, layout of g, read
+ * only.  An absorbing potential (op->absorb) returns CN_ERR_UNSUPPORTED: its inverse step
+ * amplifies. */
+cn_status cn_propagate_adjoint_reconstruct(cn_handle_t handle, const cn_layout* layout,
+                                           const cn_operator* op, int64_t nsteps,
+                                           const double* E, const void* psi_T, int64_t K,
+                                           void* seg, void* g, double* dV, double* dE,
+                                           cn_stream_t stream);
+
 /* Autotuner: times the automatic plan and the candidate tile configurations (rows per
  * first-level partition and per innermost block; for uneven batches the persistent launches)
  * of this layout on the caller's data and keeps the fastest for later calls with the same

@@ -100,6 +100,8 @@ def lib():
         "cn_version": ([], ctypes.c_char_p),
         "cn_describe_plan": ([H, LP, ctypes.c_int, ctypes.c_char_p, i64], ctypes.c_int),
         "cn_propagate_adjoint": ([H, LP, OP, i64, P, P, i64, P, P, P, P, P], ctypes.c_int),
+        "cn_propagate_adjoint_reconstruct": ([H, LP, OP, i64, P, P, i64, P, P, P, P, P],
+                                             ctypes.c_int),
         "cn_autotune": ([H, LP, ctypes.c_int, OP, d, P, P, P, P, P, ctypes.c_char_p, i64, P],
                         ctypes.c_int),
         "cn_handle_info": ([H, ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -120,7 +122,7 @@ def lib():
 EXPORTED = ["cn_check_layout", "cn_create", "cn_destroy", "cn_status_string", "cn_reserve", "cn_tridiag_solve",
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
             "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
-            "cn_propagate_adjoint", "cn_handle_info", "cn_tridiag_solve_noalloc", "cn_profile",
+            "cn_propagate_adjoint", "cn_propagate_adjoint_reconstruct", "cn_handle_info", "cn_tridiag_solve_noalloc", "cn_profile",
             "cn_profile_report", "cn_tune_cache", "cn_radial_step"]
 
 

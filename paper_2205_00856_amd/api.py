@@ -21,7 +21,7 @@ from ._lib import CnLayout, CnOperator, check
 __all__ = ["Layout", "Handle", "handle", "solve", "solve_noalloc", "solve_adjoint", "assemble", "rhs", "step",
            "propagate", "step_adjoint", "get_status", "describe_plan", "reserve", "autotune",
            "profile", "profile_report", "tune_cache", "radial_step",
-           "propagate_adjoint"]
+           "propagate_adjoint", "propagate_adjoint_reconstruct"]
 
 
 @dataclass
@@ -344,6 +344,39 @@ def propagate_adjoint(ckpt, g, V, dx, dt, nsteps, K, E=None, xgrid=None, v_scale
     check(_lib.lib().cn_propagate_adjoint(h.ptr, ctypes.byref(Lc), ctypes.byref(op), int(nsteps),
                                           Ep, _ptr(ckpt), int(K), _ptr(seg), _ptr(g), _ptr(dV),
                                           _ptr(dE), _stream(g)), "cn_propagate_adjoint")
+    return g
+
+
+def propagate_adjoint_reconstruct(psi_T, g, V, dx, dt, nsteps, K, E=None, xgrid=None,
+                                  v_scale=1.0, dV=None, dE=None, seg=None,
+                                  layout: Optional[Layout] = None, W=None):
+    """Reverse mode of propagate without checkpoints (cn_propagate_adjoint_reconstruct): the
+    states are rebuilt backwards from the final state psi_T (read only) segment by segment of K
+    steps.  g, dV, dE as in propagate_adjoint.  Real potentials only: with W the library
+    refuses (CN_ERR_UNSUPPORTED)."""
+    L = _layout_for(g, layout)
+    span = L.span()
+    _need(g, torch.complex128, "g", span)
+    _need(psi_T, torch.complex128, "psi_T", span)
+    _check_op(L, V, xgrid, None, W)
+    m = min(K, nsteps)
+    if seg is None:
+        seg = torch.empty((m + 1) * span, dtype=torch.complex128, device=g.device)
+    _need(seg, torch.complex128, "seg", (m + 1) * span)
+    Earr = None
+    if E is not None:
+        Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
+        if Earr.shape[0] < nsteps:
+            raise ValueError("E needs one value per step")
+    if dE is not None:
+        _need(dE, torch.float64, "dE", nsteps)
+    op = _operator(V, dx, dt, xgrid, v_scale, None, W)
+    h = handle(g.device.index)
+    Lc = L.c()
+    Ep = None if Earr is None else Earr.ctypes.data_as(ctypes.c_void_p)
+    check(_lib.lib().cn_propagate_adjoint_reconstruct(
+        h.ptr, ctypes.byref(Lc), ctypes.byref(op), int(nsteps), Ep, _ptr(psi_T), int(K),
+        _ptr(seg), _ptr(g), _ptr(dV), _ptr(dE), _stream(g)), "cn_propagate_adjoint_reconstruct")
     return g
 
 

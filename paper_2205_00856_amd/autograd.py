@@ -4,7 +4,9 @@ CNSolve      x = T^{-1} d for a tridiagonal T (a, b, c, d complex128); backward 
              conjugate-transposed system with the same N-shaped method (cn_tridiag_solve_adjoint).
 CNPropagate  psi_T after nsteps Crank-Nicolson steps with H_k = H_0 + diag(V + x E_k) (Sec. 2);
              backward (cn_propagate_adjoint) recomputes each segment of K steps forward from a
-             stored checkpoint and runs the adjoint recursion backwards through it.
+             stored checkpoint and runs the adjoint recursion backwards through it; with
+             reconstruct=True no checkpoint is stored and the backward rebuilds the segments
+             backwards from psi_T (cn_propagate_adjoint_reconstruct).
 
 Complex gradients use torch's convention (d/dRe + i d/dIm of a real loss), for which
   grad d = T^{-H} grad x,  grad a_i = -lambda_i conj(x_i),  grad b_i = -lambda_i conj(x_{i-1}),
@@ -54,20 +56,26 @@ class CNPropagate(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, psi0, V, E, dx: float, dt: float, xgrid, K: int, v_scale: float = 1.0,
-                W=None):
+                W=None, reconstruct: bool = False):
         nsteps = int(E.shape[0]) if E is not None else 0
         if nsteps < 1:
             raise ValueError("CNPropagate needs at least one step (E has one value per step)")
+        if reconstruct and W is not None:
+            raise ValueError("reconstruct needs a real potential (the inverse step with W amplifies)")
         Eh = E.detach().cpu().numpy().astype(np.float64) if E.is_cuda else \
             E.detach().numpy().astype(np.float64)
         L = api.Layout.contiguous(psi0.shape[0], 1)
         nseg = (nsteps + K - 1) // K
-        ckpt = torch.empty(nseg * psi0.shape[0], dtype=psi0.dtype, device=psi0.device)
+        ckpt = None if reconstruct else torch.empty(nseg * psi0.shape[0], dtype=psi0.dtype,
+                                                    device=psi0.device)
         psi = psi0.detach().clone()
         api.propagate(psi, V.detach(), dx, dt, nsteps, E=Eh, xgrid=xgrid, v_scale=v_scale,
                       ckpt=ckpt, K=K, layout=L, W=W)
         ctx.W = W
-        ctx.save_for_backward(V, xgrid if xgrid is not None else torch.empty(0), ckpt)
+        ctx.reconstruct = reconstruct
+        # the checkpoints, or (reconstruct) the final state the backward rebuilds from
+        ctx.save_for_backward(V, xgrid if xgrid is not None else torch.empty(0),
+                              psi.clone() if reconstruct else ckpt)
         ctx.meta = (Eh, dx, dt, K, v_scale, nsteps, xgrid is not None, E.device, E.dtype)
         return psi
 
@@ -81,11 +89,16 @@ class CNPropagate(torch.autograd.Function):
         dV = torch.zeros(n, dtype=torch.float64, device=dev)
         dE = torch.zeros(nsteps, dtype=torch.float64, device=dev) if has_x else None
         g = gT.contiguous().clone()
-        api.propagate_adjoint(ckpt, g, V.detach(), dx, dt, nsteps, K, E=Eh, xgrid=xgrid,
-                              v_scale=v_scale, dV=dV, dE=dE, W=ctx.W)
+        if ctx.reconstruct:
+            api.propagate_adjoint_reconstruct(ckpt, g, V.detach(), dx, dt, nsteps, K, E=Eh,
+                                              xgrid=xgrid, v_scale=v_scale, dV=dV, dE=dE)
+        else:
+            api.propagate_adjoint(ckpt, g, V.detach(), dx, dt, nsteps, K, E=Eh, xgrid=xgrid,
+                                  v_scale=v_scale, dV=dV, dE=dE, W=ctx.W)
         gE = dE.to(device=Edev, dtype=Edt) if has_x else None
-        return g, dV, gE, None, None, None, None, None, None
+        return g, dV, gE, None, None, None, None, None, None, None
 
 
-def cn_propagate(psi0, V, E, dx, dt, xgrid=None, K=50, v_scale=1.0, W=None):
-    return CNPropagate.apply(psi0, V, E, dx, dt, xgrid, K, v_scale, W)
+def cn_propagate(psi0, V, E, dx, dt, xgrid=None, K=50, v_scale=1.0, W=None,
+                 reconstruct: bool = False):
+    return CNPropagate.apply(psi0, V, E, dx, dt, xgrid, K, v_scale, W, reconstruct)

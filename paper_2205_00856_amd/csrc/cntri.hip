@@ -1901,11 +1901,17 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
   return CN_OK;
 }
 
-cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* op,
-                               int64_t nsteps, const double* E, const void* ckpt, int64_t K,
-                               void* seg, void* g, double* dV_accum, double* dE,
-                               cn_stream_t stream) {
-  if (!h || !L || !ckpt || !seg || !g || nsteps < 1 || K < 1) return CN_ERR_INVALID_ARG;
+namespace {
+// The reverse mode of cn_propagate.  The states of each segment of K steps come either from a
+// checkpoint (ckpt: recomputed forward) or, with psi_T instead, from the state at the
+// segment's end (rebuilt backwards: psi_k = (1 - i tau H_k)^{-1} (1 + i tau H_k) psi_{k+1}, a
+// CN step with dt -> -dt, the inverse of the forward step for a real potential).
+cn_status propagate_adjoint_impl(cn_handle_t h, const cn_layout* L, const cn_operator* op,
+                                 int64_t nsteps, const double* E, const void* ckpt,
+                                 const void* psi_T, int64_t K, void* seg, void* g,
+                                 double* dV_accum, double* dE, cn_stream_t stream) {
+  if (!h || !L || (!ckpt == !psi_T) || !seg || !g || nsteps < 1 || K < 1)
+    return CN_ERR_INVALID_ARG;
   if (L && L->shared_coefficients == 1) return CN_ERR_UNSUPPORTED;
   if (L->offsets) return CN_ERR_UNSUPPORTED;
   cn_status st = check_op(op);
@@ -1942,8 +1948,29 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   // recompute segment sg forward from its checkpoint into buf (its K+1 states): a fused chain
   // on the second workspace when there is one, else step by step
   const FusePlan fzr = fuse_enabled() ? fuse_plan(P) : FusePlan();
+  // rebuild segment sg backwards into buf from psi at its end: psi_T for the last segment, else
+  // the first state of segment sg+1 (held in src_of(sg), which stays valid until that
+  // segment's recursion has finished, after this rebuild)
+  std::function<const cd*(int64_t)> src_of;  // set once the segment buffers are known
+  auto rebuild = [&](int64_t sg, cd* buf, void* ws, hipStream_t st) -> cn_status {
+    const int64_t k0 = k0_of(sg), k1 = k1_of(sg), m = k1 - k0;
+    const cd* end = (sg == nseg - 1) ? (const cd*)psi_T : src_of(sg);
+    HIP_TRY(hipMemcpyAsync(buf + m * span, end, span * sizeof(cd), hipMemcpyDeviceToDevice, st));
+    auto bargs = [&](int64_t i) {
+      UserArgs u = cn_args(op, Ek(k1 - 1 - i), buf + (m - i) * span, buf + (m - i - 1) * span);
+      u.dt = -op->dt;
+      return u;
+    };
+    if (fzr.ok && ws && m >= 2) return run_chain(h, P, fzr, m, bargs, nullptr, nullptr, st, ws);
+    for (int64_t i = 0; i < m; ++i) {
+      cn_status r = run_plan(h, P, bargs(i), st, ws);
+      if (r != CN_OK) return r;
+    }
+    return CN_OK;
+  };
   auto recompute = [&](int64_t sg, cd* buf, void* ws, hipStream_t st) -> cn_status {
     const int64_t k0 = k0_of(sg), k1 = k1_of(sg);
+    if (psi_T) return rebuild(sg, buf, ws, st);
     HIP_TRY(hipMemcpyAsync(buf, (const cd*)ckpt + sg * span, span * sizeof(cd),
                            hipMemcpyDeviceToDevice, st));
     if (fzr.ok && ws && k1 - k0 >= 2) {
@@ -1983,6 +2010,7 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
   const bool chain = fz.ok && h->ws2 && h->ws2_size >= P->ws_bytes;
   cd* bufs[2] = {segs, overlap ? (cd*)h->seg2 : segs};
   auto buf_of = [&](int64_t sg) { return overlap ? bufs[(nseg - 1 - sg) & 1] : segs; };
+  src_of = [&](int64_t sg) -> const cd* { return buf_of(sg + 1); };
   hipEvent_t start = h->ev[0], rec_done[2] = {h->ev[1], h->ev[2]},
              adj_done[2] = {h->ev[3], h->ev[4]};
   // The recursion runs on g in place, step k = nsteps-1 .. 0 (chain step i = nsteps-1-k):
@@ -2052,6 +2080,27 @@ cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_opera
     if ((st = after(i)) != CN_OK) return st;
   }
   return CN_OK;
+}
+}  // namespace
+
+cn_status cn_propagate_adjoint(cn_handle_t h, const cn_layout* L, const cn_operator* op,
+                               int64_t nsteps, const double* E, const void* ckpt, int64_t K,
+                               void* seg, void* g, double* dV_accum, double* dE,
+                               cn_stream_t stream) {
+  if (!ckpt) return CN_ERR_INVALID_ARG;
+  return propagate_adjoint_impl(h, L, op, nsteps, E, ckpt, nullptr, K, seg, g, dV_accum, dE,
+                                stream);
+}
+
+cn_status cn_propagate_adjoint_reconstruct(cn_handle_t h, const cn_layout* L,
+                                           const cn_operator* op, int64_t nsteps,
+                                           const double* E, const void* psi_T, int64_t K,
+                                           void* seg, void* g, double* dV_accum, double* dE,
+                                           cn_stream_t stream) {
+  if (!psi_T || !op) return CN_ERR_INVALID_ARG;
+  if (op->absorb) return CN_ERR_UNSUPPORTED;  // the backward step would amplify
+  return propagate_adjoint_impl(h, L, op, nsteps, E, nullptr, psi_T, K, seg, g, dV_accum, dE,
+                                stream);
 }
 
 cn_status cn_handle_info(cn_handle_t h, int64_t* device_bytes, int64_t* retired_buffers,

@@ -332,3 +332,88 @@ def test_reduced_system_in_pass_graph_and_reverse(gpu, oracle_mod):
     assert rel(dV.cpu().numpy(), rV) <= 1e-10
     assert rel(dE.cpu().numpy(), rE) <= 1e-10
     assert cn.get_status() == 0
+
+
+# ------------------------------------------------------ reverse mode without checkpoints
+@pytest.mark.parametrize("n,steps,K,T,M", [(100_003, 23, 5, 0, 0), (65536, 40, 7, 512, 4),
+                                           (1 << 20, 30, 10, 0, 0), (3000, 6, 4, 0, 0),
+                                           (50_000, 9, 20, 0, 0)])
+def test_reverse_reconstruction(gpu, oracle_mod, n, steps, K, T, M):
+    """cn_propagate_adjoint_reconstruct: no checkpoints; each segment's states are rebuilt
+    backwards from the state at its end (psi_T for the last), a CN step with -dt, beside the
+    recursion on g.  Against the oracle's reverse mode (which steps forward from psi_0) and the
+    checkpointed GPU reverse mode; psi_T is left untouched.  Cases: fused chains in segments of
+    5, 7 and 10 steps (the 2^20 one with its reduced system solved in the pass), whole-system
+    tiles stepped one at a time, one segment longer than the sequence."""
+    torch, cn = gpu
+    log("reverse reconstruction", n, steps, K, T, M)
+    dx, dt = 0.05, 0.01
+    g = np.random.default_rng(n % 1000 + steps)
+    x1 = workloads.grid_1d(n, dx)
+    V = g.uniform(-1.0, 0.0, n)
+    P0 = workloads.complex_normal(g, n)
+    GT = workloads.complex_normal(g, n)
+    E = g.normal(0.0, 0.05, steps)
+    L = cn.Layout.contiguous(n, 1, partition=T, rows_per_thread=M)
+    tV, tx, tp, tg = to_dev(torch, V, x1, P0, GT)
+    cn.propagate(tp, tV, dx, dt, steps, E=E, xgrid=tx, layout=L)
+    psiT = tp.clone()
+    dV = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dE = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    cn.propagate_adjoint_reconstruct(tp, tg, tV, dx, dt, steps, K, E=E, xgrid=tx, dV=dV, dE=dE,
+                                     layout=L)
+    assert torch.equal(tp, psiT)
+    r0, rV, rE = oracle_mod.cn_propagate_grad(P0, V, dx, dt, steps, GT, x1, E)
+    assert rel(tg.cpu().numpy(), r0) <= 1e-10
+    assert rel(dV.cpu().numpy(), rV) <= 1e-10
+    assert rel(dE.cpu().numpy(), rE) <= 1e-10
+    # the checkpointed reverse mode on the same forward
+    tp2 = to_dev(torch, P0)[0]
+    ckpt = torch.empty(((steps + K - 1) // K) * n, dtype=torch.complex128, device="cuda")
+    cn.propagate(tp2, tV, dx, dt, steps, E=E, xgrid=tx, ckpt=ckpt, K=K, layout=L)
+    g2 = to_dev(torch, GT)[0]
+    dV2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dE2 = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    cn.propagate_adjoint(ckpt, g2, tV, dx, dt, steps, K, E=E, xgrid=tx, dV=dV2, dE=dE2,
+                         layout=L)
+    assert rel(tg.cpu().numpy(), g2.cpu().numpy()) <= 1e-11
+    assert rel(dV.cpu().numpy(), dV2.cpu().numpy()) <= 1e-11
+    assert cn.get_status() == 0
+
+
+def test_reverse_reconstruction_refuses_absorbing(gpu):
+    """The inverse of a step with an absorbing potential amplifies: refused."""
+    torch, cn = gpu
+    from paper_2205_00856_amd._lib import CnError
+
+    n = 4096
+    tV = torch.zeros(n, dtype=torch.float64, device="cuda")
+    W = torch.full((n,), 0.1, dtype=torch.float64, device="cuda")
+    p = torch.ones(n, dtype=torch.complex128, device="cuda")
+    g = torch.ones(n, dtype=torch.complex128, device="cuda")
+    with pytest.raises(CnError):
+        cn.propagate_adjoint_reconstruct(p, g, tV, 0.1, 0.01, 4, 2, W=W)
+
+
+def test_autograd_reconstruct_matches_checkpointed(gpu):
+    """autograd.cn_propagate(reconstruct=True) gives the gradients of the checkpointed form."""
+    torch, cn = gpu
+    from paper_2205_00856_amd import autograd as ag
+
+    n, steps, dx, dt = 20_000, 25, 0.05, 0.01
+    g = np.random.default_rng(8)
+    x = torch.tensor(workloads.grid_1d(n, dx), device="cuda")
+    p0 = torch.tensor(workloads.complex_normal(g, n), device="cuda")
+    phi = torch.tensor(workloads.complex_normal(g, n), device="cuda")
+    V0 = g.uniform(-1.0, 0.0, n)
+    E0 = g.normal(0.0, 0.05, steps)
+    grads = []
+    for rec in (False, True):
+        V = torch.tensor(V0, device="cuda", requires_grad=True)
+        E = torch.tensor(E0, device="cuda", requires_grad=True)
+        out = ag.cn_propagate(p0, V, E, dx, dt, xgrid=x, K=6, reconstruct=rec)
+        loss = torch.abs((torch.conj(phi) * out).sum() * dx) ** 2
+        loss.backward()
+        grads.append((V.grad.cpu().numpy(), E.grad.cpu().numpy()))
+    assert rel(grads[1][0], grads[0][0]) <= 1e-11
+    assert rel(grads[1][1], grads[0][1]) <= 1e-11
