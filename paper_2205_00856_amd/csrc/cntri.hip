@@ -1796,8 +1796,14 @@ cn_status cn_autotune(cn_handle_t h, const cn_layout* L, int cn_mode, const cn_o
   struct Cand {
     int T, M;
   };
-  const Cand cands[] = {{0, 0},    {128, 2},  {256, 4},  {512, 4},  {1024, 4}, {2048, 4},
-                        {4096, 4}, {512, 8},  {1024, 8}, {2048, 8}, {4096, 8}};
+  std::vector<Cand> cands = {{0, 0},    {128, 2},  {256, 4},  {512, 4},  {1024, 4}, {2048, 4},
+                             {4096, 4}, {512, 8},  {1024, 8}, {2048, 8}, {4096, 8}};
+  // interleaved batches run the column kernels: their tiles of T = W M rows are the candidates
+  if (!L->offsets && L->batch_stride == 1 && L->batch >= 64 && L->elem_stride >= L->batch &&
+      !L->shared_coefficients) {
+    cands.resize(1);
+    for (const Cfg& c : kColCfgs) cands.push_back({c.M * c.W, c.M});
+  }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
