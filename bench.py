@@ -936,7 +936,7 @@ def absorbing_large(torch, np, cn, workloads, dev):
     return {"steps": steps, "us_per_step": us, "unknowns_per_s": n / (us * 1e-6),
             "GBps_48": 48.0 * n / (us * 1e-6) / 1e9,
             "frac_of_8TBps_48B": 48.0 * n / (us * 1e-6) / 8e12,
-            "plan": cn.describe_plan(Lb, False),
+            "plan": cn.describe_plan(Lb, absorbing=True),
             "materialised_us_per_step": us_m,
             "materialised_frac_of_8TBps_192B": 192.0 * n / (us_m * 1e-6) / 8e12,
             "fused_vs_materialised_rel_l2": agree}

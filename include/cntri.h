@@ -341,11 +341,13 @@ cn_status cn_profile_report(cn_handle_t handle, char* buf, int64_t buflen);
  * non-finite result since the last call (and clears the flag), else CN_OK. */
 cn_status cn_get_status(cn_handle_t handle, cn_stream_t stream);
 
-/* Version string and the plan chosen for a layout (for logs and benchmarks).  With cn_mode the
- * description of the Crank-Nicolson plan ends with how cn_propagate chains its steps: one fused
- * pass per step, and whether the pass's last workgroup also solves the reduced system of the
- * tile joints (one system whose joints fit one whole-system tile), which saves a launch per
- * step. */
+/* Version string and the plan chosen for a layout (for logs and benchmarks).  cn_mode 0: the
+ * plan of cn_tridiag_solve; 1: the Crank-Nicolson plan (real potential), whose description ends
+ * with how cn_propagate chains its steps: one fused pass per step, and whether the pass's last
+ * workgroup also solves the reduced system of the tile joints (one system whose joints fit one
+ * whole-system tile), which saves a launch per step; 2: the plan of the fused steps with an
+ * absorbing potential (CN_ERR_UNSUPPORTED for a layout whose absorbing steps run
+ * materialised).  Other values: CN_ERR_INVALID_ARG. */
 const char* cn_version(void);
 cn_status cn_describe_plan(cn_handle_t handle, const cn_layout* layout, int cn_mode, char* buf,
                            int64_t buflen);

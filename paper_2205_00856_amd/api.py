@@ -183,11 +183,15 @@ def reserve(layout: Layout, device=None):
     check(_lib.lib().cn_reserve(h.ptr, ctypes.byref(Lc)), "cn_reserve")
 
 
-def describe_plan(layout: Layout, cn_mode: bool = False, device=None) -> str:
+def describe_plan(layout: Layout, cn_mode: bool = False, device=None,
+                  absorbing: bool = False) -> str:
+    """The plan of cn_tridiag_solve, of the Crank-Nicolson steps (cn_mode) or of the fused
+    steps with an absorbing potential (absorbing)."""
     h = handle(device)
     Lc = layout.c()
     buf = ctypes.create_string_buffer(4096)
-    check(_lib.lib().cn_describe_plan(h.ptr, ctypes.byref(Lc), int(cn_mode), buf, 4096),
+    mode = 2 if absorbing else int(bool(cn_mode))
+    check(_lib.lib().cn_describe_plan(h.ptr, ctypes.byref(Lc), mode, buf, 4096),
           "cn_describe_plan")
     return buf.value.decode()
 

@@ -240,8 +240,9 @@ int multi_cfg(int64_t n, int64_t batch, const Knobs& k, int level, int src) {
     return ci;
   }
   // Crank-Nicolson lines with enough rows for 512 tiles of 2048: 8 rows per lane, whose
-  // substitution runs along the RD rows (measured 10% faster per step at 2^20 and 2^24 rows)
-  if (level == 1 && src == nsd::SRC_CN && k.rpt == 0 && batch * ((n + 2047) / 2048) >= 512)
+  // substitution runs along the RD rows (measured 10% faster per step at 2^20 and 2^24 rows;
+  // with an absorbing potential 20% faster at 2^24 than 1024-row tiles of 4 rows per lane)
+  if (level == 1 && nsd::cn_src(src) && k.rpt == 0 && batch * ((n + 2047) / 2048) >= 512)
     return find_cfg(2048, 8);
   // enough tiles to fill the chip (>= 4 workgroups per CU when the system allows it)
   const int64_t target = 1024;
@@ -584,10 +585,8 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
   }
   // automatic plan of a caller's uneven batch: the long systems are solved two-pass over
   // 2048-row tiles of 8 rows per lane (measured best for lengths up to 65536)
-  // (with an absorbing potential: 1024-row tiles of 4 rows per lane, the configuration its fused
-  // pass is built for)
   int ci = (level == 1 && kn.partition == 0 && src != nsd::SRC_SLOTS)
-               ? (src == nsd::SRC_CNW ? find_cfg(1024, 4) : find_cfg(2048, 8))
+               ? find_cfg(2048, 8)
                : multi_cfg(nl / (int64_t)large.size(), (int64_t)large.size(), kn, level, src);
   const int64_t T = kCfgs[ci].T();
   std::vector<int64_t> tbase(batch + 1, 0);
@@ -1511,9 +1510,10 @@ cn_status cn_reserve(cn_handle_t h, const cn_layout* L) {
 
 cn_status cn_describe_plan(cn_handle_t h, const cn_layout* L, int cn_mode, char* buf,
                            int64_t buflen) {
-  if (!h || !buf || buflen < 1) return CN_ERR_INVALID_ARG;
+  if (!h || !buf || buflen < 1 || cn_mode < 0 || cn_mode > 2) return CN_ERR_INVALID_ARG;
   Plan* P = nullptr;
-  cn_status st = get_plan(h, L, cn_mode ? nsd::SRC_CN : nsd::SRC_EXPL, nullptr, &P);
+  const int src = cn_mode == 2 ? nsd::SRC_CNW : cn_mode ? nsd::SRC_CN : nsd::SRC_EXPL;
+  cn_status st = get_plan(h, L, src, nullptr, &P);
   if (st != CN_OK) return st;
   std::string d = P->desc;
   if (cn_mode) {

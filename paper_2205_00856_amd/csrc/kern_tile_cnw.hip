@@ -33,7 +33,7 @@ void reg_tile_cnw(Tables& t) {
   reg_all<4, 1>(t);
   reg_all<4, 2>(t);
   reg_all<4, 4>(t);
-  reg_single<8, 4>(t);
+  reg_all<8, 4>(t);
   reg_single<8, 8>(t);
 }
 

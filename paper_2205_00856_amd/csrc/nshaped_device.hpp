@@ -173,13 +173,16 @@ struct CnEdges {
 // levels instead of three.  RU only has to deliver the final row J+1 for JU; unrolled, that row
 // is the forward sum  psi_{J+1} = sum_k P_k (delta_k - beta_k psi_J) + P_M psi_K  with P_1 = 1,
 // P_{k+1} = -gamma_k P_k, accumulated here during RD, so no RD row is held for a backward pass.
-template <int M, typename E>
-__device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const E& e,
-                                                cd (&D)[M], double bK, Blk& o) {
+// CR: the diagonal's real parts are ar instead of 1 (a Crank-Nicolson matrix with an absorbing
+// potential: 1 + tau W); the off-diagonals stay those of e.
+template <int M, bool CR, typename E>
+__device__ __forceinline__ void reduce_block_rd_g(const double (&ar)[M], const double (&ay)[M],
+                                                  const E& e, cd (&D)[M], double bK, Blk& o) {
   static_assert(M >= 2, "blocks with interior rows");
+  auto dg = [&](int i) { return mk(CR ? ar[i] : 1.0, ay[i]); };
   cd beta, gam;
   {
-    const cd ia = crecip(mk(1.0, ay[1]));
+    const cd ia = crecip(dg(1));
     beta = cimul(e.b(1), ia);
     gam = cimul(e.c(1), ia);
     D[1] = cmul(D[1], ia);
@@ -188,7 +191,7 @@ __device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const E& 
 #pragma unroll
   for (int i = 2; i < M; ++i) {
     const double bi = e.b(i);
-    const cd a = csub(mk(1.0, ay[i]), cimul(bi, gam));
+    const cd a = csub(dg(i), cimul(bi, gam));
     const cd d = csub(D[i], cimul(bi, D[i - 1]));
     const cd b = cneg(cimul(bi, beta));
     const cd ia = crecip(a);
@@ -205,21 +208,28 @@ __device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const E& 
   o.DD = cneg(cimul(bK, D[M - 1]));
   // JU at J with row J+1 final: beta = fb, gamma = -P, delta = fd
   const double c0 = e.c(0);
-  o.UA = csub(mk(1.0, ay[0]), cimul(c0, fb));
+  o.UA = csub(dg(0), cimul(c0, fb));
   o.UD = csub(D[0], cimul(c0, fd));
   o.UC = cimul(c0, P);
 }
+template <int M, typename E>
+__device__ __forceinline__ void reduce_block_rd(const double (&ay)[M], const E& e,
+                                                cd (&D)[M], double bK, Blk& o) {
+  reduce_block_rd_g<M, false>(ay, ay, e, D, bK, o);
+}
 
-// SS along the RD rows of reduce_block_rd: with psi_J and psi_K = psi_{J+M} known,
+// SS along the RD rows of reduce_block_rd(_g): with psi_J and psi_K = psi_{J+M} known,
 //   psi_i = delta_i - beta_i psi_J - gamma_i psi_{i+1},  i = M-1 down to 1,
 // where beta_i and gamma_i are recomputed from ay and e with reduce_block_rd's operations.
-template <int M, typename E>
-__device__ __forceinline__ void ss_block_rd(const double (&ay)[M], const E& e,
-                                            const cd (&D)[M], cd pJ, cd pK, cd (&x)[M]) {
+template <int M, bool CR, typename E>
+__device__ __forceinline__ void ss_block_rd_g(const double (&ar)[M], const double (&ay)[M],
+                                              const E& e, const cd (&D)[M], cd pJ, cd pK,
+                                              cd (&x)[M]) {
+  auto dg = [&](int i) { return mk(CR ? ar[i] : 1.0, ay[i]); };
   cd gam[M], dp[M];
   cd beta;
   {
-    const cd ia = crecip(mk(1.0, ay[1]));
+    const cd ia = crecip(dg(1));
     beta = cimul(e.b(1), ia);
     gam[1] = cimul(e.c(1), ia);
     dp[1] = cfms(beta, pJ, D[1]);
@@ -227,7 +237,7 @@ __device__ __forceinline__ void ss_block_rd(const double (&ay)[M], const E& e,
 #pragma unroll
   for (int i = 2; i < M; ++i) {
     const double bi = e.b(i);
-    const cd a = csub(mk(1.0, ay[i]), cimul(bi, gam[i - 1]));
+    const cd a = csub(dg(i), cimul(bi, gam[i - 1]));
     const cd ia = crecip(a);
     beta = cmul(cneg(cimul(bi, beta)), ia);
     gam[i] = cimul(e.c(i), ia);
@@ -240,6 +250,11 @@ __device__ __forceinline__ void ss_block_rd(const double (&ay)[M], const E& e,
     nx = cfms(gam[i], nx, dp[i]);
     x[i] = nx;
   }
+}
+template <int M, typename E>
+__device__ __forceinline__ void ss_block_rd(const double (&ay)[M], const E& e,
+                                            const cd (&D)[M], cd pJ, cd pK, cd (&x)[M]) {
+  ss_block_rd_g<M, false>(ay, ay, e, D, pJ, pK, x);
 }
 
 // SS on the lane's block: psi_i = delta_i - beta_i psi_J - gamma_i psi_K.

@@ -347,12 +347,8 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
       const double t = tau * (idx2 + fma(xv[j + 1], A.E_next, A.vscale * vv[j + 1]));
       ayn[j] = row_in<IN>(J + j, G.n) ? t : 0.0;
     }
-    // SRC_CNW: tau W of the next step after the M imaginary parts
-    if constexpr (WA) {
-#pragma unroll
-      for (int j = 0; j < M; ++j)
-        ayn[M + j] = row_in<IN>(J + j, G.n) ? tau * (A.wscale * wv[j + 1]) : 0.0;
-    }
+    // (SRC_CNW: the real parts, 1 + tau W, do not change from step to step: the next step takes
+    // those of this one)
   }
 }
 
@@ -589,9 +585,8 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
   constexpr int PL = (PH == PH_FUSE) ? PH_SUBST : PH;  // the rows are those of a PH_SUBST pass
-  // PH_FUSE: diagonal of the next step, from this pass's loads of V and xgrid (imaginary parts;
-  // SRC_CNW: then tau W, the real parts less one)
-  double ayn[SRC == SRC_CNW ? 2 * M : M];
+  // PH_FUSE: diagonal of the next step, from this pass's loads of V and xgrid (imaginary parts)
+  double ayn[M];
   double* ayp = (PH == PH_FUSE) ? ayn : nullptr;
   // wavefront-uniform choice between the interior path and the general one
   if (SRC != SRC_SLOTS && w0 >= 1 && G.n >= w0 + 64 * M + 1) {
@@ -614,7 +609,8 @@ __device__ __forceinline__ void tile_run(const KArgs& A, const Geo& G, TileSmem<
 // ss_block_rd (fewer registers, so two 512-lane workgroups fit a CU; with fewer rows per lane
 // the extra arithmetic buys no occupancy): keep holds 64 * M doubles of this wavefront's LDS for
 // the diagonals between the two, and kap is the off-diagonal magnitude (tau / (2 dx^2)) that
-// ss_block_rd recomputes the couplings from.
+// ss_block_rd recomputes the couplings from.  With an absorbing potential the diagonal's real
+// parts (1 + tau W) stay in registers between the two (the staging buffer has no room for them).
 // A store that reaches the level of the memory system shared by all XCDs (a relaxed atomic at
 // device scope), used for the values a tile hands to the next level: the last workgroup of a
 // pass that solves the reduced system itself reads them right after the other workgroups have
@@ -626,7 +622,7 @@ __device__ __forceinline__ void st_coh(cd* p, cd v) {
 
 template <int M, int W, int SRC, int PH>
 struct RdSubst {
-  static constexpr bool on = SRC == SRC_CN && PH != PH_REDUCE && M == 8;
+  static constexpr bool on = cn_src(SRC) && PH != PH_REDUCE && M == 8;
 };
 
 // COH: the slots and edge rows of a PH_REDUCE part are stored device-coherent (st_coh), for a
@@ -655,16 +651,22 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
 
   Blk blk;
   const CnEdges<IN> edges{J, G.n, kap};
+  // SRC_CNW: real parts of the diagonal (1 + tau W), held from the reduction to the substitution
+  constexpr bool CR = SRC == SRC_CNW;
+  double ar[M];
   wave_sync();
   if constexpr (RD) {
     double ay[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) ay[j] = Ar[j].y;
+    for (int j = 0; j < M; ++j) {
+      ay[j] = Ar[j].y;
+      ar[j] = CR ? Ar[j].x : 1.0;
+    }
     if constexpr (PH != PH_REDUCE) {
 #pragma unroll
       for (int j = 1; j < M; ++j) keep[j * 64 + lane] = ay[j];
     }
-    reduce_block_rd<M>(ay, edges, Dr, bK.y, blk);
+    reduce_block_rd_g<M, CR>(ar, ay, edges, Dr, bK.y, blk);
   } else {
     reduce_block<M, cn_src(SRC)>(Ar, Br, Cr, Dr, bK, blk);
   }
@@ -731,7 +733,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
       ay[0] = 0.0;
 #pragma unroll
       for (int j = 1; j < M; ++j) ay[j] = keep[j * 64 + lane];
-      ss_block_rd<M>(ay, edges, Dr, pJ, pM, xo);
+      ss_block_rd_g<M, CR>(ar, ay, edges, Dr, pJ, pM, xo);
     } else {
       ss_block<M>(Br, Cr, Dr, pJ, pM, xo);
     }
@@ -757,7 +759,8 @@ __device__ __forceinline__ void check_rows(const KArgs& A, const Geo& G, int64_t
 template <int M, int W, bool IN, int SRC = SRC_CN>
 __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                           cd* buf, int64_t J, int lane, int wave,
-                                          const cd (&xo)[M], cd pM, const double* ayn) {
+                                          const cd (&xo)[M], cd pM, const double* ayn,
+                                          const double* arn = nullptr) {
   static_assert(M >= 2, "the next step is reduced in the RD form");
   constexpr bool WA = SRC == SRC_CNW;
   using S = Stage<M>;
@@ -774,8 +777,9 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
     for (int j = 0; j < M + 2; ++j) vp[j] = csel(J - 1 + j < G.n, vp[j], czero());
   }
   wave_sync();
-  // the rows of the next step: its diagonal came with the first half's loads (ayn), the
-  // right-hand side is the explicit half-step of cn_rows with the same diagonal
+  // the rows of the next step: its diagonal came with the first half's loads (ayn; SRC_CNW: the
+  // real parts arn = 1 + tau W are this step's), the right-hand side is the explicit half-step
+  // of cn_rows with the same diagonal
   const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
   const double kap = cn_kappa(A.dt, dx);
   const cd zero = czero();
@@ -786,17 +790,16 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
     const cd p = vp[j + 1];
     const cd s2 = cadd(vp[j], vp[j + 2]);
     const bool ok = row_in<IN>(J + j, G.n);
+    Br[j] = Cr[j] = zero;  // the RD form takes the couplings from kap
     if constexpr (WA) {
-      // the general reduction: full complex diagonal, couplings -i kappa inside the system
-      const double tw = ayn[M + j];
-      Ar[j] = mk(1.0 + tw, w);
-      Br[j] = mk(0.0, (ok && row_pos<IN>(J + j)) ? -kap : 0.0);
-      Cr[j] = mk(0.0, (ok && row_notlast<IN>(J + j, G.n)) ? -kap : 0.0);
+      // tau W recovered from 1 + tau W exactly (Sterbenz): the diagonal is this step's to the
+      // bit, the explicit side's tau W within an ulp of 1 of it
+      const double tw = arn[j] - 1.0;
+      Ar[j] = mk(arn[j], w);
       Dr[j] = csel(ok, mk(fma(-tw, p.x, fma(w, p.y, fma(-kap, s2.y, p.x))),
                           fma(-tw, p.y, fma(-w, p.x, fma(kap, s2.x, p.y)))), zero);
     } else {
       Ar[j] = mk(1.0, w);
-      Br[j] = Cr[j] = zero;  // the RD form takes the couplings from kap
       Dr[j] = csel(ok, mk(fma(w, p.y, fma(-kap, s2.y, p.x)), fma(-w, p.x, fma(kap, s2.x, p.y))),
                    zero);
     }
@@ -804,10 +807,9 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
   const cd bK = mk(0.0, row_in<IN>(J + M, G.n) ? -kap : 0.0);
   Node* wnode = reinterpret_cast<Node*>(buf);
   double* keep = reinterpret_cast<double*>(wnode + 64);
-  // reduced in the RD form (real potentials): the diagonal and the right-hand side are all it
-  // keeps per row; with the absorbing term, Table 1's reduction of the full rows
-  tile_core<M, W, SRC, PH_REDUCE, IN, !WA, true>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar,
-                                                 Br, Cr, Dr, bK, vp[1], vp[M], dummy);
+  // reduced in the RD form: the diagonal and the right-hand side are all it keeps per row
+  tile_core<M, W, SRC, PH_REDUCE, IN, true, true>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar,
+                                                  Br, Cr, Dr, bK, vp[1], vp[M], dummy);
 }
 
 // Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
@@ -831,6 +833,13 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
   }
   cd xo[M];
   cd pM = czero();
+  // PH_FUSE with an absorbing potential: the diagonal's real parts for the next step
+  constexpr bool KR = PH == PH_FUSE && SRC == SRC_CNW;
+  double arn[KR ? M : 1];
+  if constexpr (KR) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) arn[j] = Ar[j].x;
+  }
   tile_core<M, W, SRC, PS, IN>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar, Br, Cr, Dr, bK, fst,
                                lst, xo, PH == PH_FUSE ? &pM : nullptr);
   if constexpr (PS != PH_REDUCE) {
@@ -844,7 +853,7 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
     }
   }
   if constexpr (PH == PH_FUSE && cn_src(SRC))
-    fuse_next<M, W, IN, SRC>(A, G, sm, buf, J, lane, wave, xo, pM, ayn);
+    fuse_next<M, W, IN, SRC>(A, G, sm, buf, J, lane, wave, xo, pM, ayn, KR ? arn : nullptr);
 }
 
 // Waves per SIMD that the register allocation of a tile kernel must allow: the fused pass of
@@ -852,7 +861,7 @@ __device__ __forceinline__ void tile_finish(const KArgs& A, const Geo& G, TileSm
 // register above the budget of 3 wavefronts; the others keep the compiler's choice.
 template <int M, int PH, int SRC = SRC_CN>
 constexpr int tile_min_waves() {
-  return (PH == PH_FUSE && M == 8 && SRC == SRC_CN) ? 3 : 1;
+  return (PH == PH_FUSE && M == 8 && cn_src(SRC)) ? 3 : 1;
 }
 
 // The reduced system of a PH_FUSE pass over one system, solved in the same launch: every

@@ -166,6 +166,51 @@ def test_uneven_step_with_absorber(gpu, oracle_mod):
         assert rel(out[o0:o1], ref) <= TOL
 
 
+@pytest.mark.parametrize("part,rpt", [(0, 0), (2048, 8), (1024, 4), (512, 4), (256, 4)])
+def test_absorbing_propagate_tile_configs(gpu, oracle_mod, part, rpt):
+    """The fused absorbing pass (one pass per step: substitution of step k, then step k+1's
+    rows reduced in the RD form with the real diagonal parts 1 + tau W carried over) in every
+    tile configuration built for it, and the automatic plan, over 300_007 rows (a ragged last
+    tile) with a field: 6 steps against the oracle."""
+    torch, cn = gpu
+    n, dx, dt, steps = 300_007, 0.1, 0.02, 6
+    log("absorbing propagate tiles", part, rpt)
+    V, psi, W = case(n, 31 + part % 89, dx, dt)
+    xg = workloads.grid_1d(n, dx)
+    E = np.random.default_rng(5).normal(0.0, 0.05, steps)
+    ref = psi
+    for k in range(steps):
+        ref = oracle_mod.cn_step(ref, V, dx, dt, xg, E[k], W=W)
+    L = cn.Layout.contiguous(n, 1, partition=part, rows_per_thread=rpt)
+    tV, tpsi, tW, txg = to_dev(torch, V, psi, W, xg)
+    cn.propagate(tpsi, tV, dx, dt, steps, E=E, xgrid=txg, W=tW, layout=L)
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+    assert cn.get_status() == 0
+
+
+def test_uneven_propagate_with_absorber(gpu, oracle_mod):
+    """An uneven batch with systems of up to 40000 rows (two-pass ones in the fused form,
+    short ones whole) through 5 steps against the oracle, system by system."""
+    torch, cn = gpu
+    wl = workloads.uneven_batch(batch=60, hi=40_000, steps=1, seed=13)
+    offs = wl["offsets"]
+    steps = 5
+    W = np.concatenate([workloads.absorber(int(offs[s + 1] - offs[s]))
+                        for s in range(wl["batch"])])
+    tV, tpsi, tdx, tW = to_dev(torch, wl["V"], wl["psi0"], wl["dx"], W)
+    cn.propagate(tpsi, tV, 0.0, wl["dt"], steps, dx_per_system=tdx, W=tW,
+                 layout=cn.Layout.uneven(offs))
+    out = tpsi.cpu().numpy()
+    assert max(offs[s + 1] - offs[s] for s in range(wl["batch"])) > 4096
+    for s in range(wl["batch"]):
+        o0, o1 = offs[s], offs[s + 1]
+        ref = wl["psi0"][o0:o1]
+        for _ in range(steps):
+            ref = oracle_mod.cn_step(ref, wl["V"][o0:o1], wl["dx"][s], wl["dt"], W=W[o0:o1])
+        assert rel(out[o0:o1], ref) <= TOL
+    assert cn.get_status() == 0
+
+
 def test_absorbing_step_graph_replays(gpu):
     """After one call outside capture (which sizes the handle's buffer), the materialised step
     captures; replays with eager work between them give the eager result bit for bit."""
@@ -321,9 +366,8 @@ def test_absorbing_reverse_mode_finite_differences(gpu):
 
 
 def test_absorbing_plans_are_fused(gpu):
-    """The absorbing step takes the fused kernels: no materialised buffer appears in the
-    handle, and a propagation over a two-pass plan describes the same plan as the Hermitian
-    one would use with tiles of 4 rows per lane."""
+    """The absorbing step takes the fused kernels: after a propagation over a two-pass plan
+    the handle holds no materialised buffer."""
     torch, cn = gpu
     from paper_2205_00856_amd import _lib
 
@@ -347,6 +391,10 @@ def test_absorbing_plans_are_fused(gpu):
         assert lib.cn_handle_info(h, ctypes.byref(nbytes), None, None) == _lib.CN_OK
         # the materialised form would hold 4 complex values per row (a, b, c, d)
         assert nbytes.value < 4 * 16 * n
+        # a line of 2^20 rows: 2048-row tiles of 8 rows per lane, one fused pass per step
+        plan = cn.describe_plan(cn.Layout.contiguous(1 << 20, 1), absorbing=True)
+        log("absorbing plan:", plan)
+        assert plan.startswith("L1 multi T=2048(M=8,W=4)") and "chain: one fused pass" in plan
     finally:
         torch.cuda.synchronize()
         lib.cn_destroy(h)
