@@ -326,6 +326,7 @@ def main():
         result["parity_full_size"] = {
             "plain_1d_solve": get("plain_1d", "parity_rel_l2_solve"),
             "plain_1d_psi_200": get("plain_1d", "parity_rel_l2_200"),
+            "plain_1d_psi_200_resident": get("plain_1d", "parity_rel_l2_200_resident"),
             "adi_2d_psi_100": parity_full,
             "large_system_2^28_x": get("large_system_2^28", "parity_rel_l2"),
             "uneven_batch_psi_50": get("uneven_batch", "parity_rel_l2_50_steps"),
@@ -639,7 +640,15 @@ def extras(torch, np, cn, workloads, dev):
         psi200 = psi.cpu().numpy()
         ts_graph = timed_events(torch, gr.replay, 5)
         med = float(np.median(ts_graph))
+        # the same 200 steps as one resident launch (cn_propagate_resident)
+        pr = psi0.clone()
+        cn.propagate_resident(pr, V, w["dx"], w["dt"], w["steps"])
+        torch.cuda.synchronize()
+        psi200_res = pr.cpu().numpy()
+        ts_res = timed_events(torch, lambda: cn.propagate_resident(pr, V, w["dx"], w["dt"],
+                                                                    w["steps"]), 5)
         out["plain_1d"] = {"n": w["n"], "steps": w["steps"],
+                           "us_per_step_resident": float(np.median(ts_res)) * 1e3 / w["steps"],
                            "solve_us": float(np.median(ts_solve)) * 1e3,
                            "ms_per_200_steps_graph": med,
                            "us_per_step_graph": med * 1e3 / w["steps"],
@@ -657,6 +666,7 @@ def extras(torch, np, cn, workloads, dev):
             w["n"] * w["steps"], out["plain_1d"]["unknowns_per_s"])
         if "x" in ref:
             out["plain_1d"]["parity_rel_l2_200"] = rel_l2(psi200, ref["x"])
+            out["plain_1d"]["parity_rel_l2_200_resident"] = rel_l2(psi200_res, ref["x"])
         # the one materialised solve against the oracle's assembly, half-step and Thomas solve
         import oracle
 
@@ -944,8 +954,9 @@ def absorbing_large(torch, np, cn, workloads, dev):
 
 def latency_legs(torch, np, cn, workloads, dev):
     """Step times of the latency-bound sequences alone: the plain 1D workload (200 steps in
-    one graph, with the automatic plan and after the sequence autotuner) and the differentiated
-    workload's 2000-step forward with checkpoints and its reverse mode (C ABI directly)."""
+    one graph, with the automatic plan and after the sequence autotuner; and as one resident
+    launch) and the differentiated workload's 2000-step forward with checkpoints and its
+    reverse mode (C ABI directly)."""
     out = {}
     w = workloads.plain_1d()
     psi0 = torch.from_numpy(w["psi0"]).to(dev)
@@ -973,6 +984,11 @@ def latency_legs(torch, np, cn, workloads, dev):
     out["plain_1d_tuned"] = {"plan": cn.describe_plan(L, True), "us_per_step": graph_us(),
                              "autotune": rep}
     del tmp
+    pr = psi0.clone()
+    cn.propagate_resident(pr, V, w["dx"], w["dt"], w["steps"])
+    out["plain_1d_resident"] = {"us_per_step": float(np.median(timed_events(
+        torch, lambda: cn.propagate_resident(pr, V, w["dx"], w["dt"], w["steps"]), 5)))
+        * 1e3 / w["steps"]}
     d = workloads.differentiated()
     n, steps, K = d["n"], d["steps"], d["ckpt"]
     Ld = cn.Layout.contiguous(n, 1)

@@ -53,8 +53,11 @@ typedef enum {
   CN_ERR_NO_MEMORY = -3,      /* device allocation failed                                   */
   CN_ERR_HIP = -4,            /* a HIP runtime call failed                                  */
   CN_ERR_NOT_RESERVED = -5,   /* workspace would have to grow during graph capture          */
-  CN_ERR_SCRATCH_TOO_SMALL = -6 /* cn_tridiag_solve_noalloc: the layout needs more device
+  CN_ERR_SCRATCH_TOO_SMALL = -6, /* cn_tridiag_solve_noalloc: the layout needs more device
                                   memory than the library's fixed scratch array holds          */
+  CN_ERR_WAIT_TIMEOUT = -7    /* cn_get_status: the workgroups of a resident propagation
+                                 gave up waiting on each other (other work on the GPU kept
+                                 some from running); its state is unspecified               */
 } cn_status;
 
 /* Shape of the batch of independent systems handled by one call.
@@ -223,6 +226,29 @@ cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_ope
                        int64_t nsteps, const double* E, void* psi, void* ckpt, int64_t K,
                        cn_stream_t stream);
 
+/* All nsteps Crank-Nicolson steps of one system in ONE launch (Sec. 2, Eqs. (2)-(4), each step
+ * solved by the N-shaped partition of Sec. 4 with the explicit half-step fused, Sec. 5.3): the
+ * kernel keeps one tile of T rows per workgroup resident for the whole sequence, its rows in
+ * registers; per step every tile publishes its Table 1 slots, waits until all tiles have, solves
+ * the reduced system on the tile joints itself and substitutes.  For sequences of mid-size
+ * systems, whose chained passes are bound by launch and hand-over latency rather than by
+ * memory.  Same result as cn_propagate without checkpoints, up to rounding.
+ *   L: one contiguous system (batch 1, elem_stride 1, no offsets, no shared coefficients or
+ *      levels; rows_per_thread 0 or 8; partition 0, or 512, 1024 or 2048 rows per tile).
+ *   op: real potential (no absorb), one dx (no dx_per_system).
+ *   E: HOST, nsteps field values or null (zero field); uploaded with an asynchronous copy on
+ *      the stream (so E != null cannot be captured into a graph: CN_ERR_UNSUPPORTED).
+ *   psi: DEVICE, n complex values, updated in place.
+ * CN_ERR_UNSUPPORTED also when the system needs more tiles than fit the GPU at once or than the
+ * reduced solve of one workgroup takes (128 W joints: up to 2^20 rows), or when CN_RESIDENT=0
+ * is set; then cn_propagate is the call.  The workgroups wait on each other: a launch that runs
+ * beside other work on the same GPU (another stream, another resident propagation) may find
+ * some of its workgroups unable to start; then the waits give up after a bound, the state is
+ * left unspecified and cn_get_status returns CN_ERR_WAIT_TIMEOUT.  Enqueued on stream. */
+cn_status cn_propagate_resident(cn_handle_t handle, const cn_layout* layout,
+                                const cn_operator* op, int64_t nsteps, const double* E,
+                                void* psi, cn_stream_t stream);
+
 /* One step of the adjoint recursion of cn_propagate (uniform batch of one system).
  * With psi_np1 = T_n^{-1} B_n psi_n, B_n = 1 - i tau H_n, and g_np1 the gradient at psi_np1:
  *   lambda = T_n^{-H} g_np1   (T_n^H = B_n for real v),
@@ -337,8 +363,9 @@ cn_status cn_handle_info(cn_handle_t handle, int64_t* device_bytes, int64_t* ret
 cn_status cn_profile(cn_handle_t handle, int enable);
 cn_status cn_profile_report(cn_handle_t handle, char* buf, int64_t buflen);
 
-/* Synchronises the stream, returns CN_NUMERICAL_BREAKDOWN if any kernel of this handle met a
- * non-finite result since the last call (and clears the flag), else CN_OK. */
+/* Synchronises the stream, returns CN_ERR_WAIT_TIMEOUT if a resident propagation of this
+ * handle gave up a wait, else CN_NUMERICAL_BREAKDOWN if any kernel of this handle met a
+ * non-finite result since the last call (and clears the flags), else CN_OK. */
 cn_status cn_get_status(cn_handle_t handle, cn_stream_t stream);
 
 /* Version string and the plan chosen for a layout (for logs and benchmarks).  cn_mode 0: the

@@ -5,6 +5,7 @@ binds it for torch device tensors and adds autograd wrappers.
 """
 from .api import (Handle, Layout, assemble, radial_step, autotune, describe_plan, get_status, handle,  # noqa: F401
                   profile, profile_report, propagate, propagate_adjoint, propagate_adjoint_reconstruct,
+                  propagate_resident,
                   reserve, rhs, solve, solve_adjoint,
                   solve_noalloc, step, tune_cache,
                   step_adjoint)

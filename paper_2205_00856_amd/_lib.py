@@ -19,6 +19,7 @@ CN_ERR_NO_MEMORY = -3
 CN_ERR_HIP = -4
 CN_ERR_NOT_RESERVED = -5
 CN_ERR_SCRATCH_TOO_SMALL = -6
+CN_ERR_WAIT_TIMEOUT = -7
 
 
 class CnLayout(ctypes.Structure):
@@ -95,6 +96,7 @@ def lib():
         "cn_rhs": ([H, LP, OP, d, P, P, P], ctypes.c_int),
         "cn_step": ([H, LP, OP, d, P, P, P], ctypes.c_int),
         "cn_propagate": ([H, LP, OP, i64, P, P, P, i64, P], ctypes.c_int),
+        "cn_propagate_resident": ([H, LP, OP, i64, P, P, P], ctypes.c_int),
         "cn_step_adjoint": ([H, LP, OP, d, P, P, P, P, P, P, P], ctypes.c_int),
         "cn_get_status": ([H, P], ctypes.c_int),
         "cn_version": ([], ctypes.c_char_p),
@@ -121,7 +123,7 @@ def lib():
 
 EXPORTED = ["cn_check_layout", "cn_create", "cn_destroy", "cn_status_string", "cn_reserve", "cn_tridiag_solve",
             "cn_tridiag_solve_adjoint", "cn_assemble", "cn_rhs", "cn_step", "cn_propagate",
-            "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
+            "cn_propagate_resident", "cn_step_adjoint", "cn_get_status", "cn_version", "cn_describe_plan", "cn_autotune",
             "cn_propagate_adjoint", "cn_propagate_adjoint_reconstruct", "cn_handle_info", "cn_tridiag_solve_noalloc", "cn_profile",
             "cn_profile_report", "cn_tune_cache", "cn_radial_step"]
 

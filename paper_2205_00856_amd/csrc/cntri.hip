@@ -35,6 +35,7 @@ nsk::Tables& nsk::tables() {
     reg_pers(x);
     reg_mrhs(x);
     reg_aux(x);
+    reg_resident(x);
     return x;
   }();
   return t;
@@ -690,6 +691,9 @@ struct cn_handle_s {
   // persistent autotune cache (cn_tune_cache): file path and entries, layout class -> "T,M"
   std::string cache_path;
   std::map<std::string, std::string> cache;
+  // resident propagation: slots, edge rows and joint values of its tiles, then the field
+  void* res = nullptr;
+  size_t res_size = 0;
   // plan log (cn_profile): HIP events around every launch of run_plan, with a label each
   bool profiling = false;
   struct Rec {
@@ -1438,6 +1442,7 @@ const char* cn_status_string(cn_status st) {
     case CN_ERR_HIP: return "CN_ERR_HIP";
     case CN_ERR_NOT_RESERVED: return "CN_ERR_NOT_RESERVED";
     case CN_ERR_SCRATCH_TOO_SMALL: return "CN_ERR_SCRATCH_TOO_SMALL";
+    case CN_ERR_WAIT_TIMEOUT: return "CN_ERR_WAIT_TIMEOUT";
   }
   return "unknown cn_status";
 }
@@ -1481,6 +1486,7 @@ cn_status cn_destroy(cn_handle_t h) {
   if (h->seg2) (void)hipFree(h->seg2);
   if (h->mat) (void)hipFree(h->mat);
   if (h->rad) (void)hipFree(h->rad);
+  if (h->res) (void)hipFree(h->res);
   for (void* p : h->retired) (void)hipFree(p);
   for (auto& r : h->recs) {
     (void)hipEventDestroy(r.e0);
@@ -1712,6 +1718,114 @@ cn_status cn_propagate(cn_handle_t h, const cn_layout* L, const cn_operator* op,
     st = run_plan(h, P, u, s);
     if (st != CN_OK) return st;
   }
+  return CN_OK;
+}
+
+// Resident propagation (k_resident): the configuration for n rows (the smallest tile whose
+// count fits both the reduced solve of one workgroup, 128 W joints, and the GPU at once), or -1.
+namespace {
+bool resident_enabled() {
+  const char* e = getenv("CN_RESIDENT");
+  return !(e && e[0] == '0');
+}
+int resident_spin() {
+  const char* e = getenv("CN_RESIDENT_SPIN");  // polls before a wait gives up (tests)
+  if (e && *e) {
+    const long v = strtol(e, nullptr, 10);
+    if (v >= 0 && v <= INT_MAX) return (int)v;
+  }
+  return 1 << 22;
+}
+int64_t resident_capacity(int ci) {
+  static std::mutex mu;
+  static int64_t cap[nsk::kNumResCfg] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (cap[ci] == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, nsk::tables().res[ci],
+                                                     64 * nsk::kResCfgs[ci].W, 0) != hipSuccess ||
+        per_cu < 1) {
+      (void)hipGetLastError();
+      per_cu = 0;
+    }
+    cap[ci] = per_cu > 0 ? (int64_t)per_cu * num_cus() : -1;
+  }
+  return cap[ci];
+}
+int resident_cfg(int64_t n, int64_t partition) {
+  for (int ci = 0; ci < nsk::kNumResCfg; ++ci) {
+    const Cfg c = nsk::kResCfgs[ci];
+    if (partition > 0 && c.T() != partition) continue;
+    const int64_t K = (n + c.T() - 1) / c.T();
+    if (K <= 128 * c.W && K <= resident_capacity(ci)) return ci;
+  }
+  return -1;
+}
+}  // namespace
+
+cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_operator* op,
+                                int64_t nsteps, const double* E, void* psi, cn_stream_t stream) {
+  if (!h || !psi || nsteps < 0 || nsteps > INT_MAX - 2) return CN_ERR_INVALID_ARG;
+  cn_status st = check_op(op);
+  if (st != CN_OK) return st;
+  int64_t rows = 0, span = 0;
+  st = validate(L, rows, span);
+  if (st != CN_OK) return st;
+  if (!resident_enabled() || op->absorb || op->dx_per_system || L->offsets || L->batch != 1 ||
+      L->elem_stride != 1 || L->shared_coefficients || L->levels ||
+      (L->rows_per_thread && L->rows_per_thread != 8))
+    return CN_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  const bool cap = capturing(s);
+  if (E && cap) return CN_ERR_UNSUPPORTED;  // the field is uploaded by a host copy
+  const int ci = resident_cfg(L->n, L->partition);
+  if (ci < 0) return CN_ERR_UNSUPPORTED;
+  if (nsteps == 0) return CN_OK;
+  const int64_t T = nsk::kResCfgs[ci].T(), K = (L->n + T - 1) / T;
+  // workspace: a flag per tile (a fixed area for the most tiles any configuration takes, zero
+  // between launches), then two parity buffers each of slots (3 + 3 per tile) and edge rows
+  // (2 per tile), then the field
+  constexpr int64_t kMaxTiles = 128 * 4;
+  const size_t o_oU = kMaxTiles * sizeof(int), o_oD = o_oU + 6 * K * sizeof(cd),
+               o_h = o_oD + 6 * K * sizeof(cd), o_E = o_h + 4 * K * sizeof(cd);
+  const size_t need = o_E + (E ? (size_t)nsteps * sizeof(double) : 0);
+  if (cap) h->captured = true;
+  if (need > h->res_size) {
+    if (cap) return CN_ERR_NOT_RESERVED;
+    st = regrow(h, &h->res, &h->res_size, need);
+    if (st != CN_OK) return st;
+    HIP_TRY(hipMemset(h->res, 0, need));  // the flags start at zero (not inside a capture)
+  }
+  char* w = (char*)h->res;
+  if (E) HIP_TRY(hipMemcpyAsync(w + o_E, E, nsteps * sizeof(double), hipMemcpyHostToDevice, s));
+  KArgs a{};
+  a.n = L->n;
+  a.ntiles = K;
+  a.es = 1;
+  a.bs = L->n;
+  a.psi = (const cd*)psi;
+  a.x = (cd*)psi;
+  a.V = op->V;
+  a.xg = op->xgrid;
+  a.vscale = op->v_scale;
+  a.dx = op->dx;
+  a.dt = op->dt;
+  a.wscale = 1.0;
+  a.oU = (cd*)(w + o_oU);
+  a.oD = (cd*)(w + o_oD);
+  a.halo_out = (cd*)(w + o_h);
+  a.status = h->status;
+  nsd::ResArgs r{};
+  r.E = E ? (const double*)(w + o_E) : nullptr;
+  r.nsteps = (int)nsteps;
+  r.flags = (int*)w;
+  r.sync = h->status + 96;
+  r.spin = resident_spin();
+  r.bufstep = K;
+  void* params[] = {&a, &r};
+  if (hipLaunchKernel(nsk::tables().res[ci], dim3((unsigned)K), dim3(64 * nsk::kResCfgs[ci].W),
+                      params, 0, s) != hipSuccess)
+    return CN_ERR_HIP;
   return CN_OK;
 }
 
@@ -2247,7 +2361,7 @@ cn_status cn_get_status(cn_handle_t h, cn_stream_t stream) {
   HIP_TRY(hipMemcpy(&v, h->status, sizeof(int), hipMemcpyDeviceToHost));
   if (v) {
     HIP_TRY(hipMemset(h->status, 0, sizeof(int)));
-    return CN_NUMERICAL_BREAKDOWN;
+    return (v & 4) ? CN_ERR_WAIT_TIMEOUT : CN_NUMERICAL_BREAKDOWN;
   }
   return CN_OK;
 }

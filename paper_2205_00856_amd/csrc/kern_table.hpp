@@ -21,6 +21,10 @@ constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr Cfg kColCfgs[] = {{4, 8}, {8, 4}, {8, 8}, {4, 16}, {16, 4}, {8, 16}};
 constexpr int kNumColCfg = sizeof(kColCfgs) / sizeof(kColCfgs[0]);
 
+// Resident propagations (k_resident): 8 rows per lane, tiles of 512, 1024 and 2048 rows.
+constexpr Cfg kResCfgs[] = {{8, 1}, {8, 2}, {8, 4}};
+constexpr int kNumResCfg = sizeof(kResCfgs) / sizeof(kResCfgs[0]);
+
 constexpr int kNumSrc = 6;  // nsd::Src
 constexpr int kNumPh = 4;   // nsd::Phase
 
@@ -42,6 +46,7 @@ struct Tables {
   const void* cols[kNumColCfg][kNumSrc][3];
   const void* mrhs[kNumCfg][3];  // one matrix, several right-hand sides (explicit source)
   const void* aux[kNumAux];
+  const void* res[kNumResCfg];   // resident propagation of one system
 };
 
 // The one table of the library (cntri.hip), filled once by the registration functions below.
@@ -57,6 +62,7 @@ void reg_cols(Tables& t);
 void reg_pers(Tables& t);
 void reg_mrhs(Tables& t);
 void reg_aux(Tables& t);
+void reg_resident(Tables& t);
 
 template <int M, int W>
 constexpr int cfg_index() {

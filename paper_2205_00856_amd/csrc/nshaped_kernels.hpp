@@ -29,8 +29,11 @@ enum Phase : int {
   PH_SINGLE = 0,  // the tile holds the whole system: reduce, RS, SS in one pass
   PH_REDUCE = 1,  // first pass of a multi-tile system: reduce, write the tile's slots
   PH_SUBST = 2,   // second pass: re-reduce, take the tile's joint lines from above, SS
-  PH_FUSE = 3     // Crank-Nicolson sequences: PH_SUBST of step n, then PH_REDUCE of step n+1 on
+  PH_FUSE = 3,    // Crank-Nicolson sequences: PH_SUBST of step n, then PH_REDUCE of step n+1 on
                   // the new state (the tile's joint row defers its left neighbour, see ud_halo)
+  PH_RES = 4      // a step of the resident propagation (k_resident): PH_REDUCE's hand-over,
+                  // then, once the reduced system is solved in the same launch, PH_SUBST's
+                  // substitution (not a phase of the kernel tables)
 };
 
 struct KArgs {
@@ -307,7 +310,7 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
                                          int64_t J, int lane, int wave, CnRaw<M, XG, WA>& raw,
                                          cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
                                          cd& bK, cd& first_state, cd& last_state,
-                                         double* ayn) {
+                                         double* ayn, double* vkeep = nullptr) {
   if constexpr (PH == PH_SUBST) {
     // the neighbours' edge rows may already hold the new state: take the saved copies
     if (A.rhs == nullptr) {
@@ -349,6 +352,18 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
     }
     // (SRC_CNW: the real parts, 1 + tau W, do not change from step to step: the next step takes
     // those of this one)
+  }
+  if (vkeep) {
+    // the resident propagation: the diagonal's imaginary part at any field E is
+    // tau (1/dx^2 + vscale v) + (tau x) E; the two terms per row
+    const double tau = 0.5 * A.dt;
+    const double idx2 = 1.0 / (dx * dx);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const bool ok = row_in<IN>(J + j, G.n);
+      vkeep[j] = ok ? tau * (idx2 + A.vscale * vv[j + 1]) : 0.0;
+      vkeep[M + j] = ok ? tau * xv[j + 1] : 0.0;
+    }
   }
 }
 
@@ -620,19 +635,28 @@ __device__ __forceinline__ void st_coh(cd* p, cd v) {
   __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+struct NoMid {
+  __device__ void operator()(cd&, cd&) const {}
+};
+
 template <int M, int W, int SRC, int PH>
 struct RdSubst {
   static constexpr bool on = cn_src(SRC) && PH != PH_REDUCE && M == 8;
 };
 
 // COH: the slots and edge rows of a PH_REDUCE part are stored device-coherent (st_coh), for a
-// fused pass whose last workgroup solves the reduced system (fuse_reduced_last)
-template <int M, int W, int SRC, int PH, bool IN, bool RDR = false, bool COH = false, typename SM>
+// fused pass whose last workgroup solves the reduced system (fuse_reduced_last).
+// PH_RES: the hand-over of PH_REDUCE, then mid(pJ, pM) (run by the whole workgroup: it waits
+// until every tile's slots are in, solves the reduced system and returns psi at the tile's two
+// joint lines), then the substitution of PH_SUBST.
+template <int M, int W, int SRC, int PH, bool IN, bool RDR = false, bool COH = false, typename SM,
+          typename Mid = NoMid>
 __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, Node* wnode,
                                           double* keep, double kap, int64_t J, int lane, int wave,
                                           cd (&Ar)[M], cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M],
                                           cd bK, cd fst, cd lst, cd (&xo)[M],
-                                          cd* pM_out = nullptr) {
+                                          cd* pM_out = nullptr, const Mid& mid = Mid{}) {
+  constexpr bool HAND = PH == PH_REDUCE || PH == PH_RES;  // the tile hands its slots over
   constexpr int LW = Log2<W>::v;
   // RDR: a Crank-Nicolson first pass reduced in the RD form as well (fewer registers)
   constexpr bool RD = RdSubst<M, W, SRC, PH>::on || RDR;
@@ -642,7 +666,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
     else
       *p = v;
   };
-  if constexpr (PH == PH_REDUCE && cn_src(SRC)) {
+  if constexpr (HAND && cn_src(SRC)) {
     if (A.halo_out) {
       if (wave == 0 && lane == 0) put(A.halo_out + 2 * G.gt, fst);
       if (wave == W - 1 && lane == 63) put(A.halo_out + 2 * G.gt + 1, lst);
@@ -689,7 +713,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
 
   cd pJ = czero(), pM = czero();
   if (wave == 0 && lane == 0) {
-    if constexpr (PH == PH_REDUCE) {
+    if constexpr (HAND) {
       put(A.oU + 3 * G.gt, blk.UA);
       put(A.oU + 3 * G.gt + 1, blk.UC);
       put(A.oU + 3 * G.gt + 2, blk.UD);
@@ -710,6 +734,7 @@ __device__ __forceinline__ void tile_core(const KArgs& A, const Geo& G, SM& sm, 
       pM = csel(G.tile + 1 < G.ntile, nxt, czero());
     }
   }
+  if constexpr (PH == PH_RES) mid(pJ, pM);
   if constexpr (PH != PH_REDUCE) {
     if constexpr (W == 1) {
       tree_down<6>(pJ, pM, wnode, lane);
@@ -756,14 +781,23 @@ __device__ __forceinline__ void check_rows(const KArgs& A, const Geo& G, int64_t
 // wedge) and from the joint line below the lane (pM).  Wavefront 0 has no left neighbour in the
 // tile: its joint row takes the explicit half-step without psi_{J-1}, whose term the reduced
 // system adds (KArgs::ud_halo); at the start of a system that neighbour is zero anyway.
-template <int M, int W, bool IN, int SRC = SRC_CN>
-__device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+// STAGED: the rows xo are already in the staging buffer (left there by store_tile); otherwise
+// they are put there first.
+template <int M, int W, bool IN, int SRC = SRC_CN, bool STAGED = true>
+__device__ __forceinline__ void next_rows(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
                                           cd* buf, int64_t J, int lane, int wave,
                                           const cd (&xo)[M], cd pM, const double* ayn,
-                                          const double* arn = nullptr) {
+                                          const double* arn, double kap, cd (&Ar)[M],
+                                          cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M], cd& bK,
+                                          cd& fst, cd& lst) {
   static_assert(M >= 2, "the next step is reduced in the RD form");
   constexpr bool WA = SRC == SRC_CNW;
   using S = Stage<M>;
+  if constexpr (!STAGED) {
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < M; ++j) buf[S::addr(lane * M + j + 1)] = xo[j];
+  }
   if (lane == 63) sm.wedge[wave] = xo[M - 1];
   __syncthreads();
   if (lane == 0) buf[S::addr(0)] = csel(wave > 0, sm.wedge[wave > 0 ? wave - 1 : 0], czero());
@@ -777,13 +811,10 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
     for (int j = 0; j < M + 2; ++j) vp[j] = csel(J - 1 + j < G.n, vp[j], czero());
   }
   wave_sync();
-  // the rows of the next step: its diagonal came with the first half's loads (ayn; SRC_CNW: the
-  // real parts arn = 1 + tau W are this step's), the right-hand side is the explicit half-step
-  // of cn_rows with the same diagonal
-  const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
-  const double kap = cn_kappa(A.dt, dx);
+  // the rows of the next step: its diagonal's imaginary parts are ayn (SRC_CNW: the real parts
+  // arn = 1 + tau W are this step's), the right-hand side is the explicit half-step of cn_rows
+  // with the same diagonal
   const cd zero = czero();
-  cd Ar[M], Br[M], Cr[M], Dr[M], dummy[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const double w = ayn[j];
@@ -804,12 +835,26 @@ __device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem
                    zero);
     }
   }
-  const cd bK = mk(0.0, row_in<IN>(J + M, G.n) ? -kap : 0.0);
+  bK = mk(0.0, row_in<IN>(J + M, G.n) ? -kap : 0.0);
+  fst = vp[1];
+  lst = vp[M];
+}
+
+template <int M, int W, bool IN, int SRC = SRC_CN>
+__device__ __forceinline__ void fuse_next(const KArgs& A, const Geo& G, TileSmem<M, W>& sm,
+                                          cd* buf, int64_t J, int lane, int wave,
+                                          const cd (&xo)[M], cd pM, const double* ayn,
+                                          const double* arn = nullptr) {
+  const double dx = A.dxs ? A.dxs[G.sys] : A.dx;
+  const double kap = cn_kappa(A.dt, dx);
+  cd Ar[M], Br[M], Cr[M], Dr[M], dummy[M], bK, fst, lst;
+  next_rows<M, W, IN, SRC>(A, G, sm, buf, J, lane, wave, xo, pM, ayn, arn, kap, Ar, Br, Cr, Dr,
+                           bK, fst, lst);
   Node* wnode = reinterpret_cast<Node*>(buf);
   double* keep = reinterpret_cast<double*>(wnode + 64);
   // reduced in the RD form: the diagonal and the right-hand side are all it keeps per row
   tile_core<M, W, SRC, PH_REDUCE, IN, true, true>(A, G, sm, wnode, keep, kap, J, lane, wave, Ar,
-                                                  Br, Cr, Dr, bK, vp[1], vp[M], dummy);
+                                                  Br, Cr, Dr, bK, fst, lst, dummy);
 }
 
 // Everything after the rows of the tile are assembled: level-1 sweeps, nesting, top, SS, store.
@@ -914,6 +959,194 @@ __global__ __launch_bounds__(64 * W, (tile_min_waves<M, PH, SRC>())) void k_tile
   if constexpr (PH == PH_FUSE && cn_src(SRC)) {
     __shared__ int last;
     if (A.inl_sync) fuse_reduced_last<M, W>(A, sm, last);
+  }
+}
+
+// ------------------------------------------------------------ resident propagation
+// Every step of a Crank-Nicolson propagation of one system in one launch.  Workgroup t owns
+// tile t for the whole sequence and keeps its rows in registers: the right-hand side of the RD
+// rows (Table 1 with substitution along them), and per row the two terms of the diagonal, so
+// that after the first loads a step neither reads nor writes the state in memory.  Per step the
+// tile reduces its rows, nested inside the tile as in k_tile, stores its two slots and edge rows
+// device-coherently and raises its flag; every workgroup waits (bounded poll) until all K flags
+// show the step, then solves the reduced system on the K tile joints itself (a whole-system
+// tile of 2 rows per lane in its own LDS, the deferred left-neighbour terms added from the edge
+// rows as in the chained passes), keeps psi at its own two joints, substitutes (SS) and builds
+// the next step's rows from the new state in registers (next_rows).  Slots and edge rows
+// alternate between two buffers by step parity: a tile publishes step k+1 only after every tile
+// has published step k, so after every tile has read step k-1's values.  The state is written
+// once, after the last step.
+struct ResArgs {
+  const double* E;  // field per step (device, nsteps values), or null for a zero field
+  int nsteps;
+  int* flags;       // one per tile: steps published in this launch; zero between launches
+  int* sync;        // [-, -, abort, workgroups out]; zero between launches
+  int spin;         // polls before a wait gives up (sets abort and status bit 4)
+  int64_t bufstep;  // elements between the two parity buffers of oU, oD (3 K) and halo (2 K)
+};
+
+template <int M, int W>
+struct ResSmem {
+  TileSmem<M, W> t;
+  TileSmem<2, W> r;  // the reduced solve
+  cd pj, pm;         // psi at this tile's joint lines
+  int flag;          // broadcast: 2 aborted, 1 last workgroup out
+};
+
+// The step's hand-over and reduced solve; returns false when the launch aborted.
+template <int M, int W>
+__device__ __forceinline__ bool res_exchange(const KArgs& A, const ResArgs& R, ResSmem<M, W>& sm,
+                                             int k, cd& pJ, cd& pM) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int K = (int)A.ntiles;
+  const int t = (int)blockIdx.x;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // this wavefront's slot and edge-row stores have completed
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (wave == 0) {
+    if (lane == 0) __hip_atomic_store(R.flags + t, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int out = 0;
+    for (int it = 0;; ++it) {
+      bool in = true;
+      for (int i = lane; i < K; i += 64)
+        in &= __hip_atomic_load(R.flags + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > k;
+      if (__all(in)) break;
+      const bool ab = __hip_atomic_load(R.sync + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (it >= R.spin || __any(ab)) {  // (wavefront-uniform)
+        if (lane == 0) {
+          atomicExch(R.sync + 2, 1);
+          atomicOr(A.status, 4);
+        }
+        out = 2;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) sm.flag = out;
+  }
+  __syncthreads();
+  if (sm.flag == 2) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  // the reduced system on the tile joints, in this workgroup
+  KArgs B = A;
+  B.sU = A.oU;
+  B.sD = A.oD;
+  B.ud_halo = k > 0 ? A.halo_out : nullptr;  // step 0's rows took both neighbours from memory
+  B.rhs = nullptr;
+  B.dxs = nullptr;
+  Geo G;
+  G.sys = 0;
+  G.tile = 0;
+  G.n = K;
+  G.base = 0;
+  G.cbase = 0;
+  G.es = 1;
+  G.gt = 0;
+  G.ntile = 1;
+  {
+    const int64_t w0 = (int64_t)wave * 64 * 2;
+    const int64_t J = w0 + (int64_t)lane * 2;
+    cd* buf = sm.r.lds[wave];
+    cd Ar[2], Br[2], Cr[2], Dr[2], bK, fst, lst, xo[2];
+    load_rows<2, W, SRC_SLOTS, PH_SINGLE, false>(B, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr,
+                                                  bK, fst, lst);
+    Node* wnode = reinterpret_cast<Node*>(buf);
+    double* keep = reinterpret_cast<double*>(wnode + 64);
+    tile_core<2, W, SRC_SLOTS, PH_SINGLE, false>(B, G, sm.r, wnode, keep, 0.0, J, lane, wave, Ar,
+                                                 Br, Cr, Dr, bK, fst, lst, xo);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (J + j == t) sm.pj = xo[j];
+      if (J + j == t + 1) sm.pm = xo[j];
+    }
+  }
+  __syncthreads();
+  pJ = sm.pj;
+  pM = t + 1 < K ? sm.pm : czero();
+  return true;
+}
+
+template <int M, int W, bool IN>
+__device__ __forceinline__ void resident_run(const KArgs& A, const ResArgs& R, const Geo& G,
+                                             ResSmem<M, W>& sm, int64_t w0, int64_t J, int lane,
+                                             int wave) {
+  cd* buf = sm.t.lds[wave];
+  cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
+  double vk[2 * M];  // per row: tau (1/dx^2 + vscale v), then tau x
+  {
+    KArgs A0 = A;
+    A0.E_mat = A0.E_rhs = R.E ? R.E[0] : 0.0;
+    CnRaw<M, true, false> raw;
+    cn_fetch<M, true, IN, false>(A0, G, w0, lane, raw);
+    cn_build<M, W, PH_REDUCE, true, IN, false>(A0, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr,
+                                               bK, fst, lst, nullptr, vk);
+  }
+  const double kap = cn_kappa(A.dt, A.dx);
+  bool ok = true;
+  for (int k = 0; k < R.nsteps; ++k) {
+    KArgs Ak = A;  // this step's parity buffer of slots and edge rows
+    const int64_t off = (k & 1) ? R.bufstep : 0;
+    Ak.oU = A.oU + 3 * off;
+    Ak.oD = A.oD + 3 * off;
+    Ak.halo_out = A.halo_out + 2 * off;
+    Node* wnode = reinterpret_cast<Node*>(buf);
+    double* keep = reinterpret_cast<double*>(wnode + 64);
+    cd xo[M];
+    cd pM = czero();
+    auto mid = [&](cd& pj, cd& pm) { ok = res_exchange<M, W>(Ak, R, sm, k, pj, pm); };
+    tile_core<M, W, SRC_CN, PH_RES, IN, true, true>(Ak, G, sm.t, wnode, keep, kap, J, lane, wave,
+                                                    Ar, Br, Cr, Dr, bK, fst, lst, xo, &pM, mid);
+    if (!ok) return;
+    if (k + 1 == R.nsteps) {
+      check_rows<M, IN>(A, G, J, lane, xo);
+      store_tile<M, W, SRC_CN, IN>(A, G, sm.t, buf, w0, lane, wave, xo);
+      return;
+    }
+    const double En = R.E ? R.E[k + 1] : 0.0;
+    double ayn[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) ayn[j] = row_in<IN>(J + j, G.n) ? fma(vk[M + j], En, vk[j]) : 0.0;
+    next_rows<M, W, IN, SRC_CN, false>(A, G, sm.t, buf, J, lane, wave, xo, pM, ayn, nullptr, kap,
+                                       Ar, Br, Cr, Dr, bK, fst, lst);
+  }
+}
+
+// One workgroup per tile of T = 64 W M rows of the one system (A.n rows, A.ntiles <= 128 W
+// tiles, unit stride); the host launches it only when every workgroup fits on the GPU at once.
+template <int M, int W>
+__global__ __launch_bounds__(64 * W) void k_resident(KArgs A, ResArgs R) {
+  __shared__ ResSmem<M, W> sm;
+  Geo G;
+  G.sys = 0;
+  G.tile = blockIdx.x;
+  G.n = A.n;
+  G.base = 0;
+  G.cbase = 0;
+  G.es = 1;
+  G.gt = blockIdx.x;
+  G.ntile = A.ntiles;
+  constexpr int64_t T = 64 * W * M;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t w0 = G.tile * T + (int64_t)wave * 64 * M;
+  const int64_t J = w0 + (int64_t)lane * M;
+  if (w0 >= 1 && G.n >= w0 + 64 * M + 1)
+    resident_run<M, W, true>(A, R, G, sm, w0, J, lane, wave);
+  else
+    resident_run<M, W, false>(A, R, G, sm, w0, J, lane, wave);
+  __syncthreads();
+  if (threadIdx.x == 0) sm.flag = atomicAdd(R.sync + 3, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (sm.flag == 1 && wave == 0) {
+    // the last workgroup out: flags and words are ready for the next launch
+    for (int i = lane; i < (int)A.ntiles; i += 64)
+      __hip_atomic_store(R.flags + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) {
+      atomicExch(R.sync + 2, 0);
+      atomicExch(R.sync + 3, 0);
+    }
   }
 }
 
