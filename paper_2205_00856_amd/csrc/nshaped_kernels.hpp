@@ -368,7 +368,16 @@ __device__ __forceinline__ void cn_build(const KArgs& A, const Geo& G, cd* buf, 
 }
 
 // ------------------------------------------------------------------ row assembly per source
-template <int M, int W, int SRC, int PH, bool IN>
+// A load at the level of the memory system shared by all XCDs (a relaxed atomic at device
+// scope), for values another workgroup of the same launch stored there (st_coh).
+__device__ __forceinline__ cd ld_coh(const cd* p) {
+  return mk(__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+            __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// CL (SRC_SLOTS): the slots, edge rows and joint values are read with ld_coh (the resident
+// propagation reads them in the launch that stores them).
+template <int M, int W, int SRC, int PH, bool IN, bool CL = false>
 __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf, int64_t w0,
                                           int64_t J, int lane, int wave, cd (&Ar)[M],
                                           cd (&Br)[M], cd (&Cr)[M], cd (&Dr)[M], cd& bK,
@@ -419,28 +428,34 @@ __device__ __forceinline__ void load_rows(const KArgs& A, const Geo& G, cd* buf,
                                      first_state, last_state, ayn);
   } else {  // SRC_SLOTS: row k of the reduced system = U slot of tile k + D slot of tile k-1
     const cd zero = czero();
+    auto ld = [](const cd* p) {
+      if constexpr (CL)
+        return ld_coh(p);
+      else
+        return *p;
+    };
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const int64_t r = J + j;
       const bool ok = r < n;
       const int64_t g = G.base + (ok ? r : n - 1);
       const int64_t gp = (ok && r > 0) ? g - 1 : g;
-      const cd ua = A.sU[3 * g], uc = A.sU[3 * g + 1], ud = A.sU[3 * g + 2];
-      const cd db = A.sD[3 * gp], da = A.sD[3 * gp + 1], dd = A.sD[3 * gp + 2];
+      const cd ua = ld(A.sU + 3 * g), uc = ld(A.sU + 3 * g + 1), ud = ld(A.sU + 3 * g + 2);
+      const cd db = ld(A.sD + 3 * gp), da = ld(A.sD + 3 * gp + 1), dd = ld(A.sD + 3 * gp + 2);
       const bool hasp = ok && r > 0;
       Ar[j] = csel(ok, cadd(ua, csel(hasp, da, zero)), mk(1.0, 0.0));
       Br[j] = csel(hasp, db, zero);
       Cr[j] = csel(ok && r < n - 1, uc, zero);
       Dr[j] = csel(ok, cadd(ud, csel(hasp, dd, zero)), zero);
       if (A.ud_halo) {
-        const cd h = A.ud_halo[2 * gp + 1];
+        const cd h = ld(A.ud_halo + 2 * gp + 1);
         const double kap = cn_kappa(A.dt, A.dxs ? A.dxs[G.sys] : A.dx);
         Dr[j] = cadd(Dr[j], csel(hasp, mk(-kap * h.y, kap * h.x), zero));
       }
     }
     const int64_t K = J + M;
     const int64_t gk = G.base + (K < n ? K - 1 : 0);
-    const cd t = A.sD[3 * gk];
+    const cd t = ld(A.sD + 3 * gk);
     bK = csel(K < n, t, zero);
     first_state = last_state = zero;
   }
@@ -1028,8 +1043,7 @@ __device__ __forceinline__ bool res_exchange(const KArgs& A, const ResArgs& R, R
   }
   __syncthreads();
   if (sm.flag == 2) return false;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  // the reduced system on the tile joints, in this workgroup
+  // the reduced system on the tile joints, in this workgroup (its values read device-coherent)
   KArgs B = A;
   B.sU = A.oU;
   B.sD = A.oD;
@@ -1050,8 +1064,8 @@ __device__ __forceinline__ bool res_exchange(const KArgs& A, const ResArgs& R, R
     const int64_t J = w0 + (int64_t)lane * 2;
     cd* buf = sm.r.lds[wave];
     cd Ar[2], Br[2], Cr[2], Dr[2], bK, fst, lst, xo[2];
-    load_rows<2, W, SRC_SLOTS, PH_SINGLE, false>(B, G, buf, w0, J, lane, wave, Ar, Br, Cr, Dr,
-                                                  bK, fst, lst);
+    load_rows<2, W, SRC_SLOTS, PH_SINGLE, false, true>(B, G, buf, w0, J, lane, wave, Ar, Br, Cr,
+                                                        Dr, bK, fst, lst);
     Node* wnode = reinterpret_cast<Node*>(buf);
     double* keep = reinterpret_cast<double*>(wnode + 64);
     tile_core<2, W, SRC_SLOTS, PH_SINGLE, false>(B, G, sm.r, wnode, keep, 0.0, J, lane, wave, Ar,
