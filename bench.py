@@ -873,8 +873,9 @@ def uneven_timing(torch, np, cn, workloads, dev):
 
 def absorbing(torch, np, cn, workloads, dev):
     """Steps with an absorbing potential (non-Hermitian H) through the fused kernels: the plain
-    1D workload with a ramp at both walls, 200 steps in a graph, with the oracle's 200 steps for
-    parity; and 2^24 rows, 10 steps per call, beside the materialised form."""
+    1D workload with a ramp at both walls, 200 steps in a graph and as one resident launch, with
+    the oracle's 200 steps for parity; and 2^24 rows, 10 steps per call, beside the materialised
+    form."""
     res = {}
     w = workloads.absorbing_1d()
     psi0 = torch.from_numpy(w["psi0"]).to(dev)
@@ -893,8 +894,16 @@ def absorbing(torch, np, cn, workloads, dev):
     torch.cuda.synchronize()
     psi200 = psi.cpu().numpy()
     med = float(np.median(timed_events(torch, gr.replay, 5)))
+    # the same 200 steps as one resident launch
+    pr = psi0.clone()
+    cn.propagate_resident(pr, V, w["dx"], w["dt"], w["steps"], W=W)
+    torch.cuda.synchronize()
+    psi200_res = pr.cpu().numpy()
+    med_res = float(np.median(timed_events(
+        torch, lambda: cn.propagate_resident(pr, V, w["dx"], w["dt"], w["steps"], W=W), 5)))
     n0 = float(np.sum(np.abs(w["psi0"]) ** 2))
     res["1d_65536"] = {"steps": w["steps"], "us_per_step_graph": med * 1e3 / w["steps"],
+                       "us_per_step_resident": med_res * 1e3 / w["steps"],
                        "unknowns_per_s": w["n"] * w["steps"] / (med * 1e-3),
                        "norm_left_after_200": float(np.sum(np.abs(psi200) ** 2)) / n0}
     ref = {}
@@ -905,7 +914,8 @@ def absorbing(torch, np, cn, workloads, dev):
         w["n"] * w["steps"], res["1d_65536"]["unknowns_per_s"])
     if "x" in ref:
         res["1d_65536"]["parity_rel_l2_200"] = rel_l2(psi200, ref["x"])
-    del psi, psi0, V, W
+        res["1d_65536"]["parity_rel_l2_200_resident"] = rel_l2(psi200_res, ref["x"])
+    del psi, psi0, V, W, pr
     res["2^24"] = absorbing_large(torch, np, cn, workloads, dev)
     return res
 

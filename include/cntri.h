@@ -235,7 +235,8 @@ cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_ope
  * memory.  Same result as cn_propagate without checkpoints, up to rounding.
  *   L: one contiguous system (batch 1, elem_stride 1, no offsets, no shared coefficients or
  *      levels; rows_per_thread 0 or 8; partition 0, or 512, 1024 or 2048 rows per tile).
- *   op: real potential (no absorb), one dx (no dx_per_system).
+ *   op: one dx (no dx_per_system); a real potential, or one with an absorbing part
+ *       (op->absorb, the potential V - iW, as in cn_propagate).
  *   E: HOST, nsteps field values or null (zero field); uploaded with an asynchronous copy on
  *      the stream (so E != null cannot be captured into a graph: CN_ERR_UNSUPPORTED).
  *   psi: DEVICE, n complex values, updated in place.

@@ -322,20 +322,20 @@ def propagate(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0, dx_per_sy
 
 
 def propagate_resident(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0,
-                       layout: Optional[Layout] = None):
+                       layout: Optional[Layout] = None, W=None):
     """nsteps CN steps of one system in place on psi in ONE launch (cn_propagate_resident).
     Raises CnError(CN_ERR_UNSUPPORTED) for layouts or operators it does not take (then
     propagate is the call); get_status raises CnError(CN_ERR_WAIT_TIMEOUT) after a launch whose
-    workgroups could not all run at once."""
+    workgroups could not all run at once.  W: absorbing potential (the potential is V - iW)."""
     L = _layout_for(psi, layout)
     _need(psi, torch.complex128, "psi", L.span())
-    _check_op(L, V, xgrid, None, None)
+    _check_op(L, V, xgrid, None, W)
     Earr = None
     if E is not None:
         Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
         if Earr.shape[0] < nsteps:
             raise ValueError("E needs one value per step")
-    op = _operator(V, dx, dt, xgrid, v_scale, None, None)
+    op = _operator(V, dx, dt, xgrid, v_scale, None, W)
     h = handle(psi.device.index)
     Lc = L.c()
     Ep = None if Earr is None else Earr.ctypes.data_as(ctypes.c_void_p)

@@ -1739,29 +1739,30 @@ int resident_spin() {
   }
   return 1 << 22;
 }
-int64_t resident_capacity(int ci) {
+// wa: the kernel for a potential with an absorbing part
+int64_t resident_capacity(int ci, int wa) {
   static std::mutex mu;
-  static int64_t cap[nsk::kNumResCfg] = {};
+  static int64_t cap[nsk::kNumResCfg][2] = {};
   std::lock_guard<std::mutex> lock(mu);
-  if (cap[ci] == 0) {
+  if (cap[ci][wa] == 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, nsk::tables().res[ci],
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, nsk::tables().res[ci][wa],
                                                      64 * nsk::kResCfgs[ci].W, 0) != hipSuccess ||
         per_cu < 1) {
       (void)hipGetLastError();
       per_cu = 0;
     }
-    cap[ci] = per_cu > 0 ? (int64_t)per_cu * num_cus() : -1;
+    cap[ci][wa] = per_cu > 0 ? (int64_t)per_cu * num_cus() : -1;
   }
-  return cap[ci];
+  return cap[ci][wa];
 }
-int resident_cfg(int64_t n, int64_t partition) {
+int resident_cfg(int64_t n, int64_t partition, int wa) {
   for (const int64_t lim : {(int64_t)128, (int64_t)0}) {
     for (int ci = 0; ci < nsk::kNumResCfg; ++ci) {
       const Cfg c = nsk::kResCfgs[ci];
       if (partition > 0 && c.T() != partition) continue;
       const int64_t K = (n + c.T() - 1) / c.T();
-      if (K <= (lim ? lim : 128 * c.W) && K <= resident_capacity(ci)) return ci;
+      if (K <= (lim ? lim : 128 * c.W) && K <= resident_capacity(ci, wa)) return ci;
     }
   }
   return -1;
@@ -1776,14 +1777,15 @@ cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_oper
   int64_t rows = 0, span = 0;
   st = validate(L, rows, span);
   if (st != CN_OK) return st;
-  if (!resident_enabled() || op->absorb || op->dx_per_system || L->offsets || L->batch != 1 ||
+  if (!resident_enabled() || op->dx_per_system || L->offsets || L->batch != 1 ||
       L->elem_stride != 1 || L->shared_coefficients || L->levels ||
       (L->rows_per_thread && L->rows_per_thread != 8))
     return CN_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const bool cap = capturing(s);
   if (E && cap) return CN_ERR_UNSUPPORTED;  // the field is uploaded by a host copy
-  const int ci = resident_cfg(L->n, L->partition);
+  const int wa = op->absorb ? 1 : 0;
+  const int ci = resident_cfg(L->n, L->partition, wa);
   if (ci < 0) return CN_ERR_UNSUPPORTED;
   if (nsteps == 0) return CN_OK;
   const int64_t T = nsk::kResCfgs[ci].T(), K = (L->n + T - 1) / T;
@@ -1815,6 +1817,7 @@ cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_oper
   a.vscale = op->v_scale;
   a.dx = op->dx;
   a.dt = op->dt;
+  a.Wabs = op->absorb;
   a.wscale = 1.0;
   a.oU = (cd*)(w + o_oU);
   a.oD = (cd*)(w + o_oD);
@@ -1828,7 +1831,8 @@ cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_oper
   r.spin = resident_spin();
   r.bufstep = K;
   void* params[] = {&a, &r};
-  if (hipLaunchKernel(nsk::tables().res[ci], dim3((unsigned)K), dim3(64 * nsk::kResCfgs[ci].W),
+  if (hipLaunchKernel(nsk::tables().res[ci][wa], dim3((unsigned)K),
+                      dim3(64 * nsk::kResCfgs[ci].W),
                       params, 0, s) != hipSuccess)
     return CN_ERR_HIP;
   return CN_OK;

@@ -1,5 +1,6 @@
 // Resident propagation kernels (k_resident): every step of a Crank-Nicolson propagation of one
-// system in one launch, for the tile configurations of kResCfgs.
+// system in one launch, for the tile configurations of kResCfgs, with real potentials and with
+// an absorbing part.
 #include "kern_table.hpp"
 #include "nshaped_kernels.hpp"
 
@@ -8,7 +9,8 @@ namespace {
 template <int I>
 void reg_one(Tables& t) {
   constexpr int M = kResCfgs[I].M, W = kResCfgs[I].W;
-  t.res[I] = (const void*)&nsd::k_resident<M, W>;
+  t.res[I][0] = (const void*)&nsd::k_resident<M, W, nsd::SRC_CN>;
+  t.res[I][1] = (const void*)&nsd::k_resident<M, W, nsd::SRC_CNW>;
 }
 template <int... I>
 void reg_range(Tables& t, std::integer_sequence<int, I...>) {

@@ -46,7 +46,7 @@ struct Tables {
   const void* cols[kNumColCfg][kNumSrc][3];
   const void* mrhs[kNumCfg][3];  // one matrix, several right-hand sides (explicit source)
   const void* aux[kNumAux];
-  const void* res[kNumResCfg];   // resident propagation of one system
+  const void* res[kNumResCfg][2];  // resident propagation of one system: [SRC_CN, SRC_CNW]
 };
 
 // The one table of the library (cntri.hip), filled once by the registration functions below.

@@ -1082,20 +1082,26 @@ __device__ __forceinline__ bool res_exchange(const KArgs& A, const ResArgs& R, R
   return true;
 }
 
-template <int M, int W, bool IN>
+template <int M, int W, int SRC, bool IN>
 __device__ __forceinline__ void resident_run(const KArgs& A, const ResArgs& R, const Geo& G,
                                              ResSmem<M, W>& sm, int64_t w0, int64_t J, int lane,
                                              int wave) {
+  constexpr bool WA = SRC == SRC_CNW;
   cd* buf = sm.t.lds[wave];
   cd Ar[M], Br[M], Cr[M], Dr[M], bK, fst, lst;
-  double vk[2 * M];  // per row: tau (1/dx^2 + vscale v), then tau x
+  double vk[2 * M];     // per row: tau (1/dx^2 + vscale v), then tau x
+  double arn[WA ? M : 1];  // SRC_CNW: the diagonal's real parts 1 + tau W, the same every step
   {
     KArgs A0 = A;
     A0.E_mat = A0.E_rhs = R.E ? R.E[0] : 0.0;
-    CnRaw<M, true, false> raw;
-    cn_fetch<M, true, IN, false>(A0, G, w0, lane, raw);
-    cn_build<M, W, PH_REDUCE, true, IN, false>(A0, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr,
-                                               bK, fst, lst, nullptr, vk);
+    CnRaw<M, true, WA> raw;
+    cn_fetch<M, true, IN, WA>(A0, G, w0, lane, raw);
+    cn_build<M, W, PH_REDUCE, true, IN, WA>(A0, G, buf, w0, J, lane, wave, raw, Ar, Br, Cr, Dr,
+                                            bK, fst, lst, nullptr, vk);
+  }
+  if constexpr (WA) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) arn[j] = Ar[j].x;
   }
   const double kap = cn_kappa(A.dt, A.dx);
   bool ok = true;
@@ -1110,26 +1116,27 @@ __device__ __forceinline__ void resident_run(const KArgs& A, const ResArgs& R, c
     cd xo[M];
     cd pM = czero();
     auto mid = [&](cd& pj, cd& pm) { ok = res_exchange<M, W>(Ak, R, sm, k, pj, pm); };
-    tile_core<M, W, SRC_CN, PH_RES, IN, true, true>(Ak, G, sm.t, wnode, keep, kap, J, lane, wave,
-                                                    Ar, Br, Cr, Dr, bK, fst, lst, xo, &pM, mid);
+    tile_core<M, W, SRC, PH_RES, IN, true, true>(Ak, G, sm.t, wnode, keep, kap, J, lane, wave, Ar,
+                                                 Br, Cr, Dr, bK, fst, lst, xo, &pM, mid);
     if (!ok) return;
     if (k + 1 == R.nsteps) {
       check_rows<M, IN>(A, G, J, lane, xo);
-      store_tile<M, W, SRC_CN, IN>(A, G, sm.t, buf, w0, lane, wave, xo);
+      store_tile<M, W, SRC, IN>(A, G, sm.t, buf, w0, lane, wave, xo);
       return;
     }
     const double En = R.E ? R.E[k + 1] : 0.0;
     double ayn[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) ayn[j] = row_in<IN>(J + j, G.n) ? fma(vk[M + j], En, vk[j]) : 0.0;
-    next_rows<M, W, IN, SRC_CN, false>(A, G, sm.t, buf, J, lane, wave, xo, pM, ayn, nullptr, kap,
-                                       Ar, Br, Cr, Dr, bK, fst, lst);
+    next_rows<M, W, IN, SRC, false>(A, G, sm.t, buf, J, lane, wave, xo, pM, ayn,
+                                    WA ? arn : nullptr, kap, Ar, Br, Cr, Dr, bK, fst, lst);
   }
 }
 
 // One workgroup per tile of T = 64 W M rows of the one system (A.n rows, A.ntiles <= 128 W
 // tiles, unit stride); the host launches it only when every workgroup fits on the GPU at once.
-template <int M, int W>
+// SRC: SRC_CN, or SRC_CNW for a potential with an absorbing part (A.Wabs, A.wscale).
+template <int M, int W, int SRC>
 __global__ __launch_bounds__(64 * W) void k_resident(KArgs A, ResArgs R) {
   __shared__ ResSmem<M, W> sm;
   Geo G;
@@ -1147,9 +1154,9 @@ __global__ __launch_bounds__(64 * W) void k_resident(KArgs A, ResArgs R) {
   const int64_t w0 = G.tile * T + (int64_t)wave * 64 * M;
   const int64_t J = w0 + (int64_t)lane * M;
   if (w0 >= 1 && G.n >= w0 + 64 * M + 1)
-    resident_run<M, W, true>(A, R, G, sm, w0, J, lane, wave);
+    resident_run<M, W, SRC, true>(A, R, G, sm, w0, J, lane, wave);
   else
-    resident_run<M, W, false>(A, R, G, sm, w0, J, lane, wave);
+    resident_run<M, W, SRC, false>(A, R, G, sm, w0, J, lane, wave);
   __syncthreads();
   if (threadIdx.x == 0) sm.flag = atomicAdd(R.sync + 3, 1) == (int)gridDim.x - 1;
   __syncthreads();

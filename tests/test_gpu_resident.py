@@ -4,7 +4,8 @@ at each step) against the CPU oracle stepping one step at a time, and against cn
 
 Tolerance: relative L2 <= 1e-11 (FP64 on both sides; rounding only).  Cases: the plain 1D
 workload's 200 steps, ragged sizes from one row to 2^20 rows with a field (every tile
-configuration: 512, 1024 and 2048 rows), a captured graph replayed against the eager result,
+configuration: 512, 1024 and 2048 rows), the absorbing workload and absorbing ramps with a
+field (the potential V - iW), a captured graph replayed against the eager result,
 the layouts and operators it refuses, and a wait that gives up (forced from the host with a
 poll bound of zero), after which the next launch is correct again.
 """
@@ -84,6 +85,40 @@ def test_resident_field_against_oracle(gpu, oracle_mod, n, part):
     assert cn.get_status() == 0
 
 
+def test_resident_absorbing_workload(gpu, oracle_mod):
+    """The absorbing workload (packet moving into the ramp at the right wall): 200 steps in one
+    launch against the oracle's steps with the potential V - iW, the norm falling."""
+    torch, cn = gpu
+    w = workloads.absorbing_1d()
+    log("resident absorbing", w["n"], w["steps"])
+    ref = oracle_mod.cn_propagate(w["psi0"], w["V"], w["dx"], w["dt"], w["steps"], W=w["W"])
+    tV, tpsi, tW = to_dev(torch, w["V"], w["psi0"], w["W"])
+    cn.propagate_resident(tpsi, tV, w["dx"], w["dt"], w["steps"], W=tW)
+    out = tpsi.cpu().numpy()
+    assert rel(out, ref) <= TOL
+    assert np.sum(np.abs(out) ** 2) < 0.5 * np.sum(np.abs(w["psi0"]) ** 2)
+    assert cn.get_status() == 0
+
+
+@pytest.mark.parametrize("n", [37, 100_003, 300_007])
+def test_resident_absorbing_with_field(gpu, oracle_mod, n):
+    """An absorbing ramp and x E_k together: 6 steps against the oracle (tiles of 512, 1024
+    and 2048 rows)."""
+    torch, cn = gpu
+    dx, dt, steps = 0.05, 0.01, 6
+    inp = workloads.random_cn(n, 23 + n % 61, dx, dt)
+    W = workloads.absorber(n, 0.2, 3.0)
+    xg = workloads.grid_1d(n, dx)
+    E = np.random.default_rng(n % 777).normal(0.0, 0.05, steps)
+    ref = inp["psi"]
+    for k in range(steps):
+        ref = oracle_mod.cn_step(ref, inp["V"], dx, dt, xg, E[k], W=W)
+    tV, tpsi, tW, txg = to_dev(torch, inp["V"], inp["psi"], W, xg)
+    cn.propagate_resident(tpsi, tV, dx, dt, steps, E=E, xgrid=txg, W=tW)
+    assert rel(tpsi.cpu().numpy(), ref) <= TOL
+    assert cn.get_status() == 0
+
+
 def test_resident_matches_chained_propagation(gpu):
     """The same 60 steps through cn_propagate (fused passes) and in one launch."""
     torch, cn = gpu
@@ -152,8 +187,6 @@ def test_resident_refusals(gpu):
     assert call(cn.Layout.contiguous(n, 1, rows_per_thread=4), op) == U
     assert call(cn.Layout.contiguous(n, 1, levels=1), op) == U
     assert call(cn.Layout.contiguous(1 << 22, 1), op) == U  # more tiles than one solve takes
-    tW = torch.zeros(n, dtype=torch.float64, device="cuda")
-    assert call(cn.Layout.contiguous(n, 1), _operator(tV, dx, dt, W=tW)) == U  # absorbing
     tdx = torch.full((1,), dx, dtype=torch.float64, device="cuda")
     assert call(cn.Layout.contiguous(n, 1), _operator(tV, 0.0, dt, dx_per_system=tdx)) == U
     assert call(cn.Layout.contiguous(n, 1), op, steps=-1) == _lib.CN_ERR_INVALID_ARG
