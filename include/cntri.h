@@ -238,7 +238,9 @@ cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_ope
  *   op: one dx (no dx_per_system); a real potential, or one with an absorbing part
  *       (op->absorb, the potential V - iW, as in cn_propagate).
  *   E: HOST, nsteps field values or null (zero field); uploaded with an asynchronous copy on
- *      the stream (so E != null cannot be captured into a graph: CN_ERR_UNSUPPORTED).
+ *      the stream (so E != null cannot be captured into a graph: CN_ERR_UNSUPPORTED).  A
+ *      launch without a field can be captured after cn_reserve of the layout (or one call
+ *      outside capture), which sizes the handle's buffer for it.
  *   psi: DEVICE, n complex values, updated in place.
  * CN_ERR_UNSUPPORTED also when the system needs more tiles than fit the GPU at once or than the
  * reduced solve of one workgroup takes (128 W joints: up to 2^20 rows), or when CN_RESIDENT=0

@@ -1500,8 +1500,16 @@ cn_status cn_destroy(cn_handle_t h) {
   return CN_OK;
 }
 
+namespace {
+cn_status reserve_resident(cn_handle_t h, const cn_layout* L);
+}
+
 cn_status cn_reserve(cn_handle_t h, const cn_layout* L) {
   if (!h) return CN_ERR_INVALID_ARG;
+  {
+    const cn_status st = reserve_resident(h, L);
+    if (st != CN_OK) return st;
+  }
   Plan* P = nullptr;
   size_t ws2 = 0;  // the second workspace of the reverse mode's fused chain
   for (int src : {nsd::SRC_EXPL, nsd::SRC_EXPL_CT, nsd::SRC_CN, nsd::SRC_CNW, nsd::SRC_LCOUP}) {
@@ -1767,6 +1775,49 @@ int resident_cfg(int64_t n, int64_t partition, int wa) {
   }
   return -1;
 }
+// Bytes of the resident propagation's buffer for K tiles (and nsteps field values): a flag per
+// tile (a fixed area for the most tiles any configuration takes, zero between launches), then
+// two parity buffers each of slots (3 + 3 per tile) and edge rows (2 per tile), then the field.
+constexpr int64_t kResMaxTiles = 128 * 4;
+struct ResLayout {
+  size_t o_oU, o_oD, o_h, o_E;
+  ResLayout(int64_t K)
+      : o_oU(kResMaxTiles * sizeof(int)),
+        o_oD(o_oU + 6 * K * sizeof(cd)),
+        o_h(o_oD + 6 * K * sizeof(cd)),
+        o_E(o_h + 4 * K * sizeof(cd)) {}
+};
+
+// A layout the resident propagation takes (either potential kind), and its tile configuration.
+bool resident_layout(const cn_layout* L, int wa, int* ci) {
+  int64_t rows = 0, span = 0;
+  if (validate(L, rows, span) != CN_OK) return false;
+  if (!resident_enabled() || L->offsets || L->batch != 1 || L->elem_stride != 1 ||
+      L->shared_coefficients || L->levels || (L->rows_per_thread && L->rows_per_thread != 8))
+    return false;
+  *ci = resident_cfg(L->n, L->partition, wa);
+  return *ci >= 0;
+}
+
+cn_status grow_resident(cn_handle_t h, size_t need) {
+  if (need <= h->res_size) return CN_OK;
+  const cn_status st = regrow(h, &h->res, &h->res_size, need);
+  if (st != CN_OK) return st;
+  HIP_TRY(hipMemset(h->res, 0, need));  // the flags start at zero (never inside a capture)
+  return CN_OK;
+}
+
+// cn_reserve: the buffer of a resident propagation without a field on this layout
+cn_status reserve_resident(cn_handle_t h, const cn_layout* L) {
+  for (int wa = 0; wa < 2; ++wa) {
+    int ci = -1;
+    if (!resident_layout(L, wa, &ci)) continue;
+    const int64_t T = nsk::kResCfgs[ci].T(), K = (L->n + T - 1) / T;
+    const cn_status st = grow_resident(h, ResLayout(K).o_E);
+    if (st != CN_OK) return st;
+  }
+  return CN_OK;
+}
 }  // namespace
 
 cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_operator* op,
@@ -1777,31 +1828,22 @@ cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_oper
   int64_t rows = 0, span = 0;
   st = validate(L, rows, span);
   if (st != CN_OK) return st;
-  if (!resident_enabled() || op->dx_per_system || L->offsets || L->batch != 1 ||
-      L->elem_stride != 1 || L->shared_coefficients || L->levels ||
-      (L->rows_per_thread && L->rows_per_thread != 8))
-    return CN_ERR_UNSUPPORTED;
+  const int wa = op->absorb ? 1 : 0;
+  int ci = -1;
+  if (op->dx_per_system || !resident_layout(L, wa, &ci)) return CN_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const bool cap = capturing(s);
   if (E && cap) return CN_ERR_UNSUPPORTED;  // the field is uploaded by a host copy
-  const int wa = op->absorb ? 1 : 0;
-  const int ci = resident_cfg(L->n, L->partition, wa);
-  if (ci < 0) return CN_ERR_UNSUPPORTED;
   if (nsteps == 0) return CN_OK;
   const int64_t T = nsk::kResCfgs[ci].T(), K = (L->n + T - 1) / T;
-  // workspace: a flag per tile (a fixed area for the most tiles any configuration takes, zero
-  // between launches), then two parity buffers each of slots (3 + 3 per tile) and edge rows
-  // (2 per tile), then the field
-  constexpr int64_t kMaxTiles = 128 * 4;
-  const size_t o_oU = kMaxTiles * sizeof(int), o_oD = o_oU + 6 * K * sizeof(cd),
-               o_h = o_oD + 6 * K * sizeof(cd), o_E = o_h + 4 * K * sizeof(cd);
+  const ResLayout RL(K);
+  const size_t o_oU = RL.o_oU, o_oD = RL.o_oD, o_h = RL.o_h, o_E = RL.o_E;
   const size_t need = o_E + (E ? (size_t)nsteps * sizeof(double) : 0);
   if (cap) h->captured = true;
   if (need > h->res_size) {
     if (cap) return CN_ERR_NOT_RESERVED;
-    st = regrow(h, &h->res, &h->res_size, need);
+    st = grow_resident(h, need);
     if (st != CN_OK) return st;
-    HIP_TRY(hipMemset(h->res, 0, need));  // the flags start at zero (not inside a capture)
   }
   char* w = (char*)h->res;
   if (E) HIP_TRY(hipMemcpyAsync(w + o_E, E, nsteps * sizeof(double), hipMemcpyHostToDevice, s));

@@ -163,6 +163,48 @@ def test_resident_graph_replays(gpu):
     assert cn.get_status() == 0
 
 
+def test_resident_capture_after_reserve(gpu):
+    """On a fresh handle, cn_reserve of the layout sizes the resident buffer, so the first call
+    can be a captured one; the replays equal eager steps."""
+    torch, cn = gpu
+    from paper_2205_00856_amd import _lib
+    from paper_2205_00856_amd.api import _operator
+
+    lib = _lib.lib()
+    n, dx, dt, steps = 100_003, 0.1, 0.02, 12
+    inp = workloads.random_cn(n, 29, dx, dt)
+    tV, p0 = to_dev(torch, inp["V"], inp["psi"])
+    want = p0.clone()
+    cn.propagate_resident(want, tV, dx, dt, steps)
+    torch.cuda.synchronize()
+    h = ctypes.c_void_p()
+    assert lib.cn_create(ctypes.byref(h), 0) == _lib.CN_OK
+    try:
+        Lc = cn.Layout.contiguous(n, 1).c()
+        op = _operator(tV, dx, dt)
+        assert lib.cn_reserve(h, ctypes.byref(Lc)) == _lib.CN_OK
+        psi = p0.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            st = lib.cn_propagate_resident(h, ctypes.byref(Lc), ctypes.byref(op), steps, None,
+                                           ctypes.c_void_p(psi.data_ptr()),
+                                           ctypes.c_void_p(side.cuda_stream))
+        assert st == _lib.CN_OK
+        for _ in range(2):
+            psi.copy_(p0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert rel(psi.cpu().numpy(), want.cpu().numpy()) <= 1e-14
+        assert lib.cn_get_status(h, None) == _lib.CN_OK
+    finally:
+        torch.cuda.synchronize()
+        lib.cn_destroy(h)
+
+
 def test_resident_refusals(gpu):
     torch, cn = gpu
     from paper_2205_00856_amd import _lib
