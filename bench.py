@@ -356,15 +356,10 @@ def large_system(torch, np, cn, dev, sweep=True, oracle_parity=True):
     parts = (0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384) if sweep else (0,)
     x_auto = None
     for T in parts:
-        if T in (64, 8192, 16384):
-            # the first-level partition of a launch is one workgroup's tile of T = 64 W M rows,
-            # with M rows per lane held in registers (2 <= M <= 16) and W <= 16 wavefronts
-            rows.append({"partition": T, "status": "unsupported",
-                         "why": "a tile of 64 rows would leave each lane one row (no interior "
-                                "rows to reduce); 8192 and 16384 rows of a, b, c, d (64 B each) "
-                                "are 0.5 and 1 MiB, beyond one CU's 512 KiB of registers"})
-            continue
-        M = 2 if T == 128 else (0 if T == 0 else 4)
+        # 64: one row per lane (every block a joint row); 8192 and 16384: chunked partitions
+        # (their rows do not fit one workgroup's registers; the second pass reads each chunk
+        # twice, 208 B per unknown instead of 144)
+        M = 2 if T == 128 else (0 if T in (0, 64, 8192, 16384) else 4)
         L = cn.Layout.contiguous(N, 1, partition=T, rows_per_thread=M)
         cn.solve(a, b, c, d, out=x, layout=L)
         if T == 0:

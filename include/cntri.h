@@ -76,7 +76,13 @@ typedef struct {
   int64_t batch_stride;
   const int64_t* offsets;
   int32_t partition;       /* rows per first-level partition (one workgroup tile); a power
-                              of two in [32, 16384]; 0 = automatic.  Uneven batches: 0 =
+                              of two in [32, 16384]; 0 = automatic.  Tiles exist for 64 to
+                              4096 rows (64: one row per lane, explicit solves only); the
+                              explicit solve of uniform batches also takes 8192 and 16384,
+                              partitions of 2 or 4 chunks of 4096 rows that one workgroup
+                              reduces in turn (its second pass reads each chunk twice);
+                              sizes without tiles for the call's source return
+                              CN_ERR_UNSUPPORTED.  Uneven batches: 0 =
                               one launch per length class for systems of up to 4096 rows
                               and two passes over 2048-row tiles for longer ones; > 0 = one
                               persistent launch over all systems with that tile            */

@@ -79,6 +79,12 @@ int find_cfg(int64_t T, int M) {
 
 constexpr int64_t kSingleMax = 4096;  // largest tile that solves a whole system in one pass
 
+// First-level partitions of the explicit solve beyond one workgroup's tile: chunks of 4096 rows
+// (k_tile_chunk), 2 for 8192 rows and 4 for 16384; 0 for other sizes.
+int chunks_of(int64_t partition) {
+  return partition == 8192 ? 2 : partition == 16384 ? 4 : 0;
+}
+
 // persistent launch for uneven batches (CN_PERSIST=0 turns it off)
 bool persist_enabled() {
   static const bool on = [] {
@@ -238,6 +244,7 @@ int multi_cfg(int64_t n, int64_t batch, const Knobs& k, int level, int src) {
     if (ci < 0) ci = find_cfg(k.partition, 4);
     if (ci < 0) ci = find_cfg(k.partition, 8);
     if (ci < 0) ci = find_cfg(k.partition, 2);
+    if (ci < 0) ci = find_cfg(k.partition, 1);
     return ci;
   }
   // Crank-Nicolson lines with enough rows for 512 tiles of 2048: 8 rows per lane, whose
@@ -437,6 +444,36 @@ void plan_level(Builder& B, std::vector<Launch>& L, const BatchDesc& bd, int src
       snprintf(line, sizeof(line), "L%d single %s n=%lld batch=%lld; ", level, cfg_str(ci).c_str(),
                (long long)n, (long long)batch);
       B.desc += line;
+      return;
+    }
+    // an explicit partition of 8192 or 16384 rows: chunked partitions (two-pass, the second
+    // pass reading each chunk twice)
+    if (level == 1 && src == nsd::SRC_EXPL && chunks_of(kn.partition) > 0 && !kn.shared) {
+      const int C = chunks_of(kn.partition);
+      const int ci = find_cfg(4096, 8);
+      const int64_t T = kn.partition;
+      const int64_t K = (n + T - 1) / T, G = K * batch;
+      const int64_t oU = B.add_ws(3 * G * sizeof(cd)), oD = B.add_ws(3 * G * sizeof(cd));
+      const int64_t oP = B.add_ws(G * sizeof(cd));
+      KArgs a = base;
+      a.n = n;
+      a.ntiles = K;
+      a.es = bd.es;
+      a.bs = bd.bs;
+      snprintf(line, sizeof(line), "L%d multi T=%lld(%d chunks of T=4096(M=8,W=8)) n=%lld "
+               "batch=%lld tiles=%lld; ", level, (long long)T, C, (long long)n,
+               (long long)batch, (long long)K);
+      B.desc += line;
+      add_launch(L, ci, src, nsd::PH_REDUCE, dim3((unsigned)K, (unsigned)batch), level, a);
+      L.back().fn = nsk::tables().chunk[C == 4][0];
+      set_common(L.back());
+      L.back().o_oU = oU;
+      L.back().o_oD = oD;
+      plan_reduced_uniform(B, L, batch, K, level, oU, oD, oP, kn);
+      add_launch(L, ci, src, nsd::PH_SUBST, dim3((unsigned)K, (unsigned)batch), level, a);
+      L.back().fn = nsk::tables().chunk[C == 4][1];
+      set_common(L.back());
+      L.back().o_psi_if = oP;
       return;
     }
     int ci = multi_cfg(n, batch, kn, level, src);
@@ -842,7 +879,10 @@ cn_status build_plan(const cn_layout* L, int src, bool adjoint_ws, Plan& P,
                          !L->shared_coefficients;
     const int M = kn.rpt > 0 ? kn.rpt : (kn.partition >= 512 ? 8 : 4);
     const bool rows_ok = find_cfg(kn.partition, M) >= 0 || find_cfg(kn.partition, 4) >= 0 ||
-                         find_cfg(kn.partition, 8) >= 0 || find_cfg(kn.partition, 2) >= 0;
+                         find_cfg(kn.partition, 8) >= 0 || find_cfg(kn.partition, 2) >= 0 ||
+                         find_cfg(kn.partition, 1) >= 0 ||
+                         (chunks_of(kn.partition) > 0 && src == nsd::SRC_EXPL && !L->offsets &&
+                          !L->shared_coefficients);
     const bool cols_ok = col_cfg(kn.partition, kn.rpt) >= 0;
     if (columns ? !cols_ok : !rows_ok) return CN_ERR_UNSUPPORTED;
   }

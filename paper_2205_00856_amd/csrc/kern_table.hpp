@@ -14,8 +14,10 @@ struct Cfg {
   constexpr int64_t T() const { return 64LL * W * M; }
 };
 // Row tiles (k_tile, k_system): (rows per lane, wavefronts per workgroup); T = 64 W M rows.
-constexpr Cfg kCfgs[] = {{2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 1},
-                         {8, 2}, {8, 4}, {8, 8}, {2, 2}, {2, 4}, {16, 4}, {16, 2}};
+// {1, 1} (a 64-row partition, every lane's block one joint row) is built for the explicit
+// sources and the reduced systems only.
+constexpr Cfg kCfgs[] = {{2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 1}, {8, 2},
+                         {8, 4}, {8, 8}, {2, 2}, {2, 4}, {16, 4}, {16, 2}, {1, 1}};
 constexpr int kNumCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
 // Column tiles of interleaved batches (k_cols): T = W M rows of 64 neighbouring systems.
 constexpr Cfg kColCfgs[] = {{4, 8}, {8, 4}, {8, 8}, {4, 16}, {16, 4}, {8, 16}};
@@ -47,6 +49,9 @@ struct Tables {
   const void* mrhs[kNumCfg][3];  // one matrix, several right-hand sides (explicit source)
   const void* aux[kNumAux];
   const void* res[kNumResCfg][2];  // resident propagation of one system: [SRC_CN, SRC_CNW]
+  // explicit solve with first-level partitions of C = 2 or 4 chunks of 4096 rows (8192 and
+  // 16384 rows, k_tile_chunk): [C == 4][0: PH_REDUCE, 1: PH_SUBST]
+  const void* chunk[2][2];
 };
 
 // The one table of the library (cntri.hip), filled once by the registration functions below.

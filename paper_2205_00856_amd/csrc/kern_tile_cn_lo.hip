@@ -8,10 +8,12 @@ template <int I>
 void reg_one(Tables& t) {
   constexpr int M = kCfgs[I].M, W = kCfgs[I].W;
   constexpr int S = nsd::SRC_CN;
-  t.tile[I][S][nsd::PH_SINGLE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_SINGLE>;
-  t.tile[I][S][nsd::PH_REDUCE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_REDUCE>;
-  t.tile[I][S][nsd::PH_SUBST] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_SUBST>;
-  t.tile[I][S][nsd::PH_FUSE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_FUSE>;
+  if constexpr (M >= 2) {  // the fused pass reduces in the RD form, which needs interior rows
+    t.tile[I][S][nsd::PH_SINGLE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_SINGLE>;
+    t.tile[I][S][nsd::PH_REDUCE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_REDUCE>;
+    t.tile[I][S][nsd::PH_SUBST] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_SUBST>;
+    t.tile[I][S][nsd::PH_FUSE] = (const void*)&nsd::k_tile<M, W, S, nsd::PH_FUSE>;
+  }
 }
 template <int... I>
 void reg_range(Tables& t, std::integer_sequence<int, I...>) {

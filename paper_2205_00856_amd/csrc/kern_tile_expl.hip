@@ -1,4 +1,5 @@
-// Row-tile kernels (k_tile) of the solve of explicit a, b, c, d arrays: every tile configuration.
+// Row-tile kernels (k_tile) of the solve of explicit a, b, c, d arrays: every tile configuration,
+// and the chunked first-level partitions of 8192 and 16384 rows (k_tile_chunk).
 #include "kern_table.hpp"
 #include "nshaped_kernels.hpp"
 
@@ -18,6 +19,12 @@ void reg_range(Tables& t, std::integer_sequence<int, I...>) {
 }
 }  // namespace
 
-void reg_tile_expl(Tables& t) { reg_range(t, std::make_integer_sequence<int, kNumCfg - 0>{}); }
+void reg_tile_expl(Tables& t) {
+  reg_range(t, std::make_integer_sequence<int, kNumCfg - 0>{});
+  t.chunk[0][0] = (const void*)&nsd::k_tile_chunk<2, nsd::PH_REDUCE>;
+  t.chunk[0][1] = (const void*)&nsd::k_tile_chunk<2, nsd::PH_SUBST>;
+  t.chunk[1][0] = (const void*)&nsd::k_tile_chunk<4, nsd::PH_REDUCE>;
+  t.chunk[1][1] = (const void*)&nsd::k_tile_chunk<4, nsd::PH_SUBST>;
+}
 
 }  // namespace nsk

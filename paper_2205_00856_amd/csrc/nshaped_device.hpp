@@ -383,8 +383,9 @@ __device__ __forceinline__ void tree_down(cd& pJ, cd& pM, const Node* nodes, int
 // of bank conflicts.
 template <int M>
 struct Stage {
-  static constexpr int QN = 64 * M + 2;       // staged rows: w0-1 .. w0+64M
-  static constexpr int QS = QN + QN / M + 2;  // padded length
+  static constexpr int QN = 64 * M + 2;  // staged rows: w0-1 .. w0+64M
+  // padded length; at least 192 complex values, the 64 tree nodes the buffer holds in between
+  static constexpr int QS = (QN + QN / M + 2) < 192 ? 192 : (QN + QN / M + 2);
   __device__ static __forceinline__ int addr(int q) { return q + q / M; }
 };
 

@@ -977,11 +977,101 @@ __global__ __launch_bounds__(64 * W, (tile_min_waves<M, PH, SRC>())) void k_tile
   }
 }
 
+// ------------------------------------------------------- chunked first-level partitions
+// First-level partitions larger than one workgroup's tile (8192 and 16384 rows: C = 2 or 4
+// chunks of T = 4096 rows, 8 rows per lane, 8 wavefronts) for the solve of explicit a, b, c, d.
+// PH_REDUCE: the workgroup reduces the chunks of its partition one after the other (as k_tile),
+// keeps their slots in LDS and merges them (the block merge of the nesting levels) into the
+// partition's two slots.  PH_SUBST: it reduces the chunks again, solves for psi at the chunk
+// joints from the merged blocks and the partition's own joint values, and substitutes chunk by
+// chunk, which reads each chunk's rows a third time: a partition whose rows do not fit one
+// workgroup's registers costs one more pass over the matrix.
+template <int C>
+struct ChunkSmem {
+  TileSmem<8, 8> t;
+  cd cU[3 * C], cD[3 * C];  // the chunks' slots
+  cd cpsi[C + 1];           // psi at the chunk joints and at the partition's end
+  Node nodes[C];            // chunk joint c eliminated in the merge of chunks 0 .. c
+};
+
+template <int C, int PH>
+__global__ __launch_bounds__(512) void k_tile_chunk(KArgs A) {
+  constexpr int M = 8, W = 8;
+  constexpr int64_t T = 64 * W * M;
+  static_assert(PH == PH_REDUCE || PH == PH_SUBST, "two-pass partitions");
+  __shared__ ChunkSmem<C> sm;
+  const Geo P = geometry<PH>(A);  // the partition: tile = its index in the system, gt its slots
+  KArgs B = A;
+  B.oU = sm.cU;
+  B.oD = sm.cD;
+  // the partition's rows as a system of their own from the partition's first row (rows past its
+  // end, up to the end of the system, are read as the chunks' neighbours)
+  Geo G = P;
+  const int64_t r0 = P.tile * C * T;
+  G.base = P.base + r0 * P.es;
+  G.cbase = P.cbase + r0 * P.es;
+  G.n = P.n - r0;
+  G.ntile = C;
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    G.tile = c;
+    G.gt = c;
+    tile_run<M, W, SRC_EXPL, PH_REDUCE>(B, G, sm.t);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    auto blk = [&](int c) {
+      Blk b;
+      b.UA = sm.cU[3 * c];
+      b.UC = sm.cU[3 * c + 1];
+      b.UD = sm.cU[3 * c + 2];
+      b.DB = sm.cD[3 * c];
+      b.DA = sm.cD[3 * c + 1];
+      b.DD = sm.cD[3 * c + 2];
+      return b;
+    };
+    Blk b = blk(0);
+    for (int c = 1; c < C; ++c) merge_into(b, blk(c), sm.nodes[c]);
+    if constexpr (PH == PH_REDUCE) {
+      A.oU[3 * P.gt] = b.UA;
+      A.oU[3 * P.gt + 1] = b.UC;
+      A.oU[3 * P.gt + 2] = b.UD;
+      A.oD[3 * P.gt] = b.DB;
+      A.oD[3 * P.gt + 1] = b.DA;
+      A.oD[3 * P.gt + 2] = b.DD;
+    } else {
+      const cd pJ = A.psi_if[P.gt];
+      const cd pM = P.tile + 1 < P.ntile ? A.psi_if[P.gt + 1] : czero();
+      sm.cpsi[0] = pJ;
+      sm.cpsi[C] = pM;
+      cd nx = pM;
+      for (int c = C - 1; c >= 1; --c) {
+        const Node t = sm.nodes[c];
+        nx = cfms(t.C, nx, cfms(t.B, pJ, t.dl));
+        sm.cpsi[c] = nx;
+      }
+    }
+  }
+  if constexpr (PH == PH_SUBST) {
+    __syncthreads();
+    B.psi_if = sm.cpsi;
+    G.ntile = C + 1;  // every chunk reads psi at its end joint from cpsi
+#pragma unroll 1
+    for (int c = 0; c < C; ++c) {
+      G.tile = c;
+      G.gt = c;
+      tile_run<M, W, SRC_EXPL, PH_SUBST>(B, G, sm.t);
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------ resident propagation
 // Every step of a Crank-Nicolson propagation of one system in one launch.  Workgroup t owns
 // tile t for the whole sequence and keeps its rows in registers: the right-hand side of the RD
-// rows (Table 1 with substitution along them), and per row the two terms of the diagonal, so
-// that after the first loads a step neither reads nor writes the state in memory.  Per step the
+// rows (Table 1 with substitution along them), and per row the two terms of the diagonal's
+// imaginary part (with an absorbing potential also its real part, 1 + tau W), so that after the
+// first loads a step neither reads nor writes the state in memory.  Per step the
 // tile reduces its rows, nested inside the tile as in k_tile, stores its two slots and edge rows
 // device-coherently and raises its flag; every workgroup waits (bounded poll) until all K flags
 // show the step, then solves the reduced system on the K tile joints itself (a whole-system

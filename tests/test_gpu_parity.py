@@ -55,9 +55,12 @@ def test_solve_single_system(gpu, oracle_mod, n, kind):
     assert cn.get_status() == 0
 
 
-@pytest.mark.parametrize("T,M", [(128, 2), (256, 4), (512, 4), (512, 8), (1024, 4), (1024, 8),
-                                 (2048, 4), (2048, 8), (4096, 8)])
+@pytest.mark.parametrize("T,M", [(64, 0), (128, 2), (256, 4), (512, 4), (512, 8), (1024, 4),
+                                 (1024, 8), (2048, 4), (2048, 8), (4096, 8), (8192, 0),
+                                 (16384, 0)])
 def test_solve_partition_sweep(gpu, oracle_mod, T, M):
+    """Every first-level partition of the sweep, 64 (one row per lane) to 16384 rows (chunked
+    partitions of 4096-row tiles), on a ragged 300_007-row system."""
     torch, cn = gpu
     n = 300_007
     log("partition", T, M)
@@ -65,8 +68,26 @@ def test_solve_partition_sweep(gpu, oracle_mod, T, M):
     ref = oracle_mod.thomas(a, b, c, d)
     ta, tb, tc, td = to_dev(torch, a, b, c, d)
     L = cn.Layout.contiguous(n, 1, partition=T, rows_per_thread=M)
+    log("plan", cn.describe_plan(L))
     x = cn.solve(ta, tb, tc, td, layout=L)
     assert rel(x.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("T", [8192, 16384])
+def test_chunked_partitions_batch_and_short(gpu, oracle_mod, T):
+    """Chunked partitions on a strided uniform batch whose systems end inside a partition's
+    first chunk (5000 rows) or span several partitions (3 T + 11 rows), and in place."""
+    torch, cn = gpu
+    for n, batch in ((5000, 3), (3 * T + 11, 2)):
+        a, b, c, d = workloads.random_system(n * batch, 13 + n % 7, "dd")
+        ta, tb, tc, td = to_dev(torch, a, b, c, d)
+        L = cn.Layout.contiguous(n, batch, partition=T)
+        assert "chunks" in cn.describe_plan(L)
+        cn.solve(ta, tb, tc, td, out=td, layout=L)
+        got = td.cpu().numpy()
+        for s_ in range(batch):
+            sl = slice(s_ * n, (s_ + 1) * n)
+            assert rel(got[sl], oracle_mod.thomas(a[sl], b[sl], c[sl], d[sl])) <= TOL
 
 
 def test_solve_in_place(gpu, oracle_mod):
