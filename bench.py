@@ -426,10 +426,10 @@ def nesting_sweep(torch, np, cn, a, b, c, d, x, N):
     optimal ratio per level (beta n / alpha)^(1/(L+1)) = n^(1/(L+1)) / delta^(2/(L+1)) are set
     beside the measured optimum and the paper's n^(1/(L+1))."""
     pts = []
-    grid = [(1, 1024), (1, 2048), (1, 4096), (2, 128), (2, 256), (2, 512), (2, 1024),
-            (3, 128), (3, 256), (3, 512)]
+    grid = [(1, 1024), (1, 2048), (1, 4096), (1, 8192), (1, 16384), (2, 128), (2, 256),
+            (2, 512), (2, 1024), (3, 128), (3, 256), (3, 512)]
     for Lv, T in grid:
-        M = 2 if T == 128 else 4
+        M = 2 if T == 128 else (0 if T > 4096 else 4)
         L = cn.Layout.contiguous(N, 1, partition=T, rows_per_thread=M, levels=Lv)
         cn.solve(a, b, c, d, out=x, layout=L)
         reps = 3 if N // T ** Lv <= (1 << 16) else 1
