@@ -1120,6 +1120,28 @@ def differentiated(torch, np, workloads, dev):
 
     bwd_rec()
     trec = float(np.median(timed_events(torch, bwd_rec, 3))) * 1e-3
+    # the forward as one resident launch (cn_propagate_resident, checkpoints from registers)
+    with torch.no_grad():
+        ag.cn_propagate(p0, tV.detach(), tE.detach(), dx, dt, xgrid=tx, K=K, resident=True)
+    tfr = []
+    for _ in range(3):
+        tV.grad = None
+        tE.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out_r = ag.cn_propagate(p0, tV, tE, dx, dt, xgrid=tx, K=K, resident=True)
+        torch.cuda.synchronize()
+        tfr.append(time.perf_counter() - t0)
+    loss_of(out_r).backward()
+    resident = {
+        "forward_ms": float(np.median(tfr)) * 1e3,
+        "forward_us_per_step": float(np.median(tfr)) * 1e6 / w["steps"],
+        "adjoint_over_forward": bwd_s / float(np.median(tfr)),
+        "rel_l2_psi_T_vs_chained": float(torch.linalg.vector_norm(out_r.detach() - out.detach())
+                                         / torch.linalg.vector_norm(out.detach())),
+        "rel_l2_dV_vs_chained": float(np.linalg.norm(tV.grad.detach().cpu().numpy() - gV)
+                                      / np.linalg.norm(gV)),
+    }
     reconstruct = {
         "backward_ms": trec * 1e3,
         "adjoint_over_forward": trec / fwd_s,
@@ -1163,6 +1185,7 @@ def differentiated(torch, np, workloads, dev):
         "plan": cn.describe_plan(Lw, True),
         "autotune_sequence": tune_rep,
         "reverse_reconstruction": reconstruct,
+        "forward_resident": resident,
     }
 
 

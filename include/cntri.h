@@ -248,6 +248,9 @@ cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_ope
  *      launch without a field can be captured after cn_reserve of the layout (or one call
  *      outside capture), which sizes the handle's buffer for it.
  *   psi: DEVICE, n complex values, updated in place.
+ *   ckpt: DEVICE or null; as in cn_propagate, the state before step k is written to
+ *      ckpt + (k / K) * n for every k divisible by K (K >= 1): the first by a copy on the
+ *      stream, the others from the kernel's registers.
  * CN_ERR_UNSUPPORTED also when the system needs more tiles than fit the GPU at once or than the
  * reduced solve of one workgroup takes (128 W joints: up to 2^20 rows), or when CN_RESIDENT=0
  * is set; then cn_propagate is the call.  The workgroups wait on each other: a launch that runs
@@ -256,7 +259,7 @@ cn_status cn_propagate(cn_handle_t handle, const cn_layout* layout, const cn_ope
  * left unspecified and cn_get_status returns CN_ERR_WAIT_TIMEOUT.  Enqueued on stream. */
 cn_status cn_propagate_resident(cn_handle_t handle, const cn_layout* layout,
                                 const cn_operator* op, int64_t nsteps, const double* E,
-                                void* psi, cn_stream_t stream);
+                                void* psi, void* ckpt, int64_t K, cn_stream_t stream);
 
 /* One step of the adjoint recursion of cn_propagate (uniform batch of one system).
  * With psi_np1 = T_n^{-1} B_n psi_n, B_n = 1 - i tau H_n, and g_np1 the gradient at psi_np1:

@@ -96,7 +96,7 @@ def lib():
         "cn_rhs": ([H, LP, OP, d, P, P, P], ctypes.c_int),
         "cn_step": ([H, LP, OP, d, P, P, P], ctypes.c_int),
         "cn_propagate": ([H, LP, OP, i64, P, P, P, i64, P], ctypes.c_int),
-        "cn_propagate_resident": ([H, LP, OP, i64, P, P, P], ctypes.c_int),
+        "cn_propagate_resident": ([H, LP, OP, i64, P, P, P, i64, P], ctypes.c_int),
         "cn_step_adjoint": ([H, LP, OP, d, P, P, P, P, P, P, P], ctypes.c_int),
         "cn_get_status": ([H, P], ctypes.c_int),
         "cn_version": ([], ctypes.c_char_p),

@@ -322,11 +322,12 @@ def propagate(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0, dx_per_sy
 
 
 def propagate_resident(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0,
-                       layout: Optional[Layout] = None, W=None):
+                       layout: Optional[Layout] = None, W=None, ckpt=None, K=1):
     """nsteps CN steps of one system in place on psi in ONE launch (cn_propagate_resident).
     Raises CnError(CN_ERR_UNSUPPORTED) for layouts or operators it does not take (then
     propagate is the call); get_status raises CnError(CN_ERR_WAIT_TIMEOUT) after a launch whose
-    workgroups could not all run at once.  W: absorbing potential (the potential is V - iW)."""
+    workgroups could not all run at once.  W: absorbing potential (the potential is V - iW);
+    ckpt, K: checkpoints as in propagate."""
     L = _layout_for(psi, layout)
     _need(psi, torch.complex128, "psi", L.span())
     _check_op(L, V, xgrid, None, W)
@@ -335,12 +336,15 @@ def propagate_resident(psi, V, dx, dt, nsteps, E=None, xgrid=None, v_scale=1.0,
         Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
         if Earr.shape[0] < nsteps:
             raise ValueError("E needs one value per step")
+    if ckpt is not None:
+        _need(ckpt, torch.complex128, "ckpt", ((nsteps + K - 1) // K) * L.span())
     op = _operator(V, dx, dt, xgrid, v_scale, None, W)
     h = handle(psi.device.index)
     Lc = L.c()
     Ep = None if Earr is None else Earr.ctypes.data_as(ctypes.c_void_p)
     check(_lib.lib().cn_propagate_resident(h.ptr, ctypes.byref(Lc), ctypes.byref(op),
-                                           int(nsteps), Ep, _ptr(psi), _stream(psi)),
+                                           int(nsteps), Ep, _ptr(psi), _ptr(ckpt), int(K),
+                                           _stream(psi)),
           "cn_propagate_resident")
     return psi
 

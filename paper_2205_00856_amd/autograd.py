@@ -56,7 +56,7 @@ class CNPropagate(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, psi0, V, E, dx: float, dt: float, xgrid, K: int, v_scale: float = 1.0,
-                W=None, reconstruct: bool = False):
+                W=None, reconstruct: bool = False, resident: bool = False):
         nsteps = int(E.shape[0]) if E is not None else 0
         if nsteps < 1:
             raise ValueError("CNPropagate needs at least one step (E has one value per step)")
@@ -69,8 +69,13 @@ class CNPropagate(torch.autograd.Function):
         ckpt = None if reconstruct else torch.empty(nseg * psi0.shape[0], dtype=psi0.dtype,
                                                     device=psi0.device)
         psi = psi0.detach().clone()
-        api.propagate(psi, V.detach(), dx, dt, nsteps, E=Eh, xgrid=xgrid, v_scale=v_scale,
-                      ckpt=ckpt, K=K, layout=L, W=W)
+        if resident:
+            # all steps in one launch (the GPU to itself; layouts it does not take raise)
+            api.propagate_resident(psi, V.detach(), dx, dt, nsteps, E=Eh, xgrid=xgrid,
+                                   v_scale=v_scale, layout=L, W=W, ckpt=ckpt, K=K)
+        else:
+            api.propagate(psi, V.detach(), dx, dt, nsteps, E=Eh, xgrid=xgrid, v_scale=v_scale,
+                          ckpt=ckpt, K=K, layout=L, W=W)
         ctx.W = W
         ctx.reconstruct = reconstruct
         # the checkpoints, or (reconstruct) the final state the backward rebuilds from
@@ -96,9 +101,11 @@ class CNPropagate(torch.autograd.Function):
             api.propagate_adjoint(ckpt, g, V.detach(), dx, dt, nsteps, K, E=Eh, xgrid=xgrid,
                                   v_scale=v_scale, dV=dV, dE=dE, W=ctx.W)
         gE = dE.to(device=Edev, dtype=Edt) if has_x else None
-        return g, dV, gE, None, None, None, None, None, None, None
+        return g, dV, gE, None, None, None, None, None, None, None, None
 
 
 def cn_propagate(psi0, V, E, dx, dt, xgrid=None, K=50, v_scale=1.0, W=None,
-                 reconstruct: bool = False):
-    return CNPropagate.apply(psi0, V, E, dx, dt, xgrid, K, v_scale, W, reconstruct)
+                 reconstruct: bool = False, resident: bool = False):
+    """resident: the forward runs as one resident launch (cn_propagate_resident) instead of the
+    chained passes; the reverse mode is the same."""
+    return CNPropagate.apply(psi0, V, E, dx, dt, xgrid, K, v_scale, W, reconstruct, resident)

@@ -1861,8 +1861,10 @@ cn_status reserve_resident(cn_handle_t h, const cn_layout* L) {
 }  // namespace
 
 cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_operator* op,
-                                int64_t nsteps, const double* E, void* psi, cn_stream_t stream) {
+                                int64_t nsteps, const double* E, void* psi, void* ckpt,
+                                int64_t K_ckpt, cn_stream_t stream) {
   if (!h || !psi || nsteps < 0 || nsteps > INT_MAX - 2) return CN_ERR_INVALID_ARG;
+  if (ckpt && (K_ckpt < 1 || K_ckpt > INT_MAX)) return CN_ERR_INVALID_ARG;
   cn_status st = check_op(op);
   if (st != CN_OK) return st;
   int64_t rows = 0, span = 0;
@@ -1887,6 +1889,8 @@ cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_oper
   }
   char* w = (char*)h->res;
   if (E) HIP_TRY(hipMemcpyAsync(w + o_E, E, nsteps * sizeof(double), hipMemcpyHostToDevice, s));
+  if (ckpt)  // the state before step 0
+    HIP_TRY(hipMemcpyAsync(ckpt, psi, L->n * sizeof(cd), hipMemcpyDeviceToDevice, s));
   KArgs a{};
   a.n = L->n;
   a.ntiles = K;
@@ -1912,6 +1916,8 @@ cn_status cn_propagate_resident(cn_handle_t h, const cn_layout* L, const cn_oper
   r.sync = h->status + 96;
   r.spin = resident_spin();
   r.bufstep = K;
+  r.ckpt = (cd*)ckpt;
+  r.K = ckpt ? (int)K_ckpt : 1;
   void* params[] = {&a, &r};
   if (hipLaunchKernel(nsk::tables().res[ci][wa], dim3((unsigned)K),
                       dim3(64 * nsk::kResCfgs[ci].W),

@@ -1088,6 +1088,8 @@ struct ResArgs {
   int* sync;        // [-, -, abort, workgroups out]; zero between launches
   int spin;         // polls before a wait gives up (sets abort and status bit 4)
   int64_t bufstep;  // elements between the two parity buffers of oU, oD (3 K) and halo (2 K)
+  cd* ckpt;         // states before the steps k = K, 2K, ... at ckpt + (k / K) n, or null (the
+  int K;            // state before step 0 is the caller's copy)
 };
 
 template <int M, int W>
@@ -1213,6 +1215,11 @@ __device__ __forceinline__ void resident_run(const KArgs& A, const ResArgs& R, c
       check_rows<M, IN>(A, G, J, lane, xo);
       store_tile<M, W, SRC, IN>(A, G, sm.t, buf, w0, lane, wave, xo);
       return;
+    }
+    if (R.ckpt && (k + 1) % R.K == 0) {  // the state before step k + 1
+      KArgs Ac = A;
+      Ac.x = R.ckpt + (int64_t)((k + 1) / R.K) * A.n;
+      store_tile<M, W, SRC, IN>(Ac, G, sm.t, buf, w0, lane, wave, xo);
     }
     const double En = R.E ? R.E[k + 1] : 0.0;
     double ayn[M];

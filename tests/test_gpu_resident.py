@@ -5,7 +5,8 @@ at each step) against the CPU oracle stepping one step at a time, and against cn
 Tolerance: relative L2 <= 1e-11 (FP64 on both sides; rounding only).  Cases: the plain 1D
 workload's 200 steps, ragged sizes from one row to 2^20 rows with a field (every tile
 configuration: 512, 1024 and 2048 rows), the absorbing workload and absorbing ramps with a
-field (the potential V - iW), a captured graph replayed against the eager result,
+field (the potential V - iW), checkpoints against the oracle's states and the autograd forward
+in one launch, a captured graph replayed against the eager result,
 the layouts and operators it refuses, and a wait that gives up (forced from the host with a
 poll bound of zero), after which the next launch is correct again.
 """
@@ -119,6 +120,59 @@ def test_resident_absorbing_with_field(gpu, oracle_mod, n):
     assert cn.get_status() == 0
 
 
+@pytest.mark.parametrize("n,steps,K", [(65_536, 30, 7), (300_007, 12, 4), (1 << 20, 9, 3)])
+def test_resident_checkpoints(gpu, oracle_mod, n, steps, K):
+    """Checkpoints every K steps with a field: each against the oracle's state before that
+    step, and equal to those of cn_propagate (the chained passes) to rounding."""
+    torch, cn = gpu
+    dx, dt = 0.05, 0.01
+    log("resident checkpoints", n, steps, K)
+    inp = workloads.random_cn(n, 7 + n % 31, dx, dt)
+    xg = workloads.grid_1d(n, dx)
+    E = np.random.default_rng(n % 101).normal(0.0, 0.05, steps)
+    nck = (steps + K - 1) // K
+    tV, txg = to_dev(torch, inp["V"], xg)
+    a, b = to_dev(torch, inp["psi"], inp["psi"])
+    ca = torch.empty(nck * n, dtype=torch.complex128, device="cuda")
+    cb = torch.empty_like(ca)
+    cn.propagate_resident(a, tV, dx, dt, steps, E=E, xgrid=txg, ckpt=ca, K=K)
+    cn.propagate(b, tV, dx, dt, steps, E=E, xgrid=txg, ckpt=cb, K=K)
+    ck = ca.cpu().numpy().reshape(nck, n)
+    ref = inp["psi"]
+    for k in range(steps):
+        if k % K == 0:
+            assert rel(ck[k // K], ref) <= TOL, k
+        ref = oracle_mod.cn_step(ref, inp["V"], dx, dt, xg, E[k])
+    assert rel(a.cpu().numpy(), ref) <= TOL
+    assert rel(ca.cpu().numpy(), cb.cpu().numpy()) <= 1e-12
+    assert cn.get_status() == 0
+
+
+def test_autograd_resident_forward(gpu):
+    """autograd.cn_propagate(resident=True): the forward in one launch with its checkpoints
+    gives the state and the gradients of the chained form."""
+    torch, cn = gpu
+    from paper_2205_00856_amd import autograd as ag
+
+    n, steps, dx, dt = 70_001, 25, 0.05, 0.01
+    g = np.random.default_rng(18)
+    x = torch.tensor(workloads.grid_1d(n, dx), device="cuda")
+    p0 = torch.tensor(workloads.complex_normal(g, n), device="cuda")
+    phi = torch.tensor(workloads.complex_normal(g, n), device="cuda")
+    V0 = g.uniform(-1.0, 0.0, n)
+    E0 = g.normal(0.0, 0.05, steps)
+    res = []
+    for resident in (False, True):
+        V = torch.tensor(V0, device="cuda", requires_grad=True)
+        E = torch.tensor(E0, device="cuda", requires_grad=True)
+        out = ag.cn_propagate(p0, V, E, dx, dt, xgrid=x, K=6, resident=resident)
+        loss = torch.abs((torch.conj(phi) * out).sum() * dx) ** 2
+        loss.backward()
+        res.append((out.detach().cpu().numpy(), V.grad.cpu().numpy(), E.grad.cpu().numpy()))
+    for a, b in zip(res[1], res[0]):
+        assert rel(a, b) <= 1e-11
+
+
 def test_resident_matches_chained_propagation(gpu):
     """The same 60 steps through cn_propagate (fused passes) and in one launch."""
     torch, cn = gpu
@@ -190,7 +244,7 @@ def test_resident_capture_after_reserve(gpu):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=side):
             st = lib.cn_propagate_resident(h, ctypes.byref(Lc), ctypes.byref(op), steps, None,
-                                           ctypes.c_void_p(psi.data_ptr()),
+                                           ctypes.c_void_p(psi.data_ptr()), None, 1,
                                            ctypes.c_void_p(side.cuda_stream))
         assert st == _lib.CN_OK
         for _ in range(2):
@@ -220,7 +274,7 @@ def test_resident_refusals(gpu):
     def call(L, op, steps=3, E=None):
         Lc = L.c()
         return lib.cn_propagate_resident(h, ctypes.byref(Lc), ctypes.byref(op), steps, E,
-                                         ctypes.c_void_p(tpsi.data_ptr()), s)
+                                         ctypes.c_void_p(tpsi.data_ptr()), None, 1, s)
 
     op = _operator(tV, dx, dt)
     U = _lib.CN_ERR_UNSUPPORTED
