@@ -380,7 +380,8 @@ cn_status cn_profile_report(cn_handle_t handle, char* buf, int64_t buflen);
  * non-finite result since the last call (and clears the flags), else CN_OK. */
 cn_status cn_get_status(cn_handle_t handle, cn_stream_t stream);
 
-/* Version string and the plan chosen for a layout (for logs and benchmarks).  cn_mode 0: the
+/* Version string and the plan chosen for a layout (for logs and benchmarks; with CN_LOG=1 in
+ * the environment every plan is also described on stderr when it is built).  cn_mode 0: the
  * plan of cn_tridiag_solve; 1: the Crank-Nicolson plan (real potential), whose description ends
  * with how cn_propagate chains its steps: one fused pass per step, and whether the pass's last
  * workgroup also solves the reduced system of the tile joints (one system whose joints fit one

@@ -62,6 +62,15 @@ int col_cfg(int64_t T, int M) {
   return -1;
 }
 
+// CN_LOG=1: every new plan is described on stderr when it is built
+bool log_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("CN_LOG");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
 // column kernels for interleaved batches (CN_COLS=0 turns them off)
 bool cols_enabled() {
   static const bool on = [] {
@@ -1058,6 +1067,10 @@ cn_status get_plan(cn_handle_t h, const cn_layout* L, int src, hipStream_t s, Pl
       P->tables_bytes = tab.size();
     }
     bind_tables(*P, (char*)P->tables);
+    if (log_enabled())
+      fprintf(stderr, "cntri: plan for source %d, layout n=%lld batch=%lld%s: %s\n", src,
+              (long long)L->n, (long long)L->batch, L->offsets ? " (uneven)" : "",
+              P->desc.c_str());
     it = h->plans.emplace(key, std::move(P)).first;
   }
   Plan* P = it->second.get();

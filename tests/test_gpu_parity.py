@@ -90,6 +90,23 @@ def test_chunked_partitions_batch_and_short(gpu, oracle_mod, T):
             assert rel(got[sl], oracle_mod.thomas(a[sl], b[sl], c[sl], d[sl])) <= TOL
 
 
+def test_plan_log_on_stderr(gpu):
+    """CN_LOG=1: a new plan is described on stderr when it is built (a child process, since the
+    library reads the variable once)."""
+    import os
+    import subprocess
+    import sys
+
+    code = ("import torch, paper_2205_00856_amd as cn; "
+            "d = torch.ones(5000, dtype=torch.complex128, device='cuda'); "
+            "a = 4 * d; cn.solve(a, d, d, d); torch.cuda.synchronize()")
+    env = dict(os.environ, CN_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=240, cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "cntri: plan for source 0, layout n=5000 batch=1" in r.stderr
+
+
 def test_solve_in_place(gpu, oracle_mod):
     torch, cn = gpu
     n = 70_001
