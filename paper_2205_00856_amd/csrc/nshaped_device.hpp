@@ -376,6 +376,200 @@ __device__ __forceinline__ void tree_down(cd& pJ, cd& pM, const Node* nodes, int
   if constexpr (LEVELS > 0) tree_level_down<1>(pJ, pM, nodes, lane);
 }
 
+// ------------------------------------------- several right-hand sides of one matrix (factored)
+// The multipliers of RD, JD, RU and JU (the r factors of Table 1) and the pivots depend on the
+// matrix alone; only the updates of d involve the right-hand side (Sec. 5.2.4 keeps the r
+// factors for this reason).  The functions below split reduce_block and merge_into into a
+// matrix part, run once per tile, and a right-hand-side part, run for each right-hand side.
+// Together they perform the very operations of the unsplit functions on the same operands in
+// the same order, so each right-hand side gets the same bits as a solve of its own.
+
+// The factors of one lane's block (general complex rows).
+template <int M>
+struct BlkFac {
+  cd ia[M];         // ia[i] (i >= 1): reciprocal of the pivot of row J+i
+  cd b[M];          // b[i] (i >= 2): the RD multiplier of delta_{i-1} in row J+i
+  cd g[M];          // g[i] (1 <= i <= M-2): the RU multiplier gamma_i of delta_{i+1}
+  cd c0, bK;        // the JU multiplier c_J and the JD multiplier b_K
+  cd Bt[M], Ct[M];  // the reduced rows (beta, gamma) that SS applies to psi_J and psi_K
+};
+
+// Matrix part of reduce_block (no IMAG): o receives UA, UC, DB, DA; F the factors.
+template <int M>
+__device__ __forceinline__ void reduce_block_fac(const cd (&A)[M], const cd (&B)[M],
+                                                 const cd (&C)[M], cd bK, BlkFac<M>& F,
+                                                 Blk& o) {
+  F.c0 = C[0];
+  F.bK = bK;
+  if constexpr (M == 1) {
+    o.UA = A[0];
+    o.UC = C[0];
+    o.DB = bK;
+    o.DA = czero();
+  } else {
+    cd Bt[M], Ct[M];
+    {
+      const cd ia = crecip(A[1]);
+      F.ia[1] = ia;
+      Bt[1] = cmul(B[1], ia);
+      Ct[1] = cmul(C[1], ia);
+    }
+#pragma unroll
+    for (int i = 2; i < M; ++i) {
+      const cd a = csub(A[i], cmul(B[i], Ct[i - 1]));
+      const cd b = cneg(cmul(B[i], Bt[i - 1]));
+      const cd ia = crecip(a);
+      F.ia[i] = ia;
+      F.b[i] = B[i];
+      Bt[i] = cmul(b, ia);
+      Ct[i] = cmul(C[i], ia);
+    }
+    o.DB = cneg(cmul(bK, Bt[M - 1]));
+    o.DA = cneg(cmul(bK, Ct[M - 1]));
+#pragma unroll
+    for (int i = M - 2; i >= 1; --i) {
+      const cd g = Ct[i];
+      F.g[i] = g;
+      Bt[i] = cfms(g, Bt[i + 1], Bt[i]);
+      Ct[i] = cneg(cmul(g, Ct[i + 1]));
+    }
+    o.UA = csub(A[0], cmul(C[0], Bt[1]));
+    o.UC = cneg(cmul(C[0], Ct[1]));
+#pragma unroll
+    for (int i = 1; i < M; ++i) {
+      F.Bt[i] = Bt[i];
+      F.Ct[i] = Ct[i];
+    }
+  }
+}
+
+// Right-hand-side part of reduce_block: D becomes the deltas that SS reads; UD, DD the block's
+// right-hand sides at its two joint lines.
+template <int M>
+__device__ __forceinline__ void reduce_block_rhs(const BlkFac<M>& F, cd (&D)[M], cd& UD,
+                                                 cd& DD) {
+  if constexpr (M == 1) {
+    UD = D[0];
+    DD = czero();
+  } else {
+    D[1] = cmul(D[1], F.ia[1]);
+#pragma unroll
+    for (int i = 2; i < M; ++i) {
+      const cd d = csub(D[i], cmul(F.b[i], D[i - 1]));
+      D[i] = cmul(d, F.ia[i]);
+    }
+    DD = cneg(cmul(F.bK, D[M - 1]));
+#pragma unroll
+    for (int i = M - 2; i >= 1; --i) D[i] = cfms(F.g[i], D[i + 1], D[i]);
+    UD = csub(D[0], cmul(F.c0, D[1]));
+  }
+}
+
+// An eliminated joint line K of the nesting, matrix part: its scaled row (B, C) for SS, the
+// reciprocal of its pivot and the JU / JD multipliers that fold its right-hand side into the
+// merged block.
+struct NodeFac {
+  cd B, C, ia, rU, rD;
+};
+
+// Matrix part of merge_into (UA, UC, DB, DA of b and o).
+__device__ __forceinline__ void merge_fac(Blk& b, const Blk& o, NodeFac& t) {
+  const cd ia = crecip(cadd(b.DA, o.UA));
+  t.B = cmul(b.DB, ia);
+  t.C = cmul(o.UC, ia);
+  t.ia = ia;
+  t.rU = b.UC;
+  t.rD = o.DB;
+  b.UA = cfms(t.rU, t.B, b.UA);
+  b.UC = cneg(cmul(t.rU, t.C));
+  b.DB = cneg(cmul(t.rD, t.B));
+  b.DA = cfms(t.rD, t.C, o.DA);
+}
+
+// Right-hand-side part of merge_into: (UD, DD) of [J, K] absorbs (oUD, oDD) of [K, M]; returns
+// the scaled right-hand side dl of row K.
+__device__ __forceinline__ cd merge_rhs(cd& UD, cd& DD, cd oUD, cd oDD, cd ia, cd rU, cd rD) {
+  const cd dl = cmul(cadd(DD, oUD), ia);
+  UD = cfms(rU, dl, UD);
+  DD = cfms(rD, dl, oDD);
+  return dl;
+}
+
+// The nesting levels of tree_up, matrix part: the lane of L keeps the factors of row K in
+// f[lane + m] (the slot tree_up gives its node); the right-hand-side part reads them back in
+// the same lane.
+template <int m>
+__device__ __forceinline__ void tree_level_up_fac(Blk& b, NodeFac* f, int lane) {
+  Blk o;
+  o.UA = xmove<m>(b.UA);
+  o.UC = xmove<m>(b.UC);
+  o.DB = xmove<m>(b.DB);
+  o.DA = xmove<m>(b.DA);
+  NodeFac t;
+  merge_fac(b, o, t);
+  if ((lane & (2 * m - 1)) == 0) f[lane + m] = t;
+}
+
+template <int LEVELS>
+__device__ __forceinline__ void tree_up_fac(Blk& b, NodeFac* f, int lane) {
+  if constexpr (LEVELS > 0) tree_level_up_fac<1>(b, f, lane);
+  if constexpr (LEVELS > 1) tree_level_up_fac<2>(b, f, lane);
+  if constexpr (LEVELS > 2) tree_level_up_fac<4>(b, f, lane);
+  if constexpr (LEVELS > 3) tree_level_up_fac<8>(b, f, lane);
+  if constexpr (LEVELS > 4) tree_level_up_fac<16>(b, f, lane);
+  if constexpr (LEVELS > 5) tree_level_up_fac<32>(b, f, lane);
+}
+
+template <int m>
+__device__ __forceinline__ void tree_level_up_rhs(cd& UD, cd& DD, const NodeFac* __restrict__ f,
+                                                  cd* __restrict__ dl, int lane) {
+  const NodeFac& t = f[(lane + m) & 63];
+  const cd oUD = xmove<m>(UD);
+  const cd oDD = xmove<m>(DD);
+  const cd d = merge_rhs(UD, DD, oUD, oDD, t.ia, t.rU, t.rD);
+  if ((lane & (2 * m - 1)) == 0) dl[lane + m] = d;
+}
+
+// Right-hand-side part of tree_up: the levels run on (UD, DD) alone with the factors of the
+// matrix part; dl receives the scaled right-hand sides of the eliminated rows in the node slots.
+template <int LEVELS>
+__device__ __forceinline__ void tree_up_rhs(cd& UD, cd& DD, const NodeFac* __restrict__ f,
+                                            cd* __restrict__ dl, int lane) {
+  if constexpr (LEVELS > 0) tree_level_up_rhs<1>(UD, DD, f, dl, lane);
+  if constexpr (LEVELS > 1) tree_level_up_rhs<2>(UD, DD, f, dl, lane);
+  if constexpr (LEVELS > 2) tree_level_up_rhs<4>(UD, DD, f, dl, lane);
+  if constexpr (LEVELS > 3) tree_level_up_rhs<8>(UD, DD, f, dl, lane);
+  if constexpr (LEVELS > 4) tree_level_up_rhs<16>(UD, DD, f, dl, lane);
+  if constexpr (LEVELS > 5) tree_level_up_rhs<32>(UD, DD, f, dl, lane);
+}
+
+// tree_level_down with the node split into its matrix part (f) and its right-hand side (dl).
+template <int m>
+__device__ __forceinline__ void tree_level_down_fac(cd& pJ, cd& pM, const NodeFac* f,
+                                                    const cd* dl, int lane) {
+  const int k = (lane + m) & 63;
+  const cd pK = cfms(f[k].C, pM, cfms(f[k].B, pJ, dl[k]));
+  const cd oK = xmove<m>(pK);
+  const cd oM = xmove<m>(pM);
+  const int low = lane & (2 * m - 1);
+  if (low == m) {
+    pJ = oK;
+    pM = oM;
+  }
+  if (low == 0) pM = pK;
+}
+
+template <int LEVELS>
+__device__ __forceinline__ void tree_down_fac(cd& pJ, cd& pM, const NodeFac* f, const cd* dl,
+                                              int lane) {
+  if constexpr (LEVELS > 5) tree_level_down_fac<32>(pJ, pM, f, dl, lane);
+  if constexpr (LEVELS > 4) tree_level_down_fac<16>(pJ, pM, f, dl, lane);
+  if constexpr (LEVELS > 3) tree_level_down_fac<8>(pJ, pM, f, dl, lane);
+  if constexpr (LEVELS > 2) tree_level_down_fac<4>(pJ, pM, f, dl, lane);
+  if constexpr (LEVELS > 1) tree_level_down_fac<2>(pJ, pM, f, dl, lane);
+  if constexpr (LEVELS > 0) tree_level_down_fac<1>(pJ, pM, f, dl, lane);
+}
+
 // ------------------------------------------------------------------ LDS staging per wavefront
 // A wavefront covers rows w0 .. w0+64M-1 plus one halo row on each side.  Global loads and
 // stores are coalesced (lane l touches row w0 + 64k + l); the lane-to-block transposition goes

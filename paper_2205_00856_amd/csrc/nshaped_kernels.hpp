@@ -1271,42 +1271,158 @@ __global__ __launch_bounds__(64 * W) void k_resident(KArgs A, ResArgs R) {
 // ------------------------------------------------------------ several right-hand sides
 // One workgroup = one tile of T = 64*W*M rows of ONE matrix (a, b, c shared by the batch:
 // cshared) and nrhs right-hand sides of it (systems blockIdx.y * nrhs + r).  The matrix rows
-// are loaded and put in lane-block order once; the loop over the right-hand sides loads only
-// d_r and runs the tile's reduction, nesting, top and substitution on it (Sec. 5.2.4: several
-// systems that share a matrix), so the matrix crosses the memory bus once per tile instead of
-// once per right-hand side.
+// are loaded once and factored once: the lane blocks' reduction and every nesting level keep
+// their pivots' reciprocals and multipliers (BlkFac, NodeFac; Sec. 5.2.4 stores the r factors
+// so that most of RD and RU needs no d).  The loop over the right-hand sides then loads only
+// d_r and repeats the updates of d, the top of the tile and the substitution: the matrix
+// crosses the memory bus once per tile, and no right-hand side pays for a division.
+// The current right-hand side's node values (dl) live where the single-right-hand-side kernels
+// keep their nodes: at the head of each wavefront's staging buffer, idle between the
+// transposition of d and the store, and for the levels across the wavefronts in xnode.
+template <int M, int W>
+struct MrhsSmem {
+  TileSmem<M, W> t;              // staging buffers, partial blocks between levels, node values
+  NodeFac wfac[W][64];           // per wavefront: factors of its nesting levels
+  NodeFac xfac[W > 1 ? 64 : 1];  // the levels across the wavefronts (wavefront 0)
+};
+
+// Rows w0 + 64k + lane (k < M) of one right-hand side, as stage_fetch without the halo rows
+// (the substitution needs no neighbours of d).
+template <int M, bool IN>
+__device__ __forceinline__ void rhs_fetch(const cd* g, int64_t es, int64_t w0, int64_t n,
+                                          int lane, cd (&v)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int64_t r = w0 + 64 * k + lane;
+    if constexpr (IN) {
+      v[k] = sel(true, g[r * es], czero());
+    } else {
+      const cd t = g[(r < n ? r : n - 1) * es];
+      v[k] = sel(r < n, t, czero());
+    }
+  }
+}
+
+// Right-hand side r of the workgroup (system s0 + r) on the factored tile: its d is in cur
+// (fetched two right-hand sides earlier), which then receives the d of right-hand side r + 2.
+// Returns false, uniformly across the workgroup, once r is past the workgroup's share.
 template <int M, int W, int PH, bool IN>
-__device__ __forceinline__ void tile_run_mrhs(const KArgs& A, const Geo& G0, TileSmem<M, W>& sm,
-                                              int64_t w0, int64_t J, int lane, int wave) {
+__device__ __forceinline__ bool mrhs_step(const KArgs& A, const Geo& G0, MrhsSmem<M, W>& sm,
+                                          cd* buf, cd* wdl, cd* xdl, const BlkFac<M>& F,
+                                          const Blk& top, int64_t w0, int64_t J, int lane,
+                                          int wave, int64_t s0, int r, cd (&cur)[M]) {
+  constexpr int LW = Log2<W>::v;
   const int64_t n = G0.n;
   const cd one = mk(1.0, 0.0), zero = czero();
-  cd* buf = sm.lds[wave];
-  cd va[M + 2], vb[M + 2], vc[M + 2];
-  {
-    cd ra[M], rb[M], rc[M], ha, hb, hc;
-    stage_fetch<M, IN>(A.a + G0.cbase, G0.es, w0, n, lane, one, ra, ha);
-    stage_fetch<M, IN>(A.b + G0.cbase, G0.es, w0, n, lane, zero, rb, hb);
-    stage_fetch<M, IN>(A.c + G0.cbase, G0.es, w0, n, lane, zero, rc, hc);
-    transpose_in<M>(buf, lane, ra, ha, va);
-    transpose_in<M>(buf, lane, rb, hb, vb);
-    transpose_in<M>(buf, lane, rc, hc, vc);
+  Geo G = G0;
+  G.sys = s0 + r;
+  if (r >= A.nrhs || G.sys >= A.batch) return false;
+  G.base = G.sys * A.bs;
+  G.gt = G.sys * A.ntiles + G.tile;
+  // psi at the tile's two joint lines, loaded before this right-hand side's elimination so
+  // that the top of the tile does not wait for memory
+  cd qJ = zero, qM = zero;
+  if constexpr (PH == PH_SUBST) {
+    qJ = A.psi_if[G.gt];
+    qM = A.psi_if[(G.tile + 1 < G.ntile) ? G.gt + 1 : G.gt];
   }
-  const int64_t s0 = G0.sys * A.nrhs;
-  // the next right-hand side's rows are fetched before this one's elimination runs, so their
-  // load latency hides behind it
-  cd rd[M], hd;
-  if (s0 < A.batch) stage_fetch<M, IN>(A.d + s0 * A.bs, G0.es, w0, n, lane, zero, rd, hd);
-  for (int r = 0; r < A.nrhs; ++r) {
-    Geo G = G0;
-    G.sys = s0 + r;
-    if (G.sys >= A.batch) break;  // uniform across the workgroup
-    G.base = G.sys * A.bs;
-    G.gt = G.sys * A.ntiles + G.tile;
-    cd vd[M + 2];
-    transpose_in<M>(buf, lane, rd, hd, vd);
-    if (r + 1 < A.nrhs && G.sys + 1 < A.batch)
-      stage_fetch<M, IN>(A.d + (G.sys + 1) * A.bs, G.es, w0, n, lane, zero, rd, hd);
-    cd Ar[M], Br[M], Cr[M], Dr[M];
+  cd vd[M + 2];
+  transpose_in<M>(buf, lane, cur, zero, vd);
+  if (r + 2 < A.nrhs && G.sys + 2 < A.batch)
+    rhs_fetch<M, IN>(A.d + (G.sys + 2) * A.bs, G.es, w0, n, lane, cur);
+  cd Dr[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) Dr[j] = csel(row_in<IN>(J + j, n), vd[j + 1], zero);
+  cd UD, DD;
+  reduce_block_rhs<M>(F, Dr, UD, DD);
+  if constexpr (W == 1) {
+    tree_up_rhs<6>(UD, DD, sm.wfac[0], wdl, lane);
+  } else {
+    tree_up_rhs<LW>(UD, DD, sm.wfac[wave], wdl, lane);
+    if ((lane & (W - 1)) == 0) {
+      Blk* q = sm.t.part(wave, lane >> LW);
+      q->UD = UD;
+      q->DD = DD;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const Blk* q = sm.t.part(lane >> (6 - LW), lane & (64 / W - 1));
+      UD = q->UD;
+      DD = q->DD;
+      tree_up_rhs<6>(UD, DD, sm.xfac, xdl, lane);
+    }
+  }
+  cd pJ = zero, pM = zero;
+  if (wave == 0 && lane == 0) {
+    if constexpr (PH == PH_REDUCE) {
+      A.oU[3 * G.gt] = top.UA;
+      A.oU[3 * G.gt + 1] = top.UC;
+      A.oU[3 * G.gt + 2] = UD;
+      A.oD[3 * G.gt] = top.DB;
+      A.oD[3 * G.gt + 1] = top.DA;
+      A.oD[3 * G.gt + 2] = DD;
+    } else if constexpr (PH == PH_SINGLE) {
+      // RS on the two joint lines of the tile (the bottom one lies past the system end)
+      const cd ia0 = crecip(top.UA);
+      const cd rr = cneg(cmul(top.DB, ia0));
+      const cd aT = cfma(rr, top.UC, cadd(one, top.DA));
+      const cd dT = cfma(rr, UD, DD);
+      pM = cmul(dT, crecip(aT));
+      pJ = cmul(cfms(top.UC, pM, UD), ia0);
+    } else {
+      pJ = qJ;
+      pM = csel(G.tile + 1 < G.ntile, qM, zero);
+    }
+  }
+  if constexpr (PH != PH_REDUCE) {
+    if constexpr (W == 1) {
+      tree_down_fac<6>(pJ, pM, sm.wfac[0], wdl, lane);
+    } else {
+      if (wave == 0) {
+        tree_down_fac<6>(pJ, pM, sm.xfac, xdl, lane);
+        cd* q = reinterpret_cast<cd*>(sm.t.part(lane >> (6 - LW), lane & (64 / W - 1)));
+        q[0] = pJ;
+        q[1] = pM;
+      }
+      __syncthreads();
+      const cd* q = reinterpret_cast<const cd*>(sm.t.part(wave, lane >> LW));
+      pJ = q[0];
+      pM = q[1];
+      tree_down_fac<LW>(pJ, pM, sm.wfac[wave], wdl, lane);
+    }
+    cd xo[M];
+    ss_block<M>(F.Bt, F.Ct, Dr, pJ, pM, xo);
+    check_rows<M, IN>(A, G, J, lane, xo);
+    store_tile<M, W, SRC_EXPL, IN>(A, G, sm.t, buf, w0, lane, wave, xo);
+  }
+  __syncthreads();  // the staging buffers and partial blocks are reused by the next one
+  return true;
+}
+
+template <int M, int W, int PH, bool IN>
+__device__ __forceinline__ void tile_run_mrhs(const KArgs& A, const Geo& G0, MrhsSmem<M, W>& sm,
+                                              int64_t w0, int64_t J, int lane, int wave) {
+  constexpr int LW = Log2<W>::v;
+  const int64_t n = G0.n;
+  const cd one = mk(1.0, 0.0), zero = czero();
+  cd* buf = sm.t.lds[wave];
+  cd* wdl = buf;
+  cd* xdl = reinterpret_cast<cd*>(sm.t.xnode);
+  static_assert(sizeof(cd) * 64 <= sizeof(Node) * 64, "node values fit the node space");
+  BlkFac<M> F;
+  Blk top;  // wavefront 0, lane 0: the matrix part of the whole tile's block
+  {
+    cd va[M + 2], vb[M + 2], vc[M + 2];
+    {
+      cd ra[M], rb[M], rc[M], ha, hb, hc;
+      stage_fetch<M, IN>(A.a + G0.cbase, G0.es, w0, n, lane, one, ra, ha);
+      stage_fetch<M, IN>(A.b + G0.cbase, G0.es, w0, n, lane, zero, rb, hb);
+      stage_fetch<M, IN>(A.c + G0.cbase, G0.es, w0, n, lane, zero, rc, hc);
+      transpose_in<M>(buf, lane, ra, ha, va);
+      transpose_in<M>(buf, lane, rb, hb, vb);
+      transpose_in<M>(buf, lane, rc, hc, vc);
+    }
+    cd Ar[M], Br[M], Cr[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const int64_t q = J + j;
@@ -1315,18 +1431,43 @@ __device__ __forceinline__ void tile_run_mrhs(const KArgs& A, const Geo& G0, Til
       Ar[j] = csel(ok, va[j + 1], one);
       Br[j] = csel(pos, vb[j + 1], zero);
       Cr[j] = csel(notlast, vc[j + 1], zero);
-      Dr[j] = csel(ok, vd[j + 1], zero);
     }
     const cd bK = csel(row_in<IN>(J + M, n), vb[M + 1], zero);
-    tile_finish<M, W, SRC_EXPL, PH, IN>(A, G, sm, buf, w0, J, lane, wave, Ar, Br, Cr, Dr, bK,
-                                         zero, zero, nullptr);
-    __syncthreads();  // the staging buffers and nodes are reused by the next right-hand side
+    reduce_block_fac<M>(Ar, Br, Cr, bK, F, top);
+  }
+  if constexpr (W == 1) {
+    tree_up_fac<6>(top, sm.wfac[0], lane);
+  } else {
+    // the same split of the levels as the single right-hand side (tile_core)
+    tree_up_fac<LW>(top, sm.wfac[wave], lane);
+    if ((lane & (W - 1)) == 0) *sm.t.part(wave, lane >> LW) = top;
+    __syncthreads();
+    if (wave == 0) {
+      top = *sm.t.part(lane >> (6 - LW), lane & (64 / W - 1));
+      tree_up_fac<6>(top, sm.xfac, lane);
+    }
+    __syncthreads();  // the partial blocks' space is the right-hand sides' from here on
+  }
+
+  const int64_t s0 = G0.sys * A.nrhs;
+  // d of the next two right-hand sides is in flight while one is eliminated: two register
+  // buffers, each refilled as soon as its rows are in LDS
+  cd rdA[M], rdB[M];
+  if (s0 < A.batch) rhs_fetch<M, IN>(A.d + s0 * A.bs, G0.es, w0, n, lane, rdA);
+  if (A.nrhs > 1 && s0 + 1 < A.batch)
+    rhs_fetch<M, IN>(A.d + (s0 + 1) * A.bs, G0.es, w0, n, lane, rdB);
+  for (int r = 0; r < A.nrhs; r += 2) {
+    if (!mrhs_step<M, W, PH, IN>(A, G0, sm, buf, wdl, xdl, F, top, w0, J, lane, wave, s0, r, rdA))
+      break;
+    if (!mrhs_step<M, W, PH, IN>(A, G0, sm, buf, wdl, xdl, F, top, w0, J, lane, wave, s0, r + 1,
+                                 rdB))
+      break;
   }
 }
 
 template <int M, int W, int PH>
 __global__ __launch_bounds__(64 * W) void k_tile_mrhs(KArgs A) {
-  __shared__ TileSmem<M, W> sm;
+  __shared__ MrhsSmem<M, W> sm;
   const Geo G = geometry<PH>(A);
   constexpr int64_t T = 64 * W * M;
   const int lane = threadIdx.x & 63;
