@@ -39,8 +39,10 @@ def log(*a):
     print(*a, flush=True)
 
 
+# (1 << 20, 5): 1024 tiles, so every workgroup takes all 5 right-hand sides (an odd count of
+# them, through both prefetch buffers); (1_000_003, 3): workgroups of 2, the second one short
 @pytest.mark.parametrize("n,nrhs", [(1, 3), (1000, 7), (4096, 5), (70_001, 6), (300_007, 16),
-                                    (1_000_003, 3), (5000, 33)])
+                                    (1_000_003, 3), (5000, 33), (1 << 20, 5)])
 def test_solve_one_matrix_many_rhs_contiguous(gpu, oracle_mod, n, nrhs):
     torch, cn = gpu
     log("shared solve", n, nrhs)
@@ -50,6 +52,8 @@ def test_solve_one_matrix_many_rhs_contiguous(gpu, oracle_mod, n, nrhs):
     ta, tb, tc, td = to_dev(torch, a, b, c, d)
     L = cn.Layout.contiguous(n, nrhs, shared_coefficients=True)
     assert "rhs/wg=" in cn.describe_plan(L)  # the matrix is loaded once per tile
+    if n == 1 << 20:
+        assert f"rhs/wg={nrhs}" in cn.describe_plan(L)
     xt = cn.solve(ta, tb, tc, td, layout=L)
     x = xt.cpu().numpy()
     for s in range(nrhs):
