@@ -17,6 +17,8 @@ void reg_one(Tables& t) {
 
 void reg_mrhs(Tables& t) {
   reg_one<2, 1>(t);
+  reg_one<2, 2>(t);
+  reg_one<2, 4>(t);
   reg_one<4, 1>(t);
   reg_one<4, 2>(t);
   reg_one<4, 4>(t);

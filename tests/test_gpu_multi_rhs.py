@@ -67,6 +67,30 @@ def test_solve_one_matrix_many_rhs_contiguous(gpu, oracle_mod, n, nrhs):
     assert cn.get_status() == 0
 
 
+@pytest.mark.parametrize("partition,rpt", [(256, 2), (512, 2), (2048, 8)])
+def test_solve_one_matrix_many_rhs_tile_shapes(gpu, oracle_mod, partition, rpt):
+    """The factored tile at other lane-block sizes (2 rows per lane over 2 and 4 wavefronts, 8
+    rows over 4): parity with the oracle and the same bits as the per-system kernels."""
+    torch, cn = gpu
+    n, nrhs = 100_003, 5
+    log("shared solve, tile shape", partition, rpt)
+    a, b, c, _ = workloads.random_system(n, 77, "dd")
+    g = np.random.default_rng(partition + rpt)
+    d = workloads.complex_normal(g, nrhs * n)
+    ta, tb, tc, td = to_dev(torch, a, b, c, d)
+    kw = dict(partition=partition, rows_per_thread=rpt)
+    L = cn.Layout.contiguous(n, nrhs, shared_coefficients=True, **kw)
+    assert "rhs/wg=" in cn.describe_plan(L)
+    xt = cn.solve(ta, tb, tc, td, layout=L)
+    x = xt.cpu().numpy()
+    for s in (0, nrhs - 1):
+        assert rel(x[s * n:(s + 1) * n], oracle_mod.thomas(a, b, c, d[s * n:(s + 1) * n])) <= TOL
+    A, B, C = (t.repeat(nrhs) for t in (ta, tb, tc))
+    xr = cn.solve(A, B, C, td, layout=cn.Layout.contiguous(n, nrhs, **kw))
+    assert torch.equal(xt, xr)
+    assert cn.get_status() == 0
+
+
 def test_solve_one_matrix_many_rhs_interleaved(gpu, oracle_mod):
     """Interleaved right-hand sides (elem_stride = batch): the coefficients are read at system
     0's elements 0, batch, 2 batch, ...; every other element of a, b, c holds NaN."""
